@@ -1,0 +1,157 @@
+/*
+ * he_mi355x.h -- C ABI of the MI355X (gfx950) full-RNS CKKS HE Mul library.
+ *
+ * Method: "HEAAN Demystified" (arXiv 2003.04510).  HE Mul = region 1 tensor
+ * product of two ciphertexts, region 2 key switching with the evaluation key,
+ * then rescale (Fig. 2, Sec. II-B; rescale by division, Sec. II-A), in the
+ * full-RNS form the paper names in Table XI: NTT/iNTT (Algorithms 3-4) plus
+ * mod up / mod down (fast base conversion, the Discussion section).
+ *
+ * Conventions (all functions):
+ *   - N = 2^log_n.  Moduli are indexed 0..L-1 for q_0..q_{L-1} and L..L+K-1
+ *     for the special primes p_0..p_{K-1}.  All primes are = 1 (mod 2N),
+ *     distinct, and below 2^60.
+ *   - A polynomial is uint64 [limbs][N], limb-major; every stored residue is
+ *     canonical, in [0, modulus).
+ *   - A ciphertext at level l (l = number of q-limbs present) is
+ *     uint64 [2][l][N]: poly 0 = b (the paper's bx), poly 1 = a (ax), in NTT
+ *     (evaluation) form, bit-reversed slot order.  Decryption: b - a*s.
+ *   - The evaluation key is uint64 [dnum][2][L+K][N] in NTT form, digit j
+ *     covering q_{j*alpha} .. q_{(j+1)*alpha-1}, alpha = ceil(L/dnum).
+ *   - Pointers named d_* are DEVICE pointers owned by the caller (the
+ *     library never frees them).  Host pointers are read before the call
+ *     returns.  Work is enqueued asynchronously on `stream` (0 = the null
+ *     stream); results are ready once the stream reaches that point.
+ *   - `ws` is a caller-owned device workspace of at least the size returned
+ *     by the matching *_workspace_bytes query; its contents on entry are
+ *     ignored and on exit undefined.
+ *   - Every function returns an he_status; on failure he_last_error()
+ *     returns a thread-local message.  Argument errors are detected before
+ *     any work is enqueued.  Device faults surface as HE_EDEVICE, possibly
+ *     from a later call.
+ */
+#ifndef HE_MI355X_H
+#define HE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum he_status {
+  HE_OK = 0,
+  HE_EINVAL = -1,        /* null pointer, bad size, unsupported parameter */
+  HE_ELEVEL = -2,        /* level out of range or mismatched */
+  HE_ENOMEM = -3,        /* workspace too small or device allocation failed */
+  HE_EDEVICE = -4,       /* a HIP call failed */
+  HE_EUNSUPPORTED = -5   /* parameter combination not implemented */
+} he_status;
+
+typedef struct he_ctx he_ctx;
+typedef void* he_stream; /* a hipStream_t */
+
+/* Primes for the RNS bases (Table III/VI of the paper give the prime-size
+ * ranges; the choice "largest primes below 2^bits that are 1 mod 2N,
+ * scanning downward" is this library's).  Writes `count` primes to `out`
+ * (host), skipping any listed in `exclude` (host, may be NULL if
+ * nexclude = 0).  HE_EINVAL if bits is not in [20, 61] or too few primes
+ * exist. */
+he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uint64_t* exclude,
+                        uint32_t nexclude, uint64_t* out);
+
+/* Create a context: moduli q (host, [L]) and p (host, [K]), dnum key-switch
+ * digits.  Builds twiddle tables (powers of the smallest primitive 2N-th root
+ * in bit-reversed order, with Shoup companions, Algorithms 2-3) and all
+ * base-conversion constants on device `device`.  The context owns those
+ * tables (freed by he_ctx_destroy).  Constraints: 12 <= log_n <= 17,
+ * 1 <= dnum <= L <= 64, 1 <= K <= 32, K special primes whose product exceeds
+ * every digit's product.  */
+he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                        const uint64_t* p, int device, he_ctx** out);
+void he_ctx_destroy(he_ctx* ctx);
+
+/* Sizes in bytes. */
+size_t he_ct_bytes(const he_ctx* ctx, uint32_t level);      /* 2*level*N*8 */
+size_t he_evk_bytes(const he_ctx* ctx);                     /* dnum*2*(L+K)*N*8 */
+size_t he_pk_bytes(const he_ctx* ctx);                      /* 2*L*N*8 */
+size_t he_workspace_bytes(const he_ctx* ctx, uint32_t level); /* for he_mul/he_rescale/keygen/... */
+
+/* Key generation (Sec. II-A: pk from sk; evk encrypts a multiple of sk^2,
+ * Fig. 2).  Random draws are inputs (host): s [N] ternary secret, e_pk [N],
+ * e_evk [dnum][N] small signed errors, a_pk [L][N] and a_evk [dnum][L+K][N]
+ * uniform residues (already NTT form, row i uniform mod modulus i).
+ * Writes d_pk = (a*s + e, a) over q_0..q_{L-1} and, per digit j,
+ * d_evk_j = (a_j*s + e_j + G_j*s^2, a_j) over all L+K moduli, where
+ * G_j = [P]_{q_i} for q_i in digit j and 0 elsewhere (P = prod p_k).
+ * Synchronous with respect to the host arrays (they are copied before
+ * return). */
+he_status he_keygen(he_ctx* ctx, const int64_t* s, const int64_t* e_pk, const uint64_t* a_pk,
+                    const int64_t* e_evk, const uint64_t* a_evk, uint64_t* d_pk, uint64_t* d_evk,
+                    void* ws, size_t ws_bytes, he_stream stream);
+
+/* Public-key encryption at `level` (Sec. II-A): ct = (v*pk0 + e0 + m,
+ * v*pk1 + e1).  m, v, e0, e1: host signed coefficient vectors [N]
+ * (m = the encoded plaintext).  d_ct: [2][level][N]. */
+he_status he_encrypt(he_ctx* ctx, uint32_t level, const int64_t* m, const int64_t* v,
+                     const int64_t* e0, const int64_t* e1, const uint64_t* d_pk, uint64_t* d_ct,
+                     void* ws, size_t ws_bytes, he_stream stream);
+
+/* Decryption to RNS coefficients (Sec. II-A: t = bx - ax*sk): writes
+ * d_m [level][N], coefficient form, limb i modulo q_i.  s: host [N]. */
+he_status he_decrypt(he_ctx* ctx, uint32_t level, const uint64_t* d_ct, const int64_t* s,
+                     uint64_t* d_m, void* ws, size_t ws_bytes, he_stream stream);
+
+/* HE Mul (Fig. 2): tensor product, key switching with evk (INTT, ModUp,
+ * NTT, inner product, INTT, ModDown), then optionally rescale by the last
+ * prime q_{level-1}.  d_ct1, d_ct2: [2][level][N].  d_relin: [2][level][N]
+ * output after key switching (may be NULL).  d_out: [2][level-1][N] output
+ * after rescale (may be NULL; requires level >= 2).  At least one output.
+ * Outputs must not alias inputs.  HE_ELEVEL if level is 0 or > L. */
+he_status he_mul(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint64_t* d_ct2,
+                 const uint64_t* d_evk, uint64_t* d_relin, uint64_t* d_out, void* ws,
+                 size_t ws_bytes, he_stream stream);
+
+/* Rescale (Sec. II-A, division by the last prime, rounded to nearest):
+ * d_in [2][level][N] -> d_out [2][level-1][N].  level >= 2. */
+he_status he_rescale(he_ctx* ctx, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,
+                     size_t ws_bytes, he_stream stream);
+
+/* Negacyclic NTT (Algorithm 3) or its inverse of `nlimbs` limbs in place:
+ * limb r is taken modulo modulus index first_mod + r.  Output order is
+ * bit-reversed (forward) / natural (inverse). */
+he_status he_ntt(he_ctx* ctx, uint64_t* d_data, uint32_t nlimbs, uint32_t first_mod, int inverse,
+                 he_stream stream);
+
+/* Parameters of a context (any pointer may be NULL). */
+he_status he_ctx_info(const he_ctx* ctx, uint32_t* log_n, uint32_t* L, uint32_t* K, uint32_t* dnum,
+                      uint64_t* moduli /* [L+K] or NULL */);
+
+/* Diagnostics: per-kernel timing.  While enabled, every kernel the library
+ * launches (or only those whose kind equals `only`, when non-NULL and
+ * non-empty) is bracketed by two HIP events on its stream, together with the
+ * kernel's algorithmic work: `ops` (butterflies for NTT passes, 64x64-bit
+ * multiply-accumulates for base conversion and the inner product, modular
+ * products for element-wise kernels) and `bytes` (limbs read + written x 8N,
+ * tables excluded).  he_timing_read -- after the streams involved are
+ * synchronized -- aggregates the recorded launches per kernel kind into
+ * `out` (up to `max` entries), sets *n to the number of kinds, and clears
+ * the record. */
+typedef struct he_kernel_stat {
+  char name[48];
+  uint32_t launches;
+  double ms;
+  double ops;
+  double bytes;
+} he_kernel_stat;
+he_status he_timing_enable(he_ctx* ctx, int enable, const char* only);
+he_status he_timing_read(he_ctx* ctx, he_kernel_stat* out, uint32_t max, uint32_t* n);
+
+const char* he_status_str(he_status s);
+const char* he_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,8 @@
+"""MI355X-native full-RNS CKKS (HEAAN) HE Mul.
+
+The computation runs in the HIP library libhe_mi355x.so (C ABI, declared in
+include/he_mi355x.h).  This package only marshals arguments: PyTorch supplies
+device memory and streams.  There is no CPU fallback: if the library is not
+built, importing the binding raises.
+"""
+from .binding import Context, HeError, load_library, workload_primes  # noqa: F401

@@ -1,0 +1,260 @@
+"""ctypes binding of libhe_mi355x.so (argument marshalling only).
+
+Ciphertexts, keys and workspaces are torch tensors on the GPU, dtype int64
+holding the uint64 residues bit for bit.  Every call enqueues work on the
+current torch stream of the context's device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhe_mi355x.so")
+
+u64p = ctypes.POINTER(ctypes.c_uint64)
+i64p = ctypes.POINTER(ctypes.c_int64)
+vp = ctypes.c_void_p
+u32 = ctypes.c_uint32
+
+_lib = None
+
+
+class HeError(RuntimeError):
+    pass
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint32), ("ms", ctypes.c_double),
+                ("ops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+def load_library():
+    """Load the built HIP library; raise if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise HeError("libhe_mi355x.so is not built (run paper_2003_04510_amd/build.py); "
+                      "there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    L.he_gen_primes.argtypes = [u32, u32, u32, u64p, u32, u64p]
+    L.he_ctx_create.argtypes = [u32, u32, u32, u32, u64p, u64p, ctypes.c_int, ctypes.POINTER(vp)]
+    L.he_ctx_destroy.argtypes = [vp]
+    L.he_ctx_destroy.restype = None
+    for f in ("he_ct_bytes", "he_workspace_bytes"):
+        getattr(L, f).argtypes = [vp, u32]
+        getattr(L, f).restype = ctypes.c_size_t
+    for f in ("he_evk_bytes", "he_pk_bytes"):
+        getattr(L, f).argtypes = [vp]
+        getattr(L, f).restype = ctypes.c_size_t
+    L.he_keygen.argtypes = [vp, i64p, i64p, u64p, i64p, u64p, vp, vp, vp, ctypes.c_size_t, vp]
+    L.he_encrypt.argtypes = [vp, u32, i64p, i64p, i64p, i64p, vp, vp, vp, ctypes.c_size_t, vp]
+    L.he_decrypt.argtypes = [vp, u32, vp, i64p, vp, vp, ctypes.c_size_t, vp]
+    L.he_mul.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.he_rescale.argtypes = [vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.he_ntt.argtypes = [vp, vp, u32, u32, ctypes.c_int, vp]
+    L.he_ctx_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32),
+                              ctypes.POINTER(u32), u64p]
+    L.he_timing_enable.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
+    L.he_timing_read.argtypes = [vp, ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
+    L.he_status_str.argtypes = [st]
+    L.he_status_str.restype = ctypes.c_char_p
+    L.he_last_error.restype = ctypes.c_char_p
+    for f in ("he_gen_primes", "he_ctx_create", "he_keygen", "he_encrypt", "he_decrypt", "he_mul",
+              "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read"):
+        getattr(L, f).restype = st
+    _lib = L
+    return L
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        L = load_library()
+        raise HeError("%s: %s (%s)" % (what, L.he_status_str(code).decode(), L.he_last_error().decode()))
+
+
+def _u64arr(xs):
+    a = np.ascontiguousarray(np.array(list(xs), dtype=np.uint64))
+    return a, a.ctypes.data_as(u64p)
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(i64p)
+
+
+def gen_primes(log_n: int, bits: int, count: int, exclude=()) -> list:
+    out = np.zeros(max(count, 1), dtype=np.uint64)
+    ex, exp = _u64arr(list(exclude) or [0])
+    _check(load_library().he_gen_primes(log_n, bits, count, exp, len(exclude), out.ctypes.data_as(u64p)),
+           "he_gen_primes")
+    return [int(x) for x in out[:count]]
+
+
+def workload_primes(w) -> tuple:
+    """q_0..q_{L-1} of the listed sizes then K special primes, all distinct,
+    each the largest prime of its size that is 1 mod 2N and not yet used."""
+    used, q, p = [], [], []
+    for b in w.q_bits:
+        (x,) = gen_primes(w.log_n, b, 1, used)
+        used.append(x)
+        q.append(x)
+    for _ in range(w.K):
+        (x,) = gen_primes(w.log_n, w.p_bits, 1, used)
+        used.append(x)
+        p.append(x)
+    return q, p
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else None
+
+
+class Context:
+    """A device context: moduli, NTT and base-conversion tables on GPU `device`."""
+
+    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0):
+        import torch
+        self.torch = torch
+        L = load_library()
+        self.log_n, self.N = log_n, 1 << log_n
+        self.q, self.p = [int(x) for x in q], [int(x) for x in p]
+        self.L, self.K, self.dnum = len(self.q), len(self.p), dnum
+        self.device = device
+        qa, qp = _u64arr(self.q)
+        pa, pp = _u64arr(self.p)
+        h = vp()
+        _check(L.he_ctx_create(log_n, self.L, self.K, dnum, qp, pp, device, ctypes.byref(h)), "he_ctx_create")
+        self._h = h
+        self._ws = {}
+
+    @classmethod
+    def for_workload(cls, w, device: int = 0):
+        q, p = workload_primes(w)
+        return cls(w.log_n, q, p, w.dnum, device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().he_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------- sizes / memory
+    @property
+    def dev(self):
+        return self.torch.device("cuda", self.device)
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def ct_bytes(self, level):
+        return int(load_library().he_ct_bytes(self._h, level))
+
+    def evk_bytes(self):
+        return int(load_library().he_evk_bytes(self._h))
+
+    def workspace_bytes(self, level):
+        return int(load_library().he_workspace_bytes(self._h, level))
+
+    def empty(self, *shape):
+        return self.torch.empty(shape, dtype=self.torch.int64, device=self.dev)
+
+    def workspace(self, level):
+        """A cached workspace tensor large enough for `level`."""
+        need = self.workspace_bytes(level) // 8
+        ws = self._ws.get("ws")
+        if ws is None or ws.numel() < need:
+            ws = self.empty(need)
+            self._ws["ws"] = ws
+        return ws
+
+    def to_device(self, arr: np.ndarray):
+        a = np.ascontiguousarray(arr, dtype=np.uint64).view(np.int64)
+        return self.torch.from_numpy(a.copy()).to(self.dev)
+
+    @staticmethod
+    def to_host(t) -> np.ndarray:
+        return t.detach().cpu().numpy().view(np.uint64)
+
+    # ---------------------------------------------------------- operations
+    def keygen(self, s, e_pk, e_evk, a_pk, a_evk):
+        """Keys from supplied random draws -> (pk [2][L][N], evk [dnum][2][L+K][N]) on the GPU."""
+        L = load_library()
+        pk = self.empty(2, self.L, self.N)
+        evk = self.empty(self.dnum, 2, self.L + self.K, self.N)
+        ws = self.workspace(self.L)
+        s_, sp = _i64(s)
+        e_, ep = _i64(e_pk)
+        ee_, eep = _i64(e_evk)
+        ap_ = np.ascontiguousarray(a_pk, dtype=np.uint64)
+        ae_ = np.ascontiguousarray(a_evk, dtype=np.uint64)
+        _check(L.he_keygen(self._h, sp, ep, ap_.ctypes.data_as(u64p), eep, ae_.ctypes.data_as(u64p),
+                           vp(pk.data_ptr()), vp(evk.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8,
+                           self._stream()), "he_keygen")
+        return pk, evk
+
+    def encrypt(self, level, m, v, e0, e1, pk):
+        ct = self.empty(2, level, self.N)
+        ws = self.workspace(level)
+        arrs = [_i64(x) for x in (m, v, e0, e1)]
+        _check(load_library().he_encrypt(self._h, level, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1],
+                                         vp(pk.data_ptr()), vp(ct.data_ptr()), vp(ws.data_ptr()),
+                                         ws.numel() * 8, self._stream()), "he_encrypt")
+        return ct
+
+    def decrypt_limbs(self, level, ct, s):
+        out = self.empty(level, self.N)
+        ws = self.workspace(level)
+        s_, sp = _i64(s)
+        _check(load_library().he_decrypt(self._h, level, vp(ct.data_ptr()), sp, vp(out.data_ptr()),
+                                         vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_decrypt")
+        return out
+
+    def he_mul(self, level, ct1, ct2, evk, relin=True, rescale=True, ws=None, out_relin=None, out=None):
+        """HE Mul; returns (relinearized ct or None, rescaled ct or None)."""
+        if relin and out_relin is None:
+            out_relin = self.empty(2, level, self.N)
+        if rescale and out is None:
+            out = self.empty(2, max(level - 1, 1), self.N)
+        ws = self.workspace(level) if ws is None else ws
+        _check(load_library().he_mul(self._h, level, vp(ct1.data_ptr()), vp(ct2.data_ptr()),
+                                     vp(evk.data_ptr()), vp(_ptr(out_relin) if relin else None),
+                                     vp(_ptr(out) if rescale else None), vp(ws.data_ptr()), ws.numel() * 8,
+                                     self._stream()), "he_mul")
+        return (out_relin if relin else None), (out if rescale else None)
+
+    def rescale(self, level, ct, out=None):
+        out = self.empty(2, max(level - 1, 1), self.N) if out is None else out
+        ws = self.workspace(level)
+        _check(load_library().he_rescale(self._h, level, vp(ct.data_ptr()), vp(out.data_ptr()),
+                                         vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_rescale")
+        return out
+
+    def timing(self, enable: bool, only: str = None):
+        """Bracket library kernels with HIP events (all kinds, or only `only`)."""
+        _check(load_library().he_timing_enable(self._h, int(enable), only.encode() if only else None),
+               "he_timing_enable")
+
+    def timing_read(self) -> dict:
+        """{kind: (launches, ms, ops, bytes)} since the last read (synchronize first)."""
+        arr = (KernelStat * 64)()
+        n = u32(0)
+        _check(load_library().he_timing_read(self._h, arr, 64, ctypes.byref(n)), "he_timing_read")
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].ops, arr[i].bytes)
+                for i in range(min(n.value, 64))}
+
+    def ntt(self, data, first_mod: int, inverse: bool = False):
+        """In-place transform of data [nlimbs][N]; limb r modulo modulus first_mod + r."""
+        nl = data.numel() // self.N
+        _check(load_library().he_ntt(self._h, vp(data.data_ptr()), nl, first_mod, int(inverse), self._stream()),
+               "he_ntt")
+        return data

@@ -1,0 +1,758 @@
+// C-ABI library: context (moduli, twiddle and base-conversion tables on the
+// device), key generation, encryption, decryption, HE Mul and rescale.
+// All device work is enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/he_mi355x.h"
+#include "host_math.hpp"
+#include "ntt.hpp"
+#include "rns_kernels.hpp"
+
+using namespace he;
+
+namespace {
+
+thread_local std::string g_err;
+
+he_status fail(he_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(x)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess)                                                            \
+      return fail(HE_EDEVICE, "%s failed: %s (%s:%d)", #x, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                               \
+  } while (0)
+
+// Host-side builder for one device blob of constant tables.
+struct Blob {
+  std::vector<uint8_t> bytes;
+  size_t add(const void* p, size_t n) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + n);
+    if (n) memcpy(bytes.data() + off, p, n);
+    return off;
+  }
+  template <class T>
+  size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
+};
+
+struct LevelPlan {
+  u32 beta = 0, dt_limbs = 0;
+  u32 lo[8] = {}, cnt[8] = {}, dt_first[8] = {};
+  size_t o_modup_jobs = 0, o_modup_consts = 0, o_modup_tmods = 0, o_modup_scale = 0, o_dt_mod = 0,
+         o_emod = 0, o_md_job = 0, o_md_consts = 0, o_qlinv = 0, o_qlmod = 0;
+  // resolved device pointers
+  const ConvJob* modup_jobs = nullptr;
+  const u64* modup_consts = nullptr;
+  const u32* modup_tmods = nullptr;
+  const u64* modup_scale = nullptr;
+  const u32* dt_mod = nullptr;
+  const u32* emod = nullptr;
+  const ConvJob* md_job = nullptr;
+  const u64* md_consts = nullptr;
+  const u64* qlinv = nullptr;
+  const u64* qlmod = nullptr;
+};
+
+}  // namespace
+
+struct he_ctx {
+  u32 log_n = 0, L = 0, K = 0, dnum = 0, alpha = 0;
+  u64 N = 0;
+  int device = 0;
+  std::vector<u64> mod;        // [L+K]
+  std::vector<u64> pmod_host;  // [P]_{m} for every modulus m
+  uint8_t* blob = nullptr;     // device constant tables
+  // device pointers into blob
+  const ModInfo* mods = nullptr;
+  const u64 *tw = nullptr, *tws = nullptr, *itw = nullptr, *itws = nullptr;
+  const u32* iota = nullptr;
+  const u64* spec_scale = nullptr;  // [K] pairs: N^-1 [(P/p_k)^-1]_{p_k}
+  const u64* pinv = nullptr;        // [L] pairs: [P^-1]_{q_i}
+  const u64* pmod = nullptr;        // [L+K]: [P]_m
+  std::vector<LevelPlan> lv;        // index = level (1..L)
+  // optional per-kernel timing (diagnostics)
+  bool timing = false;
+  std::string timing_only;          // empty = every kernel
+  struct TRec {
+    const char* name;
+    hipEvent_t a, b;
+    double ops, bytes;
+  };
+  std::vector<TRec> trecs;
+  std::vector<hipEvent_t> tpool;
+};
+
+namespace {
+
+size_t ceil_div(size_t a, size_t b) { return (a + b - 1) / b; }
+
+hipEvent_t pool_event(he_ctx* c) {
+  if (!c->tpool.empty()) {
+    hipEvent_t e = c->tpool.back();
+    c->tpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` (which enqueues one kernel on st); when timing is on for
+// `name`, bracket it with events and record its algorithmic work.
+template <class F>
+void timed(const he_ctx* cc, const char* name, double ops, double bytes, hipStream_t st, F&& launch) {
+  he_ctx* c = const_cast<he_ctx*>(cc);
+  const bool on = c->timing && (c->timing_only.empty() || c->timing_only == name);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (on) {
+    a = pool_event(c);
+    b = pool_event(c);
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  launch();
+  if (on && a && b) {
+    (void)hipEventRecord(b, st);
+    c->trecs.push_back({name, a, b, ops, bytes});
+  }
+}
+
+// ---------------------------------------------------------------- NTT dispatch
+template <bool FWD, int LOGS>
+void launch_cols(const he_ctx* c, const NttArgs& a, u32 nlimbs, u32 npolys, hipStream_t st) {
+  constexpr int LOGR = 4;
+  constexpr int T = (1 << LOGS) >> LOGR;
+  constexpr int C = 256 / T;
+  const u32 ncols = 1u << (a.log_n - LOGS);
+  const double units = (double)nlimbs * npolys;
+  const double bfly = units * (double)(c->N / 2) * LOGS + (FWD ? 0.0 : units * (double)c->N);
+  timed(c, FWD ? "ntt_cols" : "intt_cols", bfly, units * c->N * 16.0, st, [&] {
+    hipLaunchKernelGGL((k_ntt_cols<FWD, LOGS, LOGR, C>), dim3(ncols / C, nlimbs, npolys), dim3(T * C), 0, st, a);
+  });
+}
+template <bool FWD, int LOGS>
+void launch_blocks(const he_ctx* c, const NttArgs& a, u32 nlimbs, u32 npolys, hipStream_t st) {
+  constexpr int LOGR = 4;
+  constexpr int T = (1 << LOGS) >> LOGR;
+  constexpr int B = 256 / T;
+  const u32 nblk = 1u << (a.log_n - LOGS);
+  const double units = (double)nlimbs * npolys;
+  timed(c, FWD ? "ntt_blocks" : "intt_blocks", units * (double)(c->N / 2) * LOGS, units * c->N * 16.0, st, [&] {
+    hipLaunchKernelGGL((k_ntt_blocks<FWD, LOGS, LOGR, B>), dim3(nblk / B, nlimbs, npolys), dim3(T * B), 0, st,
+                       a);
+  });
+}
+template <bool FWD>
+void cols_dispatch(const he_ctx* c, int logs, const NttArgs& a, u32 nl, u32 np, hipStream_t st) {
+  switch (logs) {
+    case 6: launch_cols<FWD, 6>(c, a, nl, np, st); break;
+    case 7: launch_cols<FWD, 7>(c, a, nl, np, st); break;
+    case 8: launch_cols<FWD, 8>(c, a, nl, np, st); break;
+  }
+}
+template <bool FWD>
+void blocks_dispatch(const he_ctx* c, int logs, const NttArgs& a, u32 nl, u32 np, hipStream_t st) {
+  switch (logs) {
+    case 6: launch_blocks<FWD, 6>(c, a, nl, np, st); break;
+    case 7: launch_blocks<FWD, 7>(c, a, nl, np, st); break;
+    case 8: launch_blocks<FWD, 8>(c, a, nl, np, st); break;
+    case 9: launch_blocks<FWD, 9>(c, a, nl, np, st); break;
+  }
+}
+
+// Transform nlimbs limbs (x npolys polynomials).  src may equal dst.
+void ntt_launch(const he_ctx* c, bool fwd, const u64* src, u64* dst, u64 src_stride, u64 dst_stride,
+                u64 src_z, u64 dst_z, const u32* limb_mod, const u64* scale, u32 nlimbs, u32 npolys,
+                hipStream_t st) {
+  if (!nlimbs || !npolys) return;
+  const int n1 = (int)c->log_n / 2, n2 = (int)c->log_n - n1;
+  NttArgs a{};
+  a.limb_mod = limb_mod;
+  a.mods = c->mods;
+  a.log_n = c->log_n;
+  a.scale = scale;
+  if (fwd) {
+    a.tw = c->tw;
+    a.tws = c->tws;
+    a.src = src; a.dst = dst; a.src_stride = src_stride; a.dst_stride = dst_stride;
+    a.src_zstride = src_z; a.dst_zstride = dst_z;
+    cols_dispatch<true>(c, n1, a, nlimbs, npolys, st);
+    a.src = dst; a.src_stride = dst_stride; a.src_zstride = dst_z;
+    blocks_dispatch<true>(c, n2, a, nlimbs, npolys, st);
+  } else {
+    a.tw = c->itw;
+    a.tws = c->itws;
+    a.src = src; a.dst = dst; a.src_stride = src_stride; a.dst_stride = dst_stride;
+    a.src_zstride = src_z; a.dst_zstride = dst_z;
+    blocks_dispatch<false>(c, n2, a, nlimbs, npolys, st);
+    a.src = dst; a.src_stride = dst_stride; a.src_zstride = dst_z;
+    cols_dispatch<false>(c, n1, a, nlimbs, npolys, st);
+  }
+}
+
+dim3 ew_grid(u64 total) { return dim3((unsigned)ceil_div(total, EW_THREADS)); }
+
+// ---------------------------------------------------------------- tables
+ModInfo make_modinfo(u64 q, u64 N) {
+  ModInfo m{};
+  m.q = q;
+  m.b = bitlen(q);
+  m.mu = (u64)(((u128)1 << (2 * m.b)) / q);
+  m.r64 = (u64)(((u128)1 << 64) % q);
+  m.r64s = shoup(m.r64, q);
+  m.one_s = (u64)(((u128)1 << 64) / q);
+  m.ninv = invmod(N % q, q);
+  m.ninvs = shoup(m.ninv, q);
+  return m;
+}
+
+u64 prod_mod(const std::vector<u64>& ms, const std::vector<u32>& idx, u32 skip, u64 m) {
+  u64 r = 1 % m;
+  for (u32 i : idx)
+    if (i != skip) r = mulmod(r, ms[i] % m, m);
+  return r;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* he_status_str(he_status s) {
+  switch (s) {
+    case HE_OK: return "ok";
+    case HE_EINVAL: return "invalid argument";
+    case HE_ELEVEL: return "level out of range";
+    case HE_ENOMEM: return "insufficient memory or workspace";
+    case HE_EDEVICE: return "device error";
+    case HE_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown";
+}
+
+const char* he_last_error(void) { return g_err.c_str(); }
+
+he_status he_timing_enable(he_ctx* c, int enable, const char* only) {
+  if (!c) return fail(HE_EINVAL, "he_timing_enable: null context");
+  c->timing = enable != 0;
+  c->timing_only = only ? only : "";
+  return HE_OK;
+}
+
+he_status he_timing_read(he_ctx* c, he_kernel_stat* out, uint32_t max, uint32_t* n) {
+  if (!c || !n || (max && !out)) return fail(HE_EINVAL, "he_timing_read: null pointer");
+  std::vector<he_kernel_stat> agg;
+  for (auto& r : c->trecs) {
+    float ms = 0;
+    hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return fail(HE_EDEVICE, "he_timing_read: %s (synchronize the stream first)",
+                                     hipGetErrorString(e));
+    size_t k = 0;
+    while (k < agg.size() && strcmp(agg[k].name, r.name)) ++k;
+    if (k == agg.size()) {
+      he_kernel_stat z{};
+      snprintf(z.name, sizeof z.name, "%s", r.name);
+      agg.push_back(z);
+    }
+    agg[k].launches += 1;
+    agg[k].ms += ms;
+    agg[k].ops += r.ops;
+    agg[k].bytes += r.bytes;
+  }
+  for (auto& r : c->trecs) {
+    c->tpool.push_back(r.a);
+    c->tpool.push_back(r.b);
+  }
+  c->trecs.clear();
+  *n = (uint32_t)agg.size();
+  for (uint32_t i = 0; i < agg.size() && i < max; ++i) out[i] = agg[i];
+  return HE_OK;
+}
+
+he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uint64_t* exclude,
+                        uint32_t nexclude, uint64_t* out) {
+  if (!out || bits < 20 || bits > 61 || log_n < 1 || log_n > 20 || (nexclude && !exclude))
+    return fail(HE_EINVAL, "he_gen_primes: bad arguments");
+  if (!gen_primes(log_n, bits, count, exclude, nexclude, out))
+    return fail(HE_EINVAL, "he_gen_primes: fewer than %u primes", count);
+  return HE_OK;
+}
+
+he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                        const uint64_t* p, int device, he_ctx** out) {
+  if (!out || !q || !p) return fail(HE_EINVAL, "he_ctx_create: null pointer");
+  *out = nullptr;
+  if (log_n < 12 || log_n > 17) return fail(HE_EUNSUPPORTED, "log_n must be in [12, 17]");
+  if (L < 1 || L > 64 || K < 1 || K > 32 || dnum < 1 || dnum > L || dnum > 8)
+    return fail(HE_EINVAL, "need 1 <= dnum <= min(L, 8), L <= 64, 1 <= K <= 32");
+  const u64 N = 1ull << log_n;
+  std::unique_ptr<he_ctx> c(new he_ctx);
+  c->log_n = log_n; c->L = L; c->K = K; c->dnum = dnum; c->N = N;
+  c->alpha = (L + dnum - 1) / dnum;
+  c->device = device;
+  const u32 nm = L + K;
+  c->mod.assign(q, q + L);
+  c->mod.insert(c->mod.end(), p, p + K);
+  for (u32 i = 0; i < nm; ++i) {
+    const u64 m = c->mod[i];
+    if (m >= (1ull << 60) || m < (1ull << 20) || (m - 1) % (2 * N) || !is_prime(m))
+      return fail(HE_EINVAL, "modulus %u (%llu) is not a prime below 2^60 that is 1 mod 2N", i,
+                  (unsigned long long)m);
+    for (u32 j = 0; j < i; ++j)
+      if (c->mod[j] == m) return fail(HE_EINVAL, "moduli must be distinct");
+  }
+  if (c->alpha > CONV_MAX_SRC || K > CONV_MAX_SRC)
+    return fail(HE_EUNSUPPORTED, "digit size and K must be <= %d", CONV_MAX_SRC);
+  // special primes must cover every digit: P > prod(digit)
+  {
+    long double lp = 0, ld = 0;
+    for (u32 k = 0; k < K; ++k) lp += log2l((long double)p[k]);
+    for (u32 j = 0; j < dnum; ++j) {
+      ld = 0;
+      for (u32 i = j * c->alpha; i < std::min(L, (j + 1) * c->alpha); ++i) ld += log2l((long double)q[i]);
+      if (ld >= lp) return fail(HE_EINVAL, "special primes (%.1f bits) do not exceed digit %u (%.1f bits)",
+                                (double)lp, j, (double)ld);
+    }
+  }
+  std::vector<u32> all_idx(nm), pidx(K);
+  for (u32 i = 0; i < nm; ++i) all_idx[i] = i;
+  for (u32 k = 0; k < K; ++k) pidx[k] = L + k;
+
+  Blob B;
+  // moduli
+  std::vector<ModInfo> mi(nm);
+  for (u32 i = 0; i < nm; ++i) mi[i] = make_modinfo(c->mod[i], N);
+  const size_t o_mods = B.add(mi);
+  // twiddles: TB_W[k] = psi^bitrev(k), TB_invW[k] = psi^-bitrev(k), + Shoup companions
+  std::vector<u64> tw(nm * N), tws(nm * N), itw(nm * N), itws(nm * N);
+  for (u32 i = 0; i < nm; ++i) {
+    const u64 m = c->mod[i];
+    const u64 psi = min_root_2n(m, log_n), psii = invmod(psi, m);
+    std::vector<u64> pw(N), ipw(N);
+    pw[0] = ipw[0] = 1;
+    for (u64 k = 1; k < N; ++k) { pw[k] = mulmod(pw[k - 1], psi, m); ipw[k] = mulmod(ipw[k - 1], psii, m); }
+    for (u64 k = 0; k < N; ++k) {
+      const unsigned e = bitrev((unsigned)k, log_n);
+      tw[i * N + k] = pw[e];
+      tws[i * N + k] = shoup(pw[e], m);
+      itw[i * N + k] = ipw[e];
+      itws[i * N + k] = shoup(ipw[e], m);
+    }
+  }
+  const size_t o_tw = B.add(tw), o_tws = B.add(tws), o_itw = B.add(itw), o_itws = B.add(itws);
+  const size_t o_iota = B.add(all_idx);
+  // ModDown constants (level independent)
+  std::vector<u64> spec_scale(2 * K), pinv(2 * L), pm(nm);
+  for (u32 k = 0; k < K; ++k) {
+    const u64 m = p[k];
+    const u64 v = mulmod(invmod(N % m, m), invmod(prod_mod(c->mod, pidx, L + k, m), m), m);
+    spec_scale[2 * k] = v;
+    spec_scale[2 * k + 1] = shoup(v, m);
+  }
+  for (u32 i = 0; i < nm; ++i) pm[i] = prod_mod(c->mod, pidx, ~0u, c->mod[i]);
+  for (u32 i = 0; i < L; ++i) {
+    const u64 v = invmod(pm[i], q[i]);
+    pinv[2 * i] = v;
+    pinv[2 * i + 1] = shoup(v, q[i]);
+  }
+  c->pmod_host = pm;
+  const size_t o_spec = B.add(spec_scale), o_pinv = B.add(pinv), o_pmod = B.add(pm);
+
+  // per-level plans
+  c->lv.resize(L + 1);
+  for (u32 lvl = 1; lvl <= L; ++lvl) {
+    LevelPlan& P = c->lv[lvl];
+    P.beta = (lvl + c->alpha - 1) / c->alpha;
+    const u32 ne = lvl + K;
+    std::vector<u32> emod(ne);
+    for (u32 e = 0; e < ne; ++e) emod[e] = e < lvl ? e : L + (e - lvl);
+    std::vector<ConvJob> jobs(P.beta);
+    std::vector<u64> consts, scale(2 * lvl);
+    std::vector<u32> tmods, dt_mod;
+    u32 dt_first = 0;
+    for (u32 j = 0; j < P.beta; ++j) {
+      const u32 lo = j * c->alpha, hi = std::min(lvl, (j + 1) * c->alpha);
+      P.lo[j] = lo; P.cnt[j] = hi - lo; P.dt_first[j] = dt_first;
+      std::vector<u32> dig;
+      for (u32 i = lo; i < hi; ++i) dig.push_back(i);
+      for (u32 i = lo; i < hi; ++i) {  // y_i scale: N^-1 [(Qt_j / q_i)^-1]_{q_i}
+        const u64 m = q[i];
+        const u64 v = mulmod(invmod(N % m, m), invmod(prod_mod(c->mod, dig, i, m), m), m);
+        scale[2 * i] = v;
+        scale[2 * i + 1] = shoup(v, m);
+      }
+      ConvJob& J = jobs[j];
+      J.src_off = lo; J.ns = hi - lo; J.dst_off = dt_first; J.nt = ne - (hi - lo);
+      J.c_off = (u32)consts.size(); J.m_off = (u32)tmods.size();
+      std::vector<u32> tg;
+      for (u32 e = 0; e < ne; ++e)
+        if (!(e >= lo && e < hi)) tg.push_back(emod[e]);
+      std::vector<u64> C((hi - lo) * tg.size());
+      for (u32 s = 0; s < hi - lo; ++s)
+        for (size_t t = 0; t < tg.size(); ++t) C[s * tg.size() + t] = prod_mod(c->mod, dig, lo + s, c->mod[tg[t]]);
+      consts.insert(consts.end(), C.begin(), C.end());
+      tmods.insert(tmods.end(), tg.begin(), tg.end());
+      dt_mod.insert(dt_mod.end(), tg.begin(), tg.end());
+      dt_first += (u32)tg.size();
+    }
+    P.dt_limbs = dt_first;
+    // ModDown job: sources = K special limbs (after scaling), targets q_0..q_{lvl-1}
+    ConvJob md{};
+    md.src_off = lvl; md.ns = K; md.dst_off = 0; md.nt = lvl; md.c_off = 0; md.m_off = 0;
+    std::vector<u64> mdc((size_t)K * lvl);
+    for (u32 k = 0; k < K; ++k)
+      for (u32 i = 0; i < lvl; ++i) mdc[(size_t)k * lvl + i] = prod_mod(c->mod, pidx, L + k, q[i]);
+    // rescale constants
+    std::vector<u64> qlinv(2 * (lvl > 1 ? lvl - 1 : 1), 0), qlmod(lvl > 1 ? lvl - 1 : 1, 0);
+    for (u32 i = 0; i + 1 < lvl; ++i) {
+      const u64 m = q[i], ql = q[lvl - 1] % m;
+      qlmod[i] = ql;
+      qlinv[2 * i] = invmod(ql, m);
+      qlinv[2 * i + 1] = shoup(qlinv[2 * i], m);
+    }
+    P.o_modup_jobs = B.add(jobs); P.o_modup_consts = B.add(consts); P.o_modup_tmods = B.add(tmods);
+    P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_emod = B.add(emod);
+    P.o_md_job = B.add(&md, sizeof md); P.o_md_consts = B.add(mdc);
+    P.o_qlinv = B.add(qlinv); P.o_qlmod = B.add(qlmod);
+  }
+
+  HIP_TRY(hipSetDevice(device));
+  HIP_TRY(hipMalloc(&c->blob, B.bytes.size()));
+  {
+    hipError_t e = hipMemcpy(c->blob, B.bytes.data(), B.bytes.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(c->blob);
+      return fail(HE_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
+    }
+  }
+  uint8_t* b = c->blob;
+  c->mods = (const ModInfo*)(b + o_mods);
+  c->tw = (const u64*)(b + o_tw); c->tws = (const u64*)(b + o_tws);
+  c->itw = (const u64*)(b + o_itw); c->itws = (const u64*)(b + o_itws);
+  c->iota = (const u32*)(b + o_iota);
+  c->spec_scale = (const u64*)(b + o_spec); c->pinv = (const u64*)(b + o_pinv);
+  c->pmod = (const u64*)(b + o_pmod);
+  for (u32 lvl = 1; lvl <= L; ++lvl) {
+    LevelPlan& P = c->lv[lvl];
+    P.modup_jobs = (const ConvJob*)(b + P.o_modup_jobs);
+    P.modup_consts = (const u64*)(b + P.o_modup_consts);
+    P.modup_tmods = (const u32*)(b + P.o_modup_tmods);
+    P.modup_scale = (const u64*)(b + P.o_modup_scale);
+    P.dt_mod = (const u32*)(b + P.o_dt_mod);
+    P.emod = (const u32*)(b + P.o_emod);
+    P.md_job = (const ConvJob*)(b + P.o_md_job);
+    P.md_consts = (const u64*)(b + P.o_md_consts);
+    P.qlinv = (const u64*)(b + P.o_qlinv);
+    P.qlmod = (const u64*)(b + P.o_qlmod);
+  }
+  *out = c.release();
+  return HE_OK;
+}
+
+void he_ctx_destroy(he_ctx* c) {
+  if (!c) return;
+  for (auto& r : c->trecs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->tpool) (void)hipEventDestroy(e);
+  if (c->blob) {
+    (void)hipSetDevice(c->device);
+    (void)hipFree(c->blob);
+  }
+  delete c;
+}
+
+he_status he_ctx_info(const he_ctx* c, uint32_t* log_n, uint32_t* L, uint32_t* K, uint32_t* dnum,
+                      uint64_t* moduli) {
+  if (!c) return fail(HE_EINVAL, "null context");
+  if (log_n) *log_n = c->log_n;
+  if (L) *L = c->L;
+  if (K) *K = c->K;
+  if (dnum) *dnum = c->dnum;
+  if (moduli) memcpy(moduli, c->mod.data(), c->mod.size() * sizeof(u64));
+  return HE_OK;
+}
+
+size_t he_ct_bytes(const he_ctx* c, uint32_t level) { return c ? 2ull * level * c->N * 8 : 0; }
+size_t he_evk_bytes(const he_ctx* c) { return c ? (size_t)c->dnum * 2 * (c->L + c->K) * c->N * 8 : 0; }
+size_t he_pk_bytes(const he_ctx* c) { return c ? 2ull * c->L * c->N * 8 : 0; }
+
+static size_t mul_ws_limbs(const he_ctx* c, u32 level) {
+  const LevelPlan& P = c->lv[level];
+  // D2, Y, DT, KS, Z, RL, RS
+  return (size_t)level + level + P.dt_limbs + 2 * (level + c->K) + 2 * level + 2 * level + 2;
+}
+static size_t keygen_ws_limbs(const he_ctx* c) {
+  // S, S2, E (over L+K) + staging for small vectors (dnum+2 int64 vectors)
+  return 3 * (size_t)(c->L + c->K) + c->dnum + 2;
+}
+
+size_t he_workspace_bytes(const he_ctx* c, uint32_t level) {
+  if (!c || level < 1 || level > c->L) return 0;
+  size_t l = mul_ws_limbs(c, level);
+  if (level == c->L) l = std::max(l, keygen_ws_limbs(c));
+  l = std::max(l, 3 * (size_t)level + 4);  // encrypt / decrypt
+  return l * c->N * 8;
+}
+
+he_status he_ntt(he_ctx* c, uint64_t* d, uint32_t nlimbs, uint32_t first_mod, int inverse,
+                 he_stream stream) {
+  if (!c || !d) return fail(HE_EINVAL, "he_ntt: null pointer");
+  if (first_mod + nlimbs > c->L + c->K) return fail(HE_EINVAL, "he_ntt: modulus range");
+  HIP_TRY(hipSetDevice(c->device));
+  ntt_launch(c, !inverse, d, d, c->N, c->N, 0, 0, c->iota + first_mod, nullptr, nlimbs, 1,
+             (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return HE_OK;
+}
+
+static he_status rescale_impl(he_ctx* c, u32 level, const u64* rl, u64* out, u64* rs, u64* s,
+                              hipStream_t st) {
+  const u64 N = c->N;
+  const LevelPlan& P = c->lv[level];
+  // r_u = INTT(c_u[level-1])  (2 polys, 1 limb)
+  ntt_launch(c, false, rl + (u64)(level - 1) * N, rs, N, N, (u64)level * N, N, c->iota + (level - 1),
+             nullptr, 1, 2, st);
+  const u64 tot = (u64)(level - 1) * N;
+  timed(c, "rescale_lift", 2.0 * tot, (2.0 * tot + 2.0 * N) * 8, st, [&] {
+    hipLaunchKernelGGL(k_rescale_lift, ew_grid(tot), dim3(EW_THREADS), 0, st, rs, s, P.qlmod, c->mods,
+                       level, c->mod[level - 1], c->log_n);
+  });
+  ntt_launch(c, true, s, s, N, N, tot, tot, c->iota, nullptr, level - 1, 2, st);
+  timed(c, "rescale_combine", 2.0 * tot, 6.0 * tot * 8, st, [&] {
+    hipLaunchKernelGGL(k_rescale_combine, ew_grid(tot), dim3(EW_THREADS), 0, st, rl, s, out, P.qlinv,
+                       c->mods, level, c->log_n);
+  });
+  HIP_TRY(hipGetLastError());
+  return HE_OK;
+}
+
+he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,
+                     size_t ws_bytes, he_stream stream) {
+  if (!c || !d_in || !d_out || !ws) return fail(HE_EINVAL, "he_rescale: null pointer");
+  if (level < 2 || level > c->L) return fail(HE_ELEVEL, "he_rescale: level %u not in [2, L]", level);
+  if (ws_bytes < (2 + 2 * (size_t)level) * c->N * 8) return fail(HE_ENOMEM, "he_rescale: workspace too small");
+  HIP_TRY(hipSetDevice(c->device));
+  u64* w = (u64*)ws;
+  return rescale_impl(c, level, d_in, d_out, w, w + 2 * c->N, (hipStream_t)stream);
+}
+
+he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t* ct2,
+                 const uint64_t* evk, uint64_t* relin, uint64_t* out, void* ws, size_t ws_bytes,
+                 he_stream stream) {
+  if (!c || !ct1 || !ct2 || !evk || !ws) return fail(HE_EINVAL, "he_mul: null pointer");
+  if (!relin && !out) return fail(HE_EINVAL, "he_mul: no output requested");
+  if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_mul: level %u not in [1, L]", level);
+  if (out && level < 2) return fail(HE_ELEVEL, "he_mul: rescale needs level >= 2");
+  if (ws_bytes < mul_ws_limbs(c, level) * c->N * 8) return fail(HE_ENOMEM, "he_mul: workspace too small");
+  const u64 N = c->N, ct_words = 2ull * level * N;
+  auto overlaps = [](const void* a, size_t na, const void* b, size_t nb) {
+    return (const uint8_t*)a < (const uint8_t*)b + nb && (const uint8_t*)b < (const uint8_t*)a + na;
+  };
+  for (const u64* o : {(const u64*)relin, (const u64*)out}) {
+    if (!o) continue;
+    if (overlaps(o, ct_words * 8, ct1, ct_words * 8) || overlaps(o, ct_words * 8, ct2, ct_words * 8))
+      return fail(HE_EINVAL, "he_mul: output aliases an input");
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const LevelPlan& P = c->lv[level];
+  const u32 K = c->K, ne = level + K;
+  u64* w = (u64*)ws;
+  u64* D2 = w;               w += (u64)level * N;
+  u64* Y = w;                w += (u64)level * N;
+  u64* DT = w;               w += (u64)P.dt_limbs * N;
+  u64* KS = w;               w += 2ull * ne * N;
+  u64* Z = w;                w += 2ull * level * N;
+  u64* RLw = w;              w += 2ull * level * N;
+  u64* RS = w;
+  u64* RL = relin ? relin : RLw;
+  const u64 tot = (u64)level * N;
+
+  // region 1: tensor product
+  timed(c, "tensor", 4.0 * tot, 7.0 * tot * 8, st, [&] {
+    hipLaunchKernelGGL(k_tensor, ew_grid(tot), dim3(EW_THREADS), 0, st, ct1, ct2, RL, D2, c->mods, level,
+                       c->log_n);
+  });
+  // ModUp: y_i = INTT(d2_i) * [(Qt_j/q_i)^-1]  (scale merged with N^-1)
+  ntt_launch(c, false, D2, Y, N, N, 0, 0, c->iota, P.modup_scale, level, 1, st);
+  {
+    double macs = 0, limbs = 0;
+    for (u32 j = 0; j < P.beta; ++j) {
+      macs += (double)P.cnt[j] * (ne - P.cnt[j]) * N;
+      limbs += P.cnt[j] + (ne - P.cnt[j]);
+    }
+    timed(c, "modup_convert", macs, limbs * N * 8, st, [&] {
+      hipLaunchKernelGGL(k_convert, dim3((unsigned)ceil_div(N, EW_THREADS), P.beta, 1), dim3(EW_THREADS), 0, st,
+                         Y, DT, P.modup_jobs, P.modup_consts, P.modup_tmods, c->mods, c->log_n, 0ull, 0ull);
+    });
+  }
+  ntt_launch(c, true, DT, DT, N, N, 0, 0, P.dt_mod, nullptr, P.dt_limbs, 1, st);
+  // inner product with evk
+  IpArgs ia{};
+  ia.d2 = D2; ia.dt = DT; ia.evk = evk; ia.ks = KS; ia.mods = c->mods; ia.emod = P.emod;
+  for (u32 j = 0; j < P.beta; ++j) { ia.dt_first[j] = P.dt_first[j]; ia.lo[j] = P.lo[j]; ia.cnt[j] = P.cnt[j]; }
+  ia.beta = P.beta; ia.level = level; ia.K = K; ia.L = c->L; ia.log_n = c->log_n;
+  timed(c, "inner_product", 2.0 * P.beta * ne * N, (3.0 * P.beta + 2) * ne * N * 8, st, [&] {
+    hipLaunchKernelGGL(k_inner_product, dim3((unsigned)ceil_div(N, EW_THREADS), ne), dim3(EW_THREADS), 0, st, ia);
+  });
+  // ModDown: y_k = INTT(ks special k) * [(P/p_k)^-1], z_i = conv, Z = NTT(z)
+  ntt_launch(c, false, KS + (u64)level * N, KS + (u64)level * N, N, N, (u64)ne * N, (u64)ne * N,
+             c->iota + c->L, c->spec_scale, K, 2, st);
+  timed(c, "moddown_convert", 2.0 * K * level * N, 2.0 * (K + level) * N * 8, st, [&] {
+    hipLaunchKernelGGL(k_convert, dim3((unsigned)ceil_div(N, EW_THREADS), 1, 2), dim3(EW_THREADS), 0, st,
+                       KS, Z, P.md_job, P.md_consts, c->iota, c->mods, c->log_n, (u64)ne * N, tot);
+  });
+  ntt_launch(c, true, Z, Z, N, N, tot, tot, c->iota, nullptr, level, 2, st);
+  timed(c, "moddown_combine", 2.0 * tot, 2.0 * 4 * tot * 8, st, [&] {
+    hipLaunchKernelGGL(k_moddown_combine, ew_grid(tot), dim3(EW_THREADS), 0, st, RL, KS, Z, c->pinv, c->mods,
+                       level, K, c->log_n);
+  });
+  HIP_TRY(hipGetLastError());
+  if (out) return rescale_impl(c, level, RL, out, RS, Z, st);
+  return HE_OK;
+}
+
+// ---------------------------------------------------------------- keys & encryption
+static he_status upload_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return HE_OK;
+}
+
+he_status he_keygen(he_ctx* c, const int64_t* s, const int64_t* e_pk, const uint64_t* a_pk,
+                    const int64_t* e_evk, const uint64_t* a_evk, uint64_t* d_pk, uint64_t* d_evk,
+                    void* ws, size_t ws_bytes, he_stream stream) {
+  if (!c || !s || !e_pk || !a_pk || !e_evk || !a_evk || !d_pk || !d_evk || !ws)
+    return fail(HE_EINVAL, "he_keygen: null pointer");
+  if (ws_bytes < keygen_ws_limbs(c) * c->N * 8) return fail(HE_ENOMEM, "he_keygen: workspace too small");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const u64 N = c->N;
+  const u32 L = c->L, K = c->K, nm = L + K;
+  u64* w = (u64*)ws;
+  u64* S = w;  w += (u64)nm * N;
+  u64* S2 = w; w += (u64)nm * N;
+  u64* E = w;  w += (u64)nm * N;
+  int64_t* sv = (int64_t*)w;             // [N]
+  int64_t* ev = sv + N;                  // [N]
+  int64_t* eev = ev + N;                 // [dnum][N]
+  he_status r;
+  if ((r = upload_sync(sv, s, N * 8, st)) != HE_OK) return r;
+  if ((r = upload_sync(ev, e_pk, N * 8, st)) != HE_OK) return r;
+  if ((r = upload_sync(eev, e_evk, (u64)c->dnum * N * 8, st)) != HE_OK) return r;
+  // pk over q_0..q_{L-1}: a (host) -> d_pk poly 1
+  if ((r = upload_sync(d_pk + (u64)L * N, a_pk, (u64)L * N * 8, st)) != HE_OK) return r;
+  hipLaunchKernelGGL(k_small_to_limbs, ew_grid((u64)nm * N), dim3(EW_THREADS), 0, st, sv, S, c->iota, c->mods,
+                     nm, c->log_n);
+  ntt_launch(c, true, S, S, N, N, 0, 0, c->iota, nullptr, nm, 1, st);
+  hipLaunchKernelGGL(k_small_to_limbs, ew_grid((u64)L * N), dim3(EW_THREADS), 0, st, ev, E, c->iota, c->mods,
+                     L, c->log_n);
+  ntt_launch(c, true, E, E, N, N, 0, 0, c->iota, nullptr, L, 1, st);
+  hipLaunchKernelGGL(k_mul_add, ew_grid((u64)L * N), dim3(EW_THREADS), 0, st, d_pk + (u64)L * N, S, E, d_pk,
+                     c->iota, c->mods, L, c->log_n);
+  // evk
+  hipLaunchKernelGGL(k_mul, ew_grid((u64)nm * N), dim3(EW_THREADS), 0, st, S, S, S2, c->iota, c->mods, nm,
+                     c->log_n);
+  for (u32 j = 0; j < c->dnum; ++j) {
+    u64* bj = d_evk + (u64)j * 2 * nm * N;
+    u64* aj = bj + (u64)nm * N;
+    if ((r = upload_sync(aj, a_evk + (u64)j * nm * N, (u64)nm * N * 8, st)) != HE_OK) return r;
+    hipLaunchKernelGGL(k_small_to_limbs, ew_grid((u64)nm * N), dim3(EW_THREADS), 0, st, eev + (u64)j * N, E,
+                       c->iota, c->mods, nm, c->log_n);
+    ntt_launch(c, true, E, E, N, N, 0, 0, c->iota, nullptr, nm, 1, st);
+    const u32 dlo = j * c->alpha, dhi = std::min(L, (j + 1) * c->alpha);
+    hipLaunchKernelGGL(k_evk_b, ew_grid((u64)nm * N), dim3(EW_THREADS), 0, st, aj, S, S2, E, bj, c->pmod,
+                       c->mods, nm, dlo, dhi, c->log_n);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return HE_OK;
+}
+
+he_status he_encrypt(he_ctx* c, uint32_t level, const int64_t* m, const int64_t* v, const int64_t* e0,
+                     const int64_t* e1, const uint64_t* d_pk, uint64_t* d_ct, void* ws, size_t ws_bytes,
+                     he_stream stream) {
+  if (!c || !m || !v || !e0 || !e1 || !d_pk || !d_ct || !ws) return fail(HE_EINVAL, "he_encrypt: null pointer");
+  if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_encrypt: level %u not in [1, L]", level);
+  if (ws_bytes < (3 * (size_t)level + 4) * c->N * 8) return fail(HE_ENOMEM, "he_encrypt: workspace too small");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const u64 N = c->N, tot = (u64)level * N;
+  u64* w = (u64*)ws;
+  u64* V = w;  w += tot;
+  u64* T0 = w; w += tot;
+  u64* T1 = w; w += tot;
+  int64_t* hv = (int64_t*)w;
+  he_status r;
+  if ((r = upload_sync(hv, v, N * 8, st)) != HE_OK) return r;
+  if ((r = upload_sync(hv + N, e0, N * 8, st)) != HE_OK) return r;
+  if ((r = upload_sync(hv + 2 * N, m, N * 8, st)) != HE_OK) return r;
+  if ((r = upload_sync(hv + 3 * N, e1, N * 8, st)) != HE_OK) return r;
+  auto to_ntt = [&](const int64_t* src, u64* dst) {
+    hipLaunchKernelGGL(k_small_to_limbs, ew_grid(tot), dim3(EW_THREADS), 0, st, src, dst, c->iota, c->mods,
+                       level, c->log_n);
+    ntt_launch(c, true, dst, dst, N, N, 0, 0, c->iota, nullptr, level, 1, st);
+  };
+  to_ntt(hv, V);
+  // T0 = NTT(e0 mod q + m mod q): expand both, add, transform
+  hipLaunchKernelGGL(k_small_to_limbs, ew_grid(tot), dim3(EW_THREADS), 0, st, hv + N, T0, c->iota, c->mods,
+                     level, c->log_n);
+  hipLaunchKernelGGL(k_small_to_limbs, ew_grid(tot), dim3(EW_THREADS), 0, st, hv + 2 * N, T1, c->iota, c->mods,
+                     level, c->log_n);
+  hipLaunchKernelGGL(k_add, ew_grid(tot), dim3(EW_THREADS), 0, st, T0, T1, T0, c->iota, c->mods, level,
+                     c->log_n);
+  ntt_launch(c, true, T0, T0, N, N, 0, 0, c->iota, nullptr, level, 1, st);
+  to_ntt(hv + 3 * N, T1);
+  hipLaunchKernelGGL(k_mul_add, ew_grid(tot), dim3(EW_THREADS), 0, st, V, d_pk, T0, d_ct, c->iota, c->mods,
+                     level, c->log_n);
+  hipLaunchKernelGGL(k_mul_add, ew_grid(tot), dim3(EW_THREADS), 0, st, V, d_pk + (u64)c->L * N, T1,
+                     d_ct + tot, c->iota, c->mods, level, c->log_n);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return HE_OK;
+}
+
+he_status he_decrypt(he_ctx* c, uint32_t level, const uint64_t* d_ct, const int64_t* s, uint64_t* d_m,
+                     void* ws, size_t ws_bytes, he_stream stream) {
+  if (!c || !d_ct || !s || !d_m || !ws) return fail(HE_EINVAL, "he_decrypt: null pointer");
+  if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_decrypt: level %u not in [1, L]", level);
+  if (ws_bytes < ((size_t)level + 1) * c->N * 8) return fail(HE_ENOMEM, "he_decrypt: workspace too small");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const u64 N = c->N, tot = (u64)level * N;
+  u64* S = (u64*)ws;
+  int64_t* sv = (int64_t*)(S + tot);
+  he_status r;
+  if ((r = upload_sync(sv, s, N * 8, st)) != HE_OK) return r;
+  hipLaunchKernelGGL(k_small_to_limbs, ew_grid(tot), dim3(EW_THREADS), 0, st, sv, S, c->iota, c->mods, level,
+                     c->log_n);
+  ntt_launch(c, true, S, S, N, N, 0, 0, c->iota, nullptr, level, 1, st);
+  hipLaunchKernelGGL(k_dec, ew_grid(tot), dim3(EW_THREADS), 0, st, d_ct, S, d_m, c->mods, level, c->log_n);
+  ntt_launch(c, false, d_m, d_m, N, N, 0, 0, c->iota, nullptr, level, 1, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return HE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Device modular arithmetic for 64-bit residues on gfx950's 32-bit integer
+// ALUs.  Every 64x64 product is built from v_mad_u64_u32 / v_mul_hi_u32
+// partial products.  Moduli are odd primes below 2^60.
+//
+//   shoup_lazy : Shoup's modular multiplication by a constant with a
+//                precomputed companion (Algorithm 2), result in [0, 2q),
+//                correction left to the caller (lazy range).
+//   barrett    : reduction of a 128-bit value below 2^(2b+2) (b = bit length
+//                of q), result canonical.
+//   reduce128  : reduction of any 128-bit value with high word < 2^64 via
+//                two Shoup steps (2^64 mod q and 1), result canonical.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace he {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+struct U128 {
+  u64 lo, hi;
+};
+
+__device__ __forceinline__ U128 mul_wide(u64 a, u64 b) {
+  const u32 al = (u32)a, ah = (u32)(a >> 32), bl = (u32)b, bh = (u32)(b >> 32);
+  const u64 p0 = (u64)al * bl, p1 = (u64)al * bh, p2 = (u64)ah * bl, p3 = (u64)ah * bh;
+  const u64 mid = (p0 >> 32) + (u32)p1 + (u32)p2;
+  U128 r;
+  r.lo = (mid << 32) | (u32)p0;
+  r.hi = p3 + (p1 >> 32) + (p2 >> 32) + (mid >> 32);
+  return r;
+}
+
+__device__ __forceinline__ void add_to(U128& acc, const U128& x) {
+  acc.lo += x.lo;
+  acc.hi += x.hi + (acc.lo < x.lo ? 1 : 0);
+}
+
+__device__ __forceinline__ u64 mulhi(u64 a, u64 b) { return __umul64hi(a, b); }
+
+__device__ __forceinline__ u64 csub(u64 x, u64 m) { return x >= m ? x - m : x; }
+
+// x*w mod q in [0, 2q) for any x < 2^64; w < q, ws = floor(w 2^64 / q)
+__device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 ws, u64 q) {
+  return x * w - mulhi(x, ws) * q;
+}
+__device__ __forceinline__ u64 shoup(u64 x, u64 w, u64 ws, u64 q) {
+  return csub(shoup_lazy(x, w, ws, q), q);
+}
+
+// Per-modulus constants shared by all kernels.
+struct ModInfo {
+  u64 q;
+  u64 mu;      // floor(2^(2b) / q), Barrett
+  u64 r64;     // 2^64 mod q
+  u64 r64s;    // Shoup companion of r64
+  u64 one_s;   // floor(2^64 / q): Shoup companion of 1
+  u64 ninv;    // N^{-1} mod q
+  u64 ninvs;   // Shoup companion of ninv
+  u32 b;       // bit length of q
+  u32 pad;
+};
+
+// x < 2^(2b+2): canonical x mod q.
+__device__ __forceinline__ u64 barrett(U128 x, const ModInfo& m) {
+  const u32 s = m.b - 1;
+  const u64 x1 = (x.lo >> s) | (x.hi << (64 - s));
+  const U128 p = mul_wide(x1, m.mu);
+  const u32 t = m.b + 1;
+  const u64 qh = (p.lo >> t) | (p.hi << (64 - t));
+  u64 r = x.lo - qh * m.q;  // in [0, 7q)
+  const u64 q2 = m.q << 1, q4 = m.q << 2;
+  r = csub(r, q4);
+  r = csub(r, q2);
+  return csub(r, m.q);
+}
+
+// Any x with x.hi < 2^64: canonical x mod q.
+__device__ __forceinline__ u64 reduce128(U128 x, const ModInfo& m) {
+  const u64 u = shoup_lazy(x.hi, m.r64, m.r64s, m.q);    // hi * 2^64 mod q, [0, 2q)
+  const u64 v = x.lo - mulhi(x.lo, m.one_s) * m.q;       // lo mod q, [0, 2q)
+  u64 r = u + v;                                         // [0, 4q)
+  r = csub(r, m.q << 1);
+  return csub(r, m.q);
+}
+
+// canonical (a*b) mod q for a, b < q
+__device__ __forceinline__ u64 mulmod(u64 a, u64 b, const ModInfo& m) { return barrett(mul_wide(a, b), m); }
+
+__device__ __forceinline__ u64 addmod(u64 a, u64 b, u64 q) { return csub(a + b, q); }
+__device__ __forceinline__ u64 submod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+}  // namespace he
