@@ -3,7 +3,7 @@
  *
  * Method: "HEAAN Demystified" (arXiv 2003.04510).  HE Mul = region 1 tensor
  * product of two ciphertexts, region 2 key switching with the evaluation key,
- * then rescale (Fig. 2, Sec. II-B; rescale by division, Sec. II-A), in the
+ * then rescale (Fig. 2, Sec. III-B; rescale by division, Sec. III-A), in the
  * full-RNS form the paper names in Table XI: NTT/iNTT (Algorithms 3-4) plus
  * mod up / mod down (fast base conversion, the Discussion section).
  *
@@ -78,7 +78,7 @@ size_t he_evk_bytes(const he_ctx* ctx);                     /* dnum*2*(L+K)*N*8 
 size_t he_pk_bytes(const he_ctx* ctx);                      /* 2*L*N*8 */
 size_t he_workspace_bytes(const he_ctx* ctx, uint32_t level); /* for he_mul/he_rescale/keygen/... */
 
-/* Key generation (Sec. II-A: pk from sk; evk encrypts a multiple of sk^2,
+/* Key generation (Sec. III-A: pk from sk; evk encrypts a multiple of sk^2,
  * Fig. 2).  Random draws are inputs (host): s [N] ternary secret, e_pk [N],
  * e_evk [dnum][N] small signed errors, a_pk [L][N] and a_evk [dnum][L+K][N]
  * uniform residues (already NTT form, row i uniform mod modulus i).
@@ -91,14 +91,14 @@ he_status he_keygen(he_ctx* ctx, const int64_t* s, const int64_t* e_pk, const ui
                     const int64_t* e_evk, const uint64_t* a_evk, uint64_t* d_pk, uint64_t* d_evk,
                     void* ws, size_t ws_bytes, he_stream stream);
 
-/* Public-key encryption at `level` (Sec. II-A): ct = (v*pk0 + e0 + m,
+/* Public-key encryption at `level` (Sec. III-A): ct = (v*pk0 + e0 + m,
  * v*pk1 + e1).  m, v, e0, e1: host signed coefficient vectors [N]
  * (m = the encoded plaintext).  d_ct: [2][level][N]. */
 he_status he_encrypt(he_ctx* ctx, uint32_t level, const int64_t* m, const int64_t* v,
                      const int64_t* e0, const int64_t* e1, const uint64_t* d_pk, uint64_t* d_ct,
                      void* ws, size_t ws_bytes, he_stream stream);
 
-/* Decryption to RNS coefficients (Sec. II-A: t = bx - ax*sk): writes
+/* Decryption to RNS coefficients (Sec. III-A: t = bx - ax*sk): writes
  * d_m [level][N], coefficient form, limb i modulo q_i.  s: host [N]. */
 he_status he_decrypt(he_ctx* ctx, uint32_t level, const uint64_t* d_ct, const int64_t* s,
                      uint64_t* d_m, void* ws, size_t ws_bytes, he_stream stream);
@@ -113,7 +113,7 @@ he_status he_mul(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint6
                  const uint64_t* d_evk, uint64_t* d_relin, uint64_t* d_out, void* ws,
                  size_t ws_bytes, he_stream stream);
 
-/* Rescale (Sec. II-A, division by the last prime, rounded to nearest):
+/* Rescale (Sec. III-A, division by the last prime, rounded to nearest):
  * d_in [2][level][N] -> d_out [2][level-1][N].  level >= 2. */
 he_status he_rescale(he_ctx* ctx, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,
                      size_t ws_bytes, he_stream stream);

@@ -10,10 +10,10 @@
  *
  * Paper: "HEAAN Demystified" (arXiv 2003.04510).
  *   - NTT: Algorithm 3 (NTT) with Algorithm 4 (butt), powers of the 2N-th
- *     root of unity indexed TB_W[m+j] (Sec. III); iNTT: inverse butterflies
- *     with TB_invW and a final division by N (Sec. III, iNTT paragraph).
+ *     root of unity indexed TB_W[m+j] (Sec. IV); iNTT: inverse butterflies
+ *     with TB_invW and a final division by N (Sec. IV, iNTT paragraph).
  *   - HE Mul flow: Fig. 2 (region 1 tensor, region 2 key switching with evk,
- *     shift), rescale by division (Sec. II-A).
+ *     shift), rescale by division (Sec. III-A).
  *   - Full-RNS form (mod up / mod down): Table XI and the Discussion section
  *     ("applicability to other libraries"); the paper only names these
  *     functions, so the formulas below are the standard fast base conversion
@@ -364,7 +364,7 @@ void orc_moddown_combine(const orc_ctx* c, uint32_t level, const uint64_t* ks, c
   free(y); free(phat_inv); free(phat_q); free(pinv_q);
 }
 
-/* ---------- rescale (Sec. II-A: divide by the last prime) ---------- */
+/* ---------- rescale (Sec. III-A: divide by the last prime) ---------- */
 /* in: [2][level][N] NTT; out: [2][level-1][N] NTT. */
 void orc_rescale(const orc_ctx* c, uint32_t level, const uint64_t* in, uint64_t* out) {
   uint64_t N = c->N;

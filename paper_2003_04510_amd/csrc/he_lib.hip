@@ -16,6 +16,7 @@
 #include "../../include/he_mi355x.h"
 #include "host_math.hpp"
 #include "ntt.hpp"
+#include "fused.hpp"
 #include "rns_kernels.hpp"
 
 using namespace he;
@@ -55,20 +56,29 @@ struct Blob {
   size_t add(const std::vector<T>& v) { return add(v.data(), v.size() * sizeof(T)); }
 };
 
+// One base-conversion job as planned on the host: sources src_off .. +ns,
+// targets dst_off .. +nt, constants C[s][t] at c_off, target moduli at m_off.
+struct ConvJob {
+  u32 src_off, ns, dst_off, nt, c_off, m_off;
+};
+
 struct LevelPlan {
   u32 beta = 0, dt_limbs = 0;
+  size_t o_mu_tg = 0, o_mu_c = 0, o_md_tg = 0, o_md_c = 0, o_y_mod = 0, o_y_scale = 0, o_s_mod = 0, o_s_scale = 0;
+  const ConvTarget* mu_tg = nullptr;  // mod-up targets [dt_limbs]
+  const u32* mu_c = nullptr;          // their constants (30-bit halves)
+  const ConvTarget* md_tg = nullptr;  // mod-down targets [level]
+  const u32* md_c = nullptr;
+  const u32* y_mod = nullptr;         // INTT list of d2 (+ d0, d1 of the last limb): [level + 2]
+  const u64* y_scale = nullptr;
+  const u32* s_mod = nullptr;         // INTT list of the special limbs (+ limb level-1): [K + 1]
+  const u64* s_scale = nullptr;
   u32 lo[8] = {}, cnt[8] = {}, dt_first[8] = {};
-  size_t o_modup_jobs = 0, o_modup_consts = 0, o_modup_tmods = 0, o_modup_scale = 0, o_dt_mod = 0,
-         o_emod = 0, o_md_job = 0, o_md_consts = 0, o_qlinv = 0, o_qlmod = 0;
+  size_t o_modup_scale = 0, o_dt_mod = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
   // resolved device pointers
-  const ConvJob* modup_jobs = nullptr;
-  const u64* modup_consts = nullptr;
-  const u32* modup_tmods = nullptr;
   const u64* modup_scale = nullptr;
   const u32* dt_mod = nullptr;
   const u32* emod = nullptr;
-  const ConvJob* md_job = nullptr;
-  const u64* md_consts = nullptr;
   const u64* qlinv = nullptr;
   const u64* qlmod = nullptr;
 };
@@ -84,7 +94,7 @@ struct he_ctx {
   uint8_t* blob = nullptr;     // device constant tables
   // device pointers into blob
   const ModInfo* mods = nullptr;
-  const u64 *tw = nullptr, *tws = nullptr, *itw = nullptr, *itws = nullptr;
+  const Tw2 *tw = nullptr, *itw = nullptr;
   const u32* iota = nullptr;
   const u64* spec_scale = nullptr;  // [K] pairs: N^-1 [(P/p_k)^-1]_{p_k}
   const u64* pinv = nullptr;        // [L] pairs: [P^-1]_{q_i}
@@ -139,26 +149,23 @@ void timed(const he_ctx* cc, const char* name, double ops, double bytes, hipStre
 // ---------------------------------------------------------------- NTT dispatch
 template <bool FWD, int LOGS>
 void launch_cols(const he_ctx* c, const NttArgs& a, u32 nlimbs, u32 npolys, hipStream_t st) {
-  constexpr int LOGR = 4;
-  constexpr int T = (1 << LOGS) >> LOGR;
-  constexpr int C = 256 / T;
+  using PG = PassGeo<LOGS>;
   const u32 ncols = 1u << (a.log_n - LOGS);
   const double units = (double)nlimbs * npolys;
   const double bfly = units * (double)(c->N / 2) * LOGS + (FWD ? 0.0 : units * (double)c->N);
   timed(c, FWD ? "ntt_cols" : "intt_cols", bfly, units * c->N * 16.0, st, [&] {
-    hipLaunchKernelGGL((k_ntt_cols<FWD, LOGS, LOGR, C>), dim3(ncols / C, nlimbs, npolys), dim3(T * C), 0, st, a);
+    hipLaunchKernelGGL((k_ntt_cols<FWD, LOGS>), dim3(ncols / PG::SUBS, nlimbs, npolys), dim3(PG::THREADS), 0, st,
+                       a);
   });
 }
 template <bool FWD, int LOGS>
 void launch_blocks(const he_ctx* c, const NttArgs& a, u32 nlimbs, u32 npolys, hipStream_t st) {
-  constexpr int LOGR = 4;
-  constexpr int T = (1 << LOGS) >> LOGR;
-  constexpr int B = 256 / T;
+  using PG = PassGeo<LOGS>;
   const u32 nblk = 1u << (a.log_n - LOGS);
   const double units = (double)nlimbs * npolys;
   timed(c, FWD ? "ntt_blocks" : "intt_blocks", units * (double)(c->N / 2) * LOGS, units * c->N * 16.0, st, [&] {
-    hipLaunchKernelGGL((k_ntt_blocks<FWD, LOGS, LOGR, B>), dim3(nblk / B, nlimbs, npolys), dim3(T * B), 0, st,
-                       a);
+    hipLaunchKernelGGL((k_ntt_blocks<FWD, LOGS>), dim3(nblk / PG::SUBS, nlimbs, npolys), dim3(PG::THREADS), 0,
+                       st, a);
   });
 }
 template <bool FWD>
@@ -192,7 +199,6 @@ void ntt_launch(const he_ctx* c, bool fwd, const u64* src, u64* dst, u64 src_str
   a.scale = scale;
   if (fwd) {
     a.tw = c->tw;
-    a.tws = c->tws;
     a.src = src; a.dst = dst; a.src_stride = src_stride; a.dst_stride = dst_stride;
     a.src_zstride = src_z; a.dst_zstride = dst_z;
     cols_dispatch<true>(c, n1, a, nlimbs, npolys, st);
@@ -200,7 +206,6 @@ void ntt_launch(const he_ctx* c, bool fwd, const u64* src, u64* dst, u64 src_str
     blocks_dispatch<true>(c, n2, a, nlimbs, npolys, st);
   } else {
     a.tw = c->itw;
-    a.tws = c->itws;
     a.src = src; a.dst = dst; a.src_stride = src_stride; a.dst_stride = dst_stride;
     a.src_zstride = src_z; a.dst_zstride = dst_z;
     blocks_dispatch<false>(c, n2, a, nlimbs, npolys, st);
@@ -320,8 +325,8 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     for (u32 j = 0; j < i; ++j)
       if (c->mod[j] == m) return fail(HE_EINVAL, "moduli must be distinct");
   }
-  if (c->alpha > CONV_MAX_SRC || K > CONV_MAX_SRC)
-    return fail(HE_EUNSUPPORTED, "digit size and K must be <= %d", CONV_MAX_SRC);
+  if (c->alpha > 15 || K > 15)
+    return fail(HE_EUNSUPPORTED, "digit size ceil(L/dnum) and K must be <= 15");
   // special primes must cover every digit: P > prod(digit)
   {
     long double lp = 0, ld = 0;
@@ -343,7 +348,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   for (u32 i = 0; i < nm; ++i) mi[i] = make_modinfo(c->mod[i], N);
   const size_t o_mods = B.add(mi);
   // twiddles: TB_W[k] = psi^bitrev(k), TB_invW[k] = psi^-bitrev(k), + Shoup companions
-  std::vector<u64> tw(nm * N), tws(nm * N), itw(nm * N), itws(nm * N);
+  std::vector<Tw2> tw(nm * N), itw(nm * N);
   for (u32 i = 0; i < nm; ++i) {
     const u64 m = c->mod[i];
     const u64 psi = min_root_2n(m, log_n), psii = invmod(psi, m);
@@ -352,13 +357,11 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     for (u64 k = 1; k < N; ++k) { pw[k] = mulmod(pw[k - 1], psi, m); ipw[k] = mulmod(ipw[k - 1], psii, m); }
     for (u64 k = 0; k < N; ++k) {
       const unsigned e = bitrev((unsigned)k, log_n);
-      tw[i * N + k] = pw[e];
-      tws[i * N + k] = shoup(pw[e], m);
-      itw[i * N + k] = ipw[e];
-      itws[i * N + k] = shoup(ipw[e], m);
+      tw[i * N + k] = {pw[e], shoup63(pw[e], m)};
+      itw[i * N + k] = {ipw[e], shoup63(ipw[e], m)};
     }
   }
-  const size_t o_tw = B.add(tw), o_tws = B.add(tws), o_itw = B.add(itw), o_itws = B.add(itws);
+  const size_t o_tw = B.add(tw), o_itw = B.add(itw);
   const size_t o_iota = B.add(all_idx);
   // ModDown constants (level independent)
   std::vector<u64> spec_scale(2 * K), pinv(2 * L), pm(nm);
@@ -429,10 +432,44 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
       qlinv[2 * i] = invmod(ql, m);
       qlinv[2 * i + 1] = shoup(qlinv[2 * i], m);
     }
-    P.o_modup_jobs = B.add(jobs); P.o_modup_consts = B.add(consts); P.o_modup_tmods = B.add(tmods);
+    // fused-kernel tables: conversion targets with 30-bit split constants
+    {
+      std::vector<ConvTarget> mtg;
+      std::vector<u32> mc;
+      for (u32 j = 0; j < P.beta; ++j) {
+        const ConvJob& J = jobs[j];
+        for (u32 t = 0; t < J.nt; ++t) {
+          mtg.push_back({J.src_off, J.ns, (u32)mc.size(), tmods[J.m_off + t]});
+          for (u32 s2 = 0; s2 < J.ns; ++s2) {
+            const u64 cv = consts[J.c_off + (size_t)s2 * J.nt + t];
+            mc.push_back((u32)(cv & M30));
+            mc.push_back((u32)(cv >> 30));
+          }
+        }
+      }
+      std::vector<ConvTarget> dtg;
+      std::vector<u32> dc;
+      for (u32 i = 0; i < lvl; ++i) {
+        dtg.push_back({lvl, K, (u32)dc.size(), i});
+        for (u32 k = 0; k < K; ++k) {
+          const u64 cv = mdc[(size_t)k * lvl + i];
+          dc.push_back((u32)(cv & M30));
+          dc.push_back((u32)(cv >> 30));
+        }
+      }
+      std::vector<u32> ymod(lvl + 2), smod(K + 1);
+      std::vector<u64> ysc(2 * (lvl + 2)), ssc(2 * (K + 1));
+      for (u32 i = 0; i < lvl; ++i) { ymod[i] = i; ysc[2 * i] = scale[2 * i]; ysc[2 * i + 1] = scale[2 * i + 1]; }
+      const u64 ql = q[lvl - 1], nql = invmod(N % ql, ql);
+      for (u32 k = 0; k < 2; ++k) { ymod[lvl + k] = lvl - 1; ysc[2 * (lvl + k)] = nql; ysc[2 * (lvl + k) + 1] = shoup(nql, ql); }
+      for (u32 k = 0; k < K; ++k) { smod[k] = L + k; ssc[2 * k] = spec_scale[2 * k]; ssc[2 * k + 1] = spec_scale[2 * k + 1]; }
+      smod[K] = lvl - 1; ssc[2 * K] = nql; ssc[2 * K + 1] = shoup(nql, ql);
+      P.o_mu_tg = B.add(mtg); P.o_mu_c = B.add(mc); P.o_md_tg = B.add(dtg); P.o_md_c = B.add(dc);
+      P.o_y_mod = B.add(ymod); P.o_y_scale = B.add(ysc); P.o_s_mod = B.add(smod); P.o_s_scale = B.add(ssc);
+    }
     P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_emod = B.add(emod);
-    P.o_md_job = B.add(&md, sizeof md); P.o_md_consts = B.add(mdc);
     P.o_qlinv = B.add(qlinv); P.o_qlmod = B.add(qlmod);
+    (void)md;
   }
 
   HIP_TRY(hipSetDevice(device));
@@ -446,23 +483,22 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   }
   uint8_t* b = c->blob;
   c->mods = (const ModInfo*)(b + o_mods);
-  c->tw = (const u64*)(b + o_tw); c->tws = (const u64*)(b + o_tws);
-  c->itw = (const u64*)(b + o_itw); c->itws = (const u64*)(b + o_itws);
+  c->tw = (const Tw2*)(b + o_tw);
+  c->itw = (const Tw2*)(b + o_itw);
   c->iota = (const u32*)(b + o_iota);
   c->spec_scale = (const u64*)(b + o_spec); c->pinv = (const u64*)(b + o_pinv);
   c->pmod = (const u64*)(b + o_pmod);
   for (u32 lvl = 1; lvl <= L; ++lvl) {
     LevelPlan& P = c->lv[lvl];
-    P.modup_jobs = (const ConvJob*)(b + P.o_modup_jobs);
-    P.modup_consts = (const u64*)(b + P.o_modup_consts);
-    P.modup_tmods = (const u32*)(b + P.o_modup_tmods);
     P.modup_scale = (const u64*)(b + P.o_modup_scale);
     P.dt_mod = (const u32*)(b + P.o_dt_mod);
     P.emod = (const u32*)(b + P.o_emod);
-    P.md_job = (const ConvJob*)(b + P.o_md_job);
-    P.md_consts = (const u64*)(b + P.o_md_consts);
     P.qlinv = (const u64*)(b + P.o_qlinv);
     P.qlmod = (const u64*)(b + P.o_qlmod);
+    P.mu_tg = (const ConvTarget*)(b + P.o_mu_tg); P.mu_c = (const u32*)(b + P.o_mu_c);
+    P.md_tg = (const ConvTarget*)(b + P.o_md_tg); P.md_c = (const u32*)(b + P.o_md_c);
+    P.y_mod = (const u32*)(b + P.o_y_mod); P.y_scale = (const u64*)(b + P.o_y_scale);
+    P.s_mod = (const u32*)(b + P.o_s_mod); P.s_scale = (const u64*)(b + P.o_s_scale);
   }
   *out = c.release();
   return HE_OK;
@@ -499,8 +535,8 @@ size_t he_pk_bytes(const he_ctx* c) { return c ? 2ull * c->L * c->N * 8 : 0; }
 
 static size_t mul_ws_limbs(const he_ctx* c, u32 level) {
   const LevelPlan& P = c->lv[level];
-  // D2, Y, DT, KS, Z, RL, RS
-  return (size_t)level + level + P.dt_limbs + 2 * (level + c->K) + 2 * level + 2 * level + 2;
+  // D2, Y (+2), DTp, KS (+1 per poly), Zp, ZL, RL
+  return (size_t)level + (level + 2) + P.dt_limbs + 2 * (level + c->K + 1) + 2 * level + 2 + 2 * level;
 }
 static size_t keygen_ws_limbs(const he_ctx* c) {
   // S, S2, E (over L+K) + staging for small vectors (dnum+2 int64 vectors)
@@ -526,36 +562,106 @@ he_status he_ntt(he_ctx* c, uint64_t* d, uint32_t nlimbs, uint32_t first_mod, in
   return HE_OK;
 }
 
-static he_status rescale_impl(he_ctx* c, u32 level, const u64* rl, u64* out, u64* rs, u64* s,
-                              hipStream_t st) {
-  const u64 N = c->N;
-  const LevelPlan& P = c->lv[level];
-  // r_u = INTT(c_u[level-1])  (2 polys, 1 limb)
-  ntt_launch(c, false, rl + (u64)(level - 1) * N, rs, N, N, (u64)level * N, N, c->iota + (level - 1),
-             nullptr, 1, 2, st);
-  const u64 tot = (u64)(level - 1) * N;
-  timed(c, "rescale_lift", 2.0 * tot, (2.0 * tot + 2.0 * N) * 8, st, [&] {
-    hipLaunchKernelGGL(k_rescale_lift, ew_grid(tot), dim3(EW_THREADS), 0, st, rs, s, P.qlmod, c->mods,
-                       level, c->mod[level - 1], c->log_n);
-  });
-  ntt_launch(c, true, s, s, N, N, tot, tot, c->iota, nullptr, level - 1, 2, st);
-  timed(c, "rescale_combine", 2.0 * tot, 6.0 * tot * 8, st, [&] {
-    hipLaunchKernelGGL(k_rescale_combine, ew_grid(tot), dim3(EW_THREADS), 0, st, rl, s, out, P.qlinv,
-                       c->mods, level, c->log_n);
-  });
-  HIP_TRY(hipGetLastError());
-  return HE_OK;
+}  // extern "C"
+
+// Fused pass launchers.  EPW: elements per workgroup (cols passes read 16
+// adjacent columns = 128-byte rows; blocks passes use smaller tiles).
+constexpr int EPW_COLS = 4096, EPW_BLOCKS = 2048;
+
+static unsigned pad8(u32 n) { return (n + 7u) & ~7u; }
+
+template <template <int, int> class Launch, class... A>
+static void by_logs(int logs, A&&... args) {
+  switch (logs) {
+    case 6: Launch<6, 0>::go(args...); break;
+    case 7: Launch<7, 0>::go(args...); break;
+    case 8: Launch<8, 0>::go(args...); break;
+    case 9: Launch<9, 0>::go(args...); break;
+  }
 }
 
-he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,
-                     size_t ws_bytes, he_stream stream) {
-  if (!c || !d_in || !d_out || !ws) return fail(HE_EINVAL, "he_rescale: null pointer");
-  if (level < 2 || level > c->L) return fail(HE_ELEVEL, "he_rescale: level %u not in [2, L]", level);
-  if (ws_bytes < (2 + 2 * (size_t)level) * c->N * 8) return fail(HE_ENOMEM, "he_rescale: workspace too small");
-  HIP_TRY(hipSetDevice(c->device));
-  u64* w = (u64*)ws;
-  return rescale_impl(c, level, d_in, d_out, w, w + 2 * c->N, (hipStream_t)stream);
+template <int LOGS, int>
+struct LTensor {
+  static void go(TensorArgs a, hipStream_t st) {
+    constexpr int EPW = EPW_BLOCKS;
+    a.nitems = (a.level << (a.log_n - LOGS)) / (EPW >> LOGS);
+    hipLaunchKernelGGL((k_tensor_intt<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
+  }
+};
+template <int LOGS, int>
+struct LConv {
+  static void go(ConvNttArgs a, u32 nz, hipStream_t st) {
+    constexpr int EPW = LOGS <= 8 ? EPW_COLS : EPW_BLOCKS;
+    a.nitems = nz * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS)) * a.ntarget;
+    hipLaunchKernelGGL((k_conv_ntt_cols<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
+  }
+};
+template <int LOGS, int>
+struct LIp {
+  static void go(IpArgs a, hipStream_t st) {
+    constexpr int EPW = EPW_BLOCKS;
+    a.nitems = (a.level + a.K) * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
+    hipLaunchKernelGGL((k_ntt_ip<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
+  }
+};
+template <int LOGS, int>
+struct LCombine {
+  static void go(CombineArgs a, hipStream_t st) {
+    constexpr int EPW = EPW_BLOCKS;
+    a.nitems = 2 * a.level * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
+    hipLaunchKernelGGL((k_ntt_combine<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
+  }
+};
+template <int LOGS, int>
+struct LLift {
+  static void go(LiftArgs a, hipStream_t st) {
+    constexpr int EPW = LOGS <= 8 ? EPW_COLS : EPW_BLOCKS;
+    a.nitems = 2 * (a.level - 1) * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
+    hipLaunchKernelGGL((k_lift_ntt_cols<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
+  }
+};
+template <int LOGS, int>
+struct LRescale {
+  static void go(RescaleArgs a, hipStream_t st) {
+    constexpr int EPW = EPW_BLOCKS;
+    a.nitems = 2 * (a.level - 1) * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
+    hipLaunchKernelGGL((k_ntt_rescale<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
+  }
+};
+
+// Inverse "cols" pass over a limb list (k_ntt_cols, per-limb scale).
+static void intt_cols(const he_ctx* c, u64* data, u64 stride, u64 zstride, const u32* limb_mod,
+                      const u64* scale, u32 nlimbs, u32 npolys, hipStream_t st) {
+  NttArgs a{};
+  a.src = data; a.dst = data; a.src_stride = stride; a.dst_stride = stride;
+  a.src_zstride = zstride; a.dst_zstride = zstride;
+  a.limb_mod = limb_mod; a.mods = c->mods; a.tw = c->itw; a.scale = scale; a.log_n = c->log_n;
+  cols_dispatch<false>(c, (int)c->log_n / 2, a, nlimbs, npolys, st);
 }
+
+// Rescale of rl [2][level][N] into out [2][level-1][N]: lift + NTT cols,
+// then NTT blocks + combine.  Either r (coefficient form of the dropped
+// limb, [2][N]) or (x01, ksx, zl) is given.
+static void rescale_fused(const he_ctx* c, u32 level, const u64* rl, u64* out, const u64* r, const u64* x01,
+                          const u64* ksx, u64 ksx_z, const u64* zl, u64* sp, hipStream_t st) {
+  const LevelPlan& P = c->lv[level];
+  const int n1 = (int)c->log_n / 2, n2 = (int)c->log_n - n1;
+  const u64 N = c->N, tot = (u64)(level - 1) * N;
+  LiftArgs la{};
+  la.r = r; la.x01 = x01; la.ksx = ksx; la.ksx_z = ksx_z; la.zl = zl; la.sp = sp; la.qlmod = P.qlmod;
+  la.mods = c->mods; la.tw = c->tw; la.level = level; la.log_n = c->log_n;
+  const u64 ql = c->mod[level - 1];
+  const u64 pinv = invmod(c->pmod_host[level - 1], ql);
+  la.pw = pinv; la.pws = shoup(pinv, ql);
+  timed(c, "lift_ntt_cols", 2.0 * tot / 2 * n1, 2.0 * tot * 8 + 6.0 * N * 8, st, [&] { by_logs<LLift>(n1, la, st); });
+  RescaleArgs ra{};
+  ra.sp = sp; ra.c = rl; ra.out = out; ra.qlinv = P.qlinv; ra.mods = c->mods; ra.tw = c->tw;
+  ra.level = level; ra.log_n = c->log_n;
+  timed(c, "ntt_rescale", 2.0 * tot / 2 * n2, 2.0 * tot * 8 * 3 + 2.0 * N * 8, st,
+        [&] { by_logs<LRescale>(n2, ra, st); });
+}
+
+extern "C" {
 
 he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t* ct2,
                  const uint64_t* evk, uint64_t* relin, uint64_t* out, void* ws, size_t ws_bytes,
@@ -578,58 +684,84 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
   hipStream_t st = (hipStream_t)stream;
   const LevelPlan& P = c->lv[level];
   const u32 K = c->K, ne = level + K;
+  const int n1 = (int)c->log_n / 2, n2 = (int)c->log_n - n1;
+  const bool rs = out != nullptr;
   u64* w = (u64*)ws;
-  u64* D2 = w;               w += (u64)level * N;
-  u64* Y = w;                w += (u64)level * N;
-  u64* DT = w;               w += (u64)P.dt_limbs * N;
-  u64* KS = w;               w += 2ull * ne * N;
-  u64* Z = w;                w += 2ull * level * N;
-  u64* RLw = w;              w += 2ull * level * N;
-  u64* RS = w;
-  u64* RL = relin ? relin : RLw;
+  u64* D2 = w;  w += (u64)level * N;
+  u64* Y = w;   w += (u64)(level + 2) * N;
+  u64* DT = w;  w += (u64)P.dt_limbs * N;
+  u64* KS = w;  w += 2ull * (ne + 1) * N;
+  u64* Z = w;   w += 2ull * level * N;
+  u64* ZL = w;  w += 2ull * N;
+  u64* RL = relin ? relin : w;
   const u64 tot = (u64)level * N;
+  const double hN = (double)N / 2;
 
-  // region 1: tensor product
-  timed(c, "tensor", 4.0 * tot, 7.0 * tot * 8, st, [&] {
-    hipLaunchKernelGGL(k_tensor, ew_grid(tot), dim3(EW_THREADS), 0, st, ct1, ct2, RL, D2, c->mods, level,
-                       c->log_n);
-  });
-  // ModUp: y_i = INTT(d2_i) * [(Qt_j/q_i)^-1]  (scale merged with N^-1)
-  ntt_launch(c, false, D2, Y, N, N, 0, 0, c->iota, P.modup_scale, level, 1, st);
+  // 1. tensor product + INTT blocks pass of d2 (and of d0, d1 of the last limb)
+  TensorArgs ta{};
+  ta.ct1 = ct1; ta.ct2 = ct2; ta.rl = RL; ta.d2o = D2; ta.yp = Y; ta.x01 = rs ? Y + tot : nullptr;
+  ta.mods = c->mods; ta.itw = c->itw; ta.level = level; ta.log_n = c->log_n;
+  timed(c, "tensor_intt", tot / 2.0 * n2 + 3.0 * tot, 8.0 * tot * 8, st, [&] { by_logs<LTensor>(n2, ta, st); });
+  // 2. INTT cols pass: y_i = INTT(d2_i) * [(Qt_j/q_i)^-1]
+  const u32 ny = level + (rs ? 2 : 0);
+  timed(c, "intt_cols", ny * (hN * n1 + N), 2.0 * ny * N * 8, st,
+        [&] { intt_cols(c, Y, N, 0, P.y_mod, P.y_scale, ny, 1, st); });
+  // 3. mod up: conversion + NTT cols pass of every converted limb
+  ConvNttArgs ca{};
+  ca.src = Y; ca.dst = DT; ca.src_z = 0; ca.dst_z = 0; ca.tg = P.mu_tg; ca.consts = P.mu_c; ca.mods = c->mods;
+  ca.tw = c->tw; ca.side = nullptr; ca.side_o = 0; ca.ntarget = P.dt_limbs; ca.log_n = c->log_n;
   {
-    double macs = 0, limbs = 0;
-    for (u32 j = 0; j < P.beta; ++j) {
-      macs += (double)P.cnt[j] * (ne - P.cnt[j]) * N;
-      limbs += P.cnt[j] + (ne - P.cnt[j]);
-    }
-    timed(c, "modup_convert", macs, limbs * N * 8, st, [&] {
-      hipLaunchKernelGGL(k_convert, dim3((unsigned)ceil_div(N, EW_THREADS), P.beta, 1), dim3(EW_THREADS), 0, st,
-                         Y, DT, P.modup_jobs, P.modup_consts, P.modup_tmods, c->mods, c->log_n, 0ull, 0ull);
-    });
+    double macs = 0;
+    for (u32 j = 0; j < P.beta; ++j) macs += (double)P.cnt[j] * (ne - P.cnt[j]) * N;
+    timed(c, "modup_ntt_cols", macs + P.dt_limbs * hN * n1, (level + P.dt_limbs) * (double)N * 8, st,
+          [&] { by_logs<LConv>(n1, ca, 1u, st); });
   }
-  ntt_launch(c, true, DT, DT, N, N, 0, 0, P.dt_mod, nullptr, P.dt_limbs, 1, st);
-  // inner product with evk
+  // 4. NTT blocks pass + evk inner product (+ INTT blocks pass of special limbs)
   IpArgs ia{};
-  ia.d2 = D2; ia.dt = DT; ia.evk = evk; ia.ks = KS; ia.mods = c->mods; ia.emod = P.emod;
+  ia.d2 = D2; ia.dtp = DT; ia.evk = evk; ia.ks = KS; ia.mods = c->mods; ia.tw = c->tw; ia.itw = c->itw;
+  ia.emod = P.emod;
   for (u32 j = 0; j < P.beta; ++j) { ia.dt_first[j] = P.dt_first[j]; ia.lo[j] = P.lo[j]; ia.cnt[j] = P.cnt[j]; }
-  ia.beta = P.beta; ia.level = level; ia.K = K; ia.L = c->L; ia.log_n = c->log_n;
-  timed(c, "inner_product", 2.0 * P.beta * ne * N, (3.0 * P.beta + 2) * ne * N * 8, st, [&] {
-    hipLaunchKernelGGL(k_inner_product, dim3((unsigned)ceil_div(N, EW_THREADS), ne), dim3(EW_THREADS), 0, st, ia);
-  });
-  // ModDown: y_k = INTT(ks special k) * [(P/p_k)^-1], z_i = conv, Z = NTT(z)
-  ntt_launch(c, false, KS + (u64)level * N, KS + (u64)level * N, N, N, (u64)ne * N, (u64)ne * N,
-             c->iota + c->L, c->spec_scale, K, 2, st);
-  timed(c, "moddown_convert", 2.0 * K * level * N, 2.0 * (K + level) * N * 8, st, [&] {
-    hipLaunchKernelGGL(k_convert, dim3((unsigned)ceil_div(N, EW_THREADS), 1, 2), dim3(EW_THREADS), 0, st,
-                       KS, Z, P.md_job, P.md_consts, c->iota, c->mods, c->log_n, (u64)ne * N, tot);
-  });
-  ntt_launch(c, true, Z, Z, N, N, tot, tot, c->iota, nullptr, level, 2, st);
-  timed(c, "moddown_combine", 2.0 * tot, 2.0 * 4 * tot * 8, st, [&] {
-    hipLaunchKernelGGL(k_moddown_combine, ew_grid(tot), dim3(EW_THREADS), 0, st, RL, KS, Z, c->pinv, c->mods,
-                       level, K, c->log_n);
-  });
+  ia.beta = P.beta; ia.level = level; ia.K = K; ia.L = c->L; ia.log_n = c->log_n; ia.extra_last = rs ? 1 : 0;
+  timed(c, "ntt_ip", P.dt_limbs * hN * n2 + 2.0 * P.beta * ne * N + (2.0 * K + (rs ? 2 : 0)) * hN * n2,
+        ((double)P.dt_limbs + 2.0 * P.beta * ne + 2.0 * ne) * N * 8, st, [&] { by_logs<LIp>(n2, ia, st); });
+  // 5. INTT cols pass of the special limbs (scaled by [(P/p_k)^-1]) and of limb level-1
+  const u32 nsl = K + (rs ? 1 : 0);
+  timed(c, "intt_cols", 2.0 * nsl * (hN * n1 + N), 4.0 * nsl * N * 8, st,
+        [&] { intt_cols(c, KS + (u64)level * N, N, (u64)(ne + 1) * N, P.s_mod, P.s_scale, nsl, 2, st); });
+  // 6. mod down: conversion + NTT cols pass
+  ConvNttArgs da{};
+  da.src = KS; da.dst = Z; da.src_z = (u64)(ne + 1) * N; da.dst_z = tot; da.tg = P.md_tg; da.consts = P.md_c;
+  da.mods = c->mods; da.tw = c->tw; da.side = rs ? ZL : nullptr; da.side_o = level - 1; da.ntarget = level;
+  da.log_n = c->log_n;
+  timed(c, "moddown_ntt_cols", 2.0 * K * tot + 2.0 * tot / 2 * n1, 2.0 * (K + level) * N * 8, st,
+        [&] { by_logs<LConv>(n1, da, 2u, st); });
+  // 7. NTT blocks pass + combine
+  CombineArgs cb{};
+  cb.zp = Z; cb.ks = KS; cb.rl = RL; cb.pinv = c->pinv; cb.mods = c->mods; cb.tw = c->tw; cb.level = level;
+  cb.K = K; cb.log_n = c->log_n;
+  timed(c, "ntt_combine", 2.0 * tot / 2 * n2 + 2.0 * tot, 2.0 * tot * 4 * 8, st,
+        [&] { by_logs<LCombine>(n2, cb, st); });
+  // 8-9. rescale
+  if (rs)
+    rescale_fused(c, level, RL, out, nullptr, Y + tot, KS + (u64)ne * N, (u64)(ne + 1) * N, ZL, Z, st);
   HIP_TRY(hipGetLastError());
-  if (out) return rescale_impl(c, level, RL, out, RS, Z, st);
+  return HE_OK;
+}
+
+he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,
+                     size_t ws_bytes, he_stream stream) {
+  if (!c || !d_in || !d_out || !ws) return fail(HE_EINVAL, "he_rescale: null pointer");
+  if (level < 2 || level > c->L) return fail(HE_ELEVEL, "he_rescale: level %u not in [2, L]", level);
+  if (ws_bytes < (2 + 2 * (size_t)level) * c->N * 8) return fail(HE_ENOMEM, "he_rescale: workspace too small");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const u64 N = c->N;
+  u64* R = (u64*)ws;
+  u64* S = R + 2 * N;
+  ntt_launch(c, false, d_in + (u64)(level - 1) * N, R, N, N, (u64)level * N, N, c->iota + (level - 1), nullptr, 1,
+             2, st);
+  rescale_fused(c, level, d_in, d_out, R, nullptr, nullptr, 0, nullptr, S, st);
+  HIP_TRY(hipGetLastError());
   return HE_OK;
 }
 

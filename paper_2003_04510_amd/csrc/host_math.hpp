@@ -16,6 +16,8 @@ u64 powmod(u64 a, u64 e, u64 m);
 inline u64 invmod(u64 a, u64 m) { return powmod(a % m, m - 2, m); }  // m prime
 // Shoup companion floor(w * 2^64 / m), w < m  (the paper's Y_Shoup, Algorithm 2)
 inline u64 shoup(u64 w, u64 m) { return (u64)(((u128)w << 64) / m); }
+// 2^63-scaled companion floor(w * 2^63 / m) used by the NTT butterflies
+inline u64 shoup63(u64 w, u64 m) { return (u64)(((u128)w << 63) / m); }
 bool is_prime(u64 n);
 // The `count` largest primes below 2^bits that are 1 mod 2N, scanning down.
 bool gen_primes(unsigned log_n, unsigned bits, unsigned count, const u64* excl, unsigned nexcl,

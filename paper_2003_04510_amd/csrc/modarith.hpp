@@ -18,6 +18,15 @@ namespace he {
 typedef uint64_t u64;
 typedef uint32_t u32;
 
+// Read-only table access through the constant address space: with a
+// uniform address this becomes a scalar load (scalar cache, lgkmcnt), so it
+// never waits behind outstanding vector-memory traffic.  Only for data that
+// no kernel writes while it runs (moduli, twiddles, conversion constants).
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+  return *(const __attribute__((address_space(4))) T*)p;
+}
+
 struct U128 {
   u64 lo, hi;
 };
@@ -83,6 +92,34 @@ __device__ __forceinline__ u64 reduce128(U128 x, const ModInfo& m) {
   u64 r = u + v;                                         // [0, 4q)
   r = csub(r, m.q << 1);
   return csub(r, m.q);
+}
+
+// Shoup multiplication with a 2^63-scaled companion ws = floor(w 2^63 / q),
+// valid for x < 2^62 and q < 2^61: returns x*w mod q in [0, 2q).
+// Built so every 64-bit intermediate fits: with x_hi < 2^30 and ws_hi < 2^31
+// the middle partial products chain through v_mad_u64_u32 addends without
+// overflow, and the remainder is formed as x*w + qhat*(2^64 - q) mod 2^64
+// (additions only).  nq = 2^64 - q.
+__device__ __forceinline__ u64 shoup63_lazy(u64 x, u64 w, u64 ws, u64 nq) {
+  const u32 xl = (u32)x, xh = (u32)(x >> 32), wsl = (u32)ws, wsh = (u32)(ws >> 32);
+  const u32 p = __umulhi(xl, wsl);
+  const u64 b = (u64)xh * wsl + p;
+  const u64 a = (u64)xl * wsh + b;
+  const u64 h = (u64)xh * wsh + (a >> 32);
+  // qhat = floor(x ws / 2^63) = (h : a_lo) >> 31
+  const u32 ql = __builtin_amdgcn_alignbit((u32)h, (u32)a, 31);
+  const u32 qh = __builtin_amdgcn_alignbit((u32)(h >> 32), (u32)h, 31);
+  const u32 wl = (u32)w, wh = (u32)(w >> 32), nql = (u32)nq, nqh = (u32)(nq >> 32);
+  u64 t = (u64)xl * wl;
+  t = (u64)ql * nql + t;
+  const u32 hi = (u32)(t >> 32) + xl * wh + xh * wl + ql * nqh + qh * nql;
+  return ((u64)hi << 32) | (u32)t;
+}
+
+// x - m if x >= m else x, for x, m < 2^63; negm = 2^64 - m.
+__device__ __forceinline__ u64 sub_if_ge(u64 x, u64 negm) {
+  const u64 t = x + negm;
+  return (int64_t)t < 0 ? x : t;
 }
 
 // canonical (a*b) mod q for a, b < q

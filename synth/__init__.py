@@ -16,7 +16,7 @@ import dataclasses
 
 import numpy as np
 
-SIGMA = 3.2          # Gaussian error width (Sec. II-A)
+SIGMA = 3.2          # Gaussian error width (Sec. III-A)
 TAIL = 6.0           # Gaussian tail cut in units of sigma
 
 
