@@ -113,6 +113,38 @@ he_status he_mul(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint6
                  const uint64_t* d_evk, uint64_t* d_relin, uint64_t* d_out, void* ws,
                  size_t ws_bytes, he_stream stream);
 
+/* Batched HE Mul: many independent products (each with its own level) of
+ * one context executed as one sequence of stage kernels, each kernel
+ * covering the work of every pair (the batch analogue of he_mul; the
+ * paper's GPU mapping spreads one function's independent work over the
+ * whole device, Sec. V-C).  Item i: level, operands ct1, ct2
+ * [2][level][N], outputs relin [2][level][N] (may be NULL) and out
+ * [2][level-1][N] (may be NULL, needs level >= 2); at least one output.
+ * Outputs must not alias inputs or each other's buffers.
+ *
+ * he_batch_workspace_bytes: workspace for the items (0 if a level is out of
+ * range).  he_batch_create: validates the items, lays out the workspace
+ * `ws` (device, caller-owned, must stay valid for the batch's lifetime) and
+ * uploads descriptors (device memory owned by the batch).  he_mul_batch:
+ * enqueues the batched HE Mul on `stream`; with use_graph != 0 the kernel
+ * sequence is captured once into a HIP graph (re-captured if evk changes)
+ * and replayed as a single launch.  The buffers named at creation are read
+ * and written at execution time, so new operand values may be written into
+ * them between calls.  he_batch_destroy frees the batch (not the buffers). */
+typedef struct he_batch he_batch;
+typedef struct he_batch_item {
+  uint32_t level;
+  const uint64_t* ct1;
+  const uint64_t* ct2;
+  uint64_t* relin;
+  uint64_t* out;
+} he_batch_item;
+size_t he_batch_workspace_bytes(const he_ctx* ctx, const he_batch_item* items, uint32_t n);
+he_status he_batch_create(he_ctx* ctx, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
+                          he_batch** out);
+he_status he_mul_batch(he_ctx* ctx, he_batch* batch, const uint64_t* d_evk, int use_graph, he_stream stream);
+void he_batch_destroy(he_batch* batch);
+
 /* Rescale (Sec. III-A, division by the last prime, rounded to nearest):
  * d_in [2][level][N] -> d_out [2][level-1][N].  level >= 2. */
 he_status he_rescale(he_ctx* ctx, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,

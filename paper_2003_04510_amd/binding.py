@@ -26,6 +26,10 @@ class HeError(RuntimeError):
     pass
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_uint32), ("ct1", vp), ("ct2", vp), ("relin", vp), ("out", vp)]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint32), ("ms", ctypes.c_double),
                 ("ops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -61,11 +65,18 @@ def load_library():
                               ctypes.POINTER(u32), u64p]
     L.he_timing_enable.argtypes = [vp, ctypes.c_int, ctypes.c_char_p]
     L.he_timing_read.argtypes = [vp, ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
+    L.he_batch_workspace_bytes.argtypes = [vp, ctypes.POINTER(BatchItem), u32]
+    L.he_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.he_batch_create.argtypes = [vp, ctypes.POINTER(BatchItem), u32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.he_mul_batch.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    L.he_batch_destroy.argtypes = [vp]
+    L.he_batch_destroy.restype = None
     L.he_status_str.argtypes = [st]
     L.he_status_str.restype = ctypes.c_char_p
     L.he_last_error.restype = ctypes.c_char_p
     for f in ("he_gen_primes", "he_ctx_create", "he_keygen", "he_encrypt", "he_decrypt", "he_mul",
-              "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read"):
+              "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read", "he_batch_create",
+              "he_mul_batch"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -252,9 +263,51 @@ class Context:
         return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].ops, arr[i].bytes)
                 for i in range(min(n.value, 64))}
 
+    def batch(self, items):
+        """A batched HE Mul over items = [(level, ct1, ct2, relin_or_None, out_or_None), ...]."""
+        return Batch(self, items)
+
     def ntt(self, data, first_mod: int, inverse: bool = False):
         """In-place transform of data [nlimbs][N]; limb r modulo modulus first_mod + r."""
         nl = data.numel() // self.N
         _check(load_library().he_ntt(self._h, vp(data.data_ptr()), nl, first_mod, int(inverse), self._stream()),
                "he_ntt")
         return data
+
+
+class Batch:
+    """Many HE Muls of one context as one sequence of batched stage kernels.
+    The workspace is allocated here (torch) and kept alive with the batch."""
+
+    def __init__(self, ctx: "Context", items):
+        L = load_library()
+        self.ctx = ctx
+        self.items = list(items)
+        arr = (BatchItem * len(self.items))()
+        for i, (level, ct1, ct2, relin, out) in enumerate(self.items):
+            arr[i] = BatchItem(level, ct1.data_ptr(), ct2.data_ptr(), relin.data_ptr() if relin is not None else None,
+                               out.data_ptr() if out is not None else None)
+        self._arr = arr
+        nbytes = int(L.he_batch_workspace_bytes(ctx._h, arr, len(self.items)))
+        if nbytes == 0:
+            raise HeError("he_batch_workspace_bytes: invalid items")
+        self.ws = ctx.empty((nbytes + 7) // 8)
+        h = vp()
+        _check(L.he_batch_create(ctx._h, arr, len(self.items), vp(self.ws.data_ptr()), self.ws.numel() * 8,
+                                 ctypes.byref(h)), "he_batch_create")
+        self._h = h
+
+    def run(self, evk, use_graph: bool = False):
+        _check(load_library().he_mul_batch(self.ctx._h, self._h, vp(evk.data_ptr()), int(use_graph),
+                                           self.ctx._stream()), "he_mul_batch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().he_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

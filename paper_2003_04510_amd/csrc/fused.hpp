@@ -1,20 +1,24 @@
-// Fused stage kernels of the full-RNS HE Mul.  Each kernel is one NTT pass
-// (ntt.hpp) with the element-wise work of the neighbouring HE Mul step done
-// in its prologue or epilogue, so that the step's operands make a single
-// trip through HBM:
+// Stage kernels of the full-RNS HE Mul, for one HE Mul or a batch of them.
+//
+// Most kernels are one NTT pass (ntt.hpp) with the element-wise work of the
+// neighbouring HE Mul step done in its prologue or epilogue, so that the
+// step's operands make a single trip through HBM:
 //
 //   k_tensor_intt      tensor product (Fig. 2 region 1) + INTT "blocks" pass of d2
-//   k_conv_ntt_cols    fast base conversion (mod up / mod down) + NTT "cols" pass
-//   k_ntt_ip           NTT "blocks" pass + evk inner product (+ INTT "blocks"
-//                      pass of the special limbs)
+//   k_list_cols        NTT / INTT "cols" pass over a limb list of a pair
+//   k_list_blocks      NTT / INTT "blocks" pass over a limb list of a pair
+//   k_conv             fast base conversion (mod up / mod down)
+//   k_ip               evk inner product (Fig. 2 region 2)
 //   k_ntt_combine      NTT "blocks" pass + mod-down combine
 //   k_lift_ntt_cols    rescale lift of the dropped limb + NTT "cols" pass
 //   k_ntt_rescale      NTT "blocks" pass + rescale combine
 //
-// Work items are tiles (a limb x a group of columns or blocks); grids are
-// padded to a multiple of 8 and items are handed out so that each XCD walks
-// a contiguous item range (items that share source tiles share that XCD's
-// L2).
+// Work items.  A launch covers the work items of every pair of a batch: the
+// items of pair p are [offs[p], offs[p+1]) (per-stage prefix sums built on
+// the host); a single HE Mul is a batch of one whose descriptor travels in
+// the kernel arguments.  Item counts per pair are given by stage_items();
+// kernels decode items in the same order.  Grids are padded to a multiple
+// of 8 and items are handed out so that each XCD walks a contiguous range.
 #pragma once
 #include "ntt.hpp"
 
@@ -22,20 +26,150 @@ namespace he {
 
 constexpr u64 M30 = (1ull << 30) - 1;
 
+// Workgroup tiles: "cols" passes 4096 elements (16 adjacent columns at
+// N = 2^16), "blocks" passes 2048 elements.
+constexpr int EPW_C = 4096, EPW_B = 2048;
+constexpr int CONV_CPT = 2, CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
+constexpr int IP_CPT = 2, IP_THREADS = 256;                        // inner product
+
 // Item index for workgroup `bid` of a grid of `grid` (grid % 8 == 0):
 // hardware places consecutive workgroups on consecutive XCDs, so XCD x
 // receives items [x * grid/8, (x+1) * grid/8).
 __device__ __forceinline__ u32 xcd_item(u32 bid, u32 grid) { return (bid & 7u) * (grid >> 3) + (bid >> 3); }
 
-// ---------------------------------------------------------------- base conversion
-// One conversion target: z = (sum_{s < ns} y_s * c_s) mod t, sources
-// y_s = src[src_off + s], constants c_s = {c0, c1} (30-bit halves) at
-// consts[c_off + 2 s].  All sources and constants are below 2^60 and
-// ns <= 15, so the four partial sums of 30x30-bit products stay below 2^64.
+// ---------------------------------------------------------------- tables
+// One base-conversion target: z = (sum_{s < ns} y_s * c_s) mod t with
+// sources y_s = limb src_off + s, constants c_s = {c0, c1} (30-bit halves)
+// at consts[c_off + 2 s], t = modulus mi.
 struct ConvTarget {
   u32 src_off, ns, c_off, mi;
 };
+// One conversion job (a digit for mod up, the special limbs for mod down):
+// targets tg[tg_off .. tg_off + nt) write limbs dst_off .. dst_off + nt.
+struct ConvJobDev {
+  u32 src_off, ns, dst_off, nt, tg_off, pad;
+};
 
+// Per-level plan (device-resident, built once per context).
+struct PlanDev {
+  const ConvJobDev* mu_jobs;  // [beta]
+  const ConvTarget* mu_tg;    // [dt_limbs]
+  const u32* mu_c;
+  const ConvJobDev* md_jobs;  // [1]
+  const ConvTarget* md_tg;    // [level]
+  const u32* md_c;
+  const u32* dt_mod;   // modulus of each mod-up limb [dt_limbs]
+  const u32* emod;     // modulus of extended-basis limb e [level + K]
+  const u32* y_mod;    // INTT list d2 (+ d0, d1 of limb level-1) [level + 2]
+  const u64* y_scale;  // Shoup pairs: N^-1 [(Qt_j/q_i)^-1]_{q_i}, N^-1
+  const u32* s_mod;    // INTT list of the special limbs (+ limb level-1) [K + 1]
+  const u64* s_scale;  // Shoup pairs: N^-1 [(P/p_k)^-1]_{p_k}, N^-1
+  const u64* qlinv;    // Shoup pairs [q_{level-1}^-1]_{q_i}, i < level-1
+  const u64* qlmod;    // q_{level-1} mod q_i
+  u64 pinv_l, pinv_ls; // [P^-1]_{q_{level-1}} and its Shoup companion
+  u32 level, beta, dt_limbs, pad;
+  u32 dt_first[8], lo[8], cnt[8];
+};
+
+// One HE Mul of a launch: operands, outputs, workspace, plan.
+//   ct1, ct2 [2][level][N]; rl [2][level][N] (relinearized, also d0/d1 scratch);
+//   out [2][level-1][N] or null; r: coefficient form of the dropped limb
+//   [2][N] (stand-alone rescale only, else null);
+//   workspace: d2 [level], y [level+2], dt [dt_limbs], ks [2][level+K+1],
+//   z [2][level], zc [2][level] (limbs of N words).
+struct PairDesc {
+  const u64 *ct1, *ct2;
+  u64 *rl, *out;
+  const u64* r;
+  u64 *d2, *y, *dt, *ks, *z, *zc;
+  const PlanDev* plan;
+  u32 level, rs;  // rs: rescale requested
+};
+
+// Per-launch constants.
+struct Common {
+  const ModInfo* mods;
+  const Tw2 *tw, *itw;
+  const u64* evk;   // [dnum][2][L+K][N]
+  const u64* pinv;  // Shoup pairs [P^-1]_{q_i}
+  const u32* iota;  // 0, 1, 2, ...
+  u32 L, K, log_n, pad;
+};
+
+// Which pairs a launch covers.
+struct Batch {
+  PairDesc one;            // the pair of a single HE Mul (pairs == null)
+  const PairDesc* pairs;   // device array [npairs] for a batch
+  const u32* offs;         // device array [npairs + 1]: item prefix of this stage
+  u32 npairs, nitems;
+};
+
+__device__ __forceinline__ PairDesc resolve(const Batch& b, u32 w, u32& local) {
+  if (!b.pairs) {
+    local = w;
+    return b.one;
+  }
+  u32 lo = 0, hi = b.npairs;  // offs[lo] <= w < offs[hi]
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (ldc(b.offs + mid) <= w) lo = mid;
+    else hi = mid;
+  }
+  local = uniform(w - ldc(b.offs + lo));
+  return ldc(b.pairs + lo);
+}
+
+// ---------------------------------------------------------------- stages
+enum Stage : int {
+  ST_TENSOR = 0,   // tensor + INTT blocks (d2; d0, d1 of limb level-1 when rescaling)
+  ST_Y_ICOLS,      // INTT cols of y
+  ST_MU_CONV,      // mod-up conversion
+  ST_DT_NCOLS,     // NTT cols of the mod-up limbs
+  ST_DT_NBLOCKS,   // NTT blocks of the mod-up limbs
+  ST_IP,           // inner product with evk
+  ST_KS_IBLOCKS,   // INTT blocks of the special limbs (+ limb level-1)
+  ST_KS_ICOLS,     // INTT cols of the special limbs (+ limb level-1)
+  ST_MD_CONV,      // mod-down conversion
+  ST_Z_NCOLS,      // NTT cols of z
+  ST_COMBINE,      // NTT blocks of z + combine
+  ST_LIFT,         // rescale lift + NTT cols
+  ST_RESCALE,      // NTT blocks + rescale combine
+  ST_COUNT
+};
+
+// Tiles per limb of a cols / blocks pass at ring degree 2^log_n.
+__host__ __device__ constexpr u32 cols_tiles(u32 log_n) {
+  return (1u << (log_n - log_n / 2)) / (u32)(EPW_C >> (log_n / 2));
+}
+__host__ __device__ constexpr u32 blocks_tiles(u32 log_n) {
+  return (1u << (log_n / 2)) / (u32)(EPW_B >> (log_n - log_n / 2));
+}
+
+// Work items of one pair in a stage.
+inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_limbs, bool rs) {
+  const u32 tc = cols_tiles(log_n), tb = blocks_tiles(log_n);
+  const u32 chunks_c = (1u << log_n) / (CONV_THREADS * CONV_CPT);
+  const u32 chunks_i = (1u << log_n) / (IP_THREADS * IP_CPT);
+  const u32 ex = rs ? 1 : 0;
+  switch (st) {
+    case ST_TENSOR: return (level + 2 * ex) * tb;
+    case ST_Y_ICOLS: return (level + 2 * ex) * tc;
+    case ST_MU_CONV: return beta * CONV_GROUPS * chunks_c;
+    case ST_DT_NCOLS: return dt_limbs * tc;
+    case ST_DT_NBLOCKS: return dt_limbs * tb;
+    case ST_IP: return (level + K) * chunks_i;
+    case ST_KS_IBLOCKS: return 2 * (K + ex) * tb;
+    case ST_KS_ICOLS: return 2 * (K + ex) * tc;
+    case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_c;
+    case ST_Z_NCOLS: return 2 * level * tc;
+    case ST_COMBINE: return 2 * level * tb;
+    case ST_LIFT: return rs ? 2 * (level - 1) * tc : 0;
+    case ST_RESCALE: return rs ? 2 * (level - 1) * tb : 0;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------- base conversion helpers
 __device__ __forceinline__ u64 conv_finish(u64 sll, u64 slh, u64 shl, u64 shh, const ModInfo& m) {
   const u64 mid = slh + shl;
   const u64 cm = mid < slh ? 1 : 0;
@@ -51,22 +185,13 @@ __device__ __forceinline__ u64 conv_finish(u64 sll, u64 slh, u64 shl, u64 shh, c
   return reduce128(x, m);
 }
 
-// ---------------------------------------------------------------- K1
-// Tensor product + first INTT pass ("blocks") of d2.
-// Items: limb i < level, block tile.  Writes d0, d1 to rl[0], rl[1], d2 (NTT
-// form) to d2o, and the blocks-pass output of d2 to yp[i].  With x01 != null
-// the items of limb level-1 also run the blocks pass on d0 and d1 and write
-// it to x01[0], x01[1] (used to rescale without a second INTT later).
-struct TensorArgs {
-  const u64 *ct1, *ct2;
-  u64 *rl, *d2o, *yp, *x01;
-  const ModInfo* mods;
-  const Tw2* itw;
-  u32 level, log_n, nitems;
-};
-
+// ---------------------------------------------------------------- tensor + INTT blocks
+// Items (limb r, block tile).  r < level: limb r; stores d0, d1 into rl,
+// d2 (NTT form) into d2, and the INTT blocks pass of d2 into y[r].
+// r = level + u (rescale only): recomputes d_u of limb level-1 and writes
+// its INTT blocks pass to y[level + u] (used to rescale by linearity).
 template <int LOGS, int EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(TensorArgs a) {
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
@@ -74,254 +199,313 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(TensorA
   constexpr int FIRST = Gm::NR - 1;
   __shared__ u64 lds[PL::SUBS * Gm::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= a.nitems) return;
-  const int n1 = a.log_n - LOGS;
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
-  const u32 i = w / tpl, pos = w % tpl;
-  const u64 N = 1ull << a.log_n, tot = (u64)a.level << a.log_n;
-  const ModInfo m = a.mods[i];
+  const u32 r = uniform(local / tpl), pos = uniform(local % tpl);
+  const u32 i = r < pd.level ? r : pd.level - 1;
+  const u32 which = r < pd.level ? 2 : r - pd.level;
+  const u64 tot = (u64)pd.level << c.log_n;
+  const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS;
-  const u64 off = ((u64)i << a.log_n) + (blk0 << LOGS);
+  const u64 off = ((u64)i << c.log_n) + (blk0 << LOGS);
   const int sub = PL::sub(), tt = PL::tt();
-  const bool extra = a.x01 && i == a.level - 1;
-  u64 d0v[Gm::R], d1v[Gm::R];
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) {
     const u64 idx = off + threadIdx.x + k * THREADS;
-    const u64 b1 = a.ct1[idx], a1 = a.ct1[tot + idx], b2 = a.ct2[idx], a2 = a.ct2[tot + idx];
-    d0v[k] = barrett(mul_wide(b1, b2), m);
-    U128 s = mul_wide(a1, b2);
-    add_to(s, mul_wide(a2, b1));
-    d1v[k] = barrett(s, m);
-    const u64 d2 = barrett(mul_wide(a1, a2), m);
-    a.rl[idx] = d0v[k];
-    a.rl[tot + idx] = d1v[k];
-    a.d2o[idx] = d2;
+    const u64 b1 = pd.ct1[idx], a1 = pd.ct1[tot + idx], b2 = pd.ct2[idx], a2 = pd.ct2[tot + idx];
+    u64 v;
+    if (which == 2) {
+      const u64 d0 = barrett(mul_wide(b1, b2), m);
+      U128 s1 = mul_wide(a1, b2);
+      add_to(s1, mul_wide(a2, b1));
+      const u64 d1 = barrett(s1, m);
+      v = barrett(mul_wide(a1, a2), m);
+      pd.rl[idx] = d0;
+      pd.rl[tot + idx] = d1;
+      pd.d2[idx] = v;
+    } else if (which == 0) {
+      v = barrett(mul_wide(b1, b2), m);
+    } else {
+      U128 s1 = mul_wide(a1, b2);
+      add_to(s1, mul_wide(a2, b1));
+      v = barrett(s1, m);
+    }
     const int e = threadIdx.x + k * THREADS;
-    lds[(e >> LOGS) * Gm::SUB + Gm::pad(e & (Gm::S - 1))] = d2;
+    lds[(e >> LOGS) * Gm::SUB + Gm::pad(e & (Gm::S - 1))] = v;
   }
   __syncthreads();
-  const Tw2* tw = a.itw + ((u64)i << a.log_n);
-  const u64 base = (1ull << n1) + blk0 + sub;
+  u64* out = pd.y + ((u64)r << c.log_n) + (blk0 << LOGS) + ((u64)sub << LOGS);
   u64* tile = lds + sub * Gm::SUB;
-  {
-    u64* out = a.yp + off + ((u64)sub << LOGS);
-    u64 x[Gm::R];
-    lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
-    sub_transform_regs<false, LOGS, LOGR, false>(x, tile, tt, tw, base, m.q,
-                                                  [&](int e, u64 v) { out[e] = csub(v, m.q); });
-  }
-  if (!extra) return;
-#pragma unroll 1
-  for (int u = 0; u < 2; ++u) {
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < Gm::R; ++k) {
-      const int e = threadIdx.x + k * THREADS;
-      lds[(e >> LOGS) * Gm::SUB + Gm::pad(e & (Gm::S - 1))] = u ? d1v[k] : d0v[k];
-    }
-    __syncthreads();
-    u64* out = a.x01 + (u64)u * N + (blk0 << LOGS) + ((u64)sub << LOGS);
-    u64 x[Gm::R];
-    lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
-    sub_transform_regs<false, LOGS, LOGR, false>(x, tile, tt, tw, base, m.q,
-                                                  [&](int e, u64 v) { out[e] = csub(v, m.q); });
-  }
+  u64 x[Gm::R];
+  lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
+  sub_transform_regs<false, LOGS, LOGR, false>(x, tile, tt, c.itw + ((u64)i << c.log_n), (1ull << n1) + blk0 + sub,
+                                                m.q, [&](int e, u64 v) { out[e] = csub(v, m.q); });
 }
 
-// ---------------------------------------------------------------- K3 / K6
-// Base conversion + forward NTT "cols" pass.
-// Items: (z, column tile, target o), o fastest.  Target o reads sources
-// src + z*src_z + (t.src_off + s) N and writes dst + z*dst_z + o N.  When
-// side != null, target side_o also stores its coefficient-form value to
-// side + z*N.
-struct ConvNttArgs {
+// ---------------------------------------------------------------- NTT passes over limb lists
+struct ListView {
   const u64* src;
   u64* dst;
-  u64 src_z, dst_z;
-  const ConvTarget* tg;
-  const u32* consts;
-  const ModInfo* mods;
-  const Tw2* tw;
-  u64* side;
-  u32 side_o, ntarget, log_n, nitems;
+  u64 zs, zd;  // polynomial strides
+  const u32* limb_mod;
+  const u64* scale;  // inverse cols pass: per-limb Shoup pairs (null: N^-1)
+  u32 nl, np;
 };
 
-template <int LOGS, int EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_conv_ntt_cols(ConvNttArgs a) {
+template <int ST>
+__device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& pd) {
+  const PlanDev* P = pd.plan;
+  const u64 N = 1ull << c.log_n;
+  const u32 ex = pd.rs ? 1 : 0;
+  ListView v{};
+  if constexpr (ST == ST_Y_ICOLS) {
+    v.src = pd.y; v.dst = pd.y; v.nl = pd.level + 2 * ex; v.np = 1;
+    v.limb_mod = ldc(&P->y_mod); v.scale = ldc(&P->y_scale);
+  } else if constexpr (ST == ST_DT_NCOLS || ST == ST_DT_NBLOCKS) {
+    v.src = pd.dt; v.dst = pd.dt; v.nl = ldc(&P->dt_limbs); v.np = 1;
+    v.limb_mod = ldc(&P->dt_mod); v.scale = nullptr;
+  } else if constexpr (ST == ST_KS_IBLOCKS || ST == ST_KS_ICOLS) {
+    const u64 ne = pd.level + c.K;
+    v.src = pd.ks + ((u64)pd.level << c.log_n); v.dst = pd.ks + ((u64)pd.level << c.log_n);
+    v.zs = v.zd = (ne + 1) * N; v.nl = c.K + ex; v.np = 2;
+    v.limb_mod = ldc(&P->s_mod); v.scale = ldc(&P->s_scale);
+  } else {  // ST_Z_NCOLS
+    v.src = pd.zc; v.dst = pd.z; v.zs = v.zd = (u64)pd.level * N; v.nl = pd.level; v.np = 2;
+    v.limb_mod = c.iota; v.scale = nullptr;
+  }
+  return v;
+}
+
+template <bool FWD, int LOGS, int EPW, int ST>
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
-  using RF = RoundShape<LOGS, LOGR, 0>;
+  constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
+  using RF = RoundShape<LOGS, LOGR, FIRST>;
   __shared__ u64 lds[PL::SUBS * Gm::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= a.nitems) return;
-  const int n2 = a.log_n - LOGS;
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const ListView v = list_view<ST>(c, pd);
+  const int n2 = c.log_n - LOGS;
   const u32 tpc = (1u << n2) / PL::SUBS;
-  const u32 o = w % a.ntarget, rest = w / a.ntarget;
-  const u32 pos = rest % tpc, z = rest / tpc;
-  const ConvTarget T = a.tg[o];
-  const ModInfo m = a.mods[T.mi];
+  const u32 pos = uniform(local % tpc), rest = local / tpc;
+  const u32 limb = uniform(rest % v.nl), z = uniform(rest / v.nl);
+  const u32 mi = ldc(v.limb_mod + limb);
+  const u64 q = ldc(&c.mods[mi].q);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 col = (u64)pos * PL::SUBS + sub;
-  const u64* src = a.src + (u64)z * a.src_z + ((u64)T.src_off << a.log_n) + col;
-  const u32* C = a.consts + T.c_off;
+  const u64* in = v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + col;
+  u64* out = v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + col;
+  u64 sw = ldc(&c.mods[mi].ninv), sws = ldc(&c.mods[mi].ninvs);
+  if (!FWD && v.scale) {
+    sw = ldc(v.scale + 2 * (u64)limb);
+    sws = ldc(v.scale + 2 * (u64)limb + 1);
+  }
   u64 x[Gm::R];
 #pragma unroll
-  for (int u = 0; u < RF::NG; ++u) {
+  for (int u = 0; u < RF::NG; ++u)
 #pragma unroll
-    for (int i = 0; i < RF::G; ++i) {
-      const u64 e = (u64)RF::elem(tt, u, i) << n2;
-      u64 sll = 0, slh = 0, shl = 0, shh = 0;
+    for (int i = 0; i < RF::G; ++i) x[u * RF::G + i] = in[(u64)RF::elem(tt, u, i) << n2];
+  sub_transform_regs<FWD, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n), 1,
+                                             q, [&](int e, u64 val) {
+                                               out[(u64)e << n2] =
+                                                   FWD ? ntt_canon<true>(val, q) : csub(shoup_lazy(val, sw, sws, q), q);
+                                             });
+}
+
+// Blocks pass; the side whose register layout is thread-contiguous
+// (forward output, inverse input) goes through LDS so global accesses stay
+// coalesced.
+template <bool FWD, int LOGS, int EPW, int ST>
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common c, Batch b) {
+  constexpr int LOGR = Radix<LOGS>::LOGR;
+  using Gm = Geo<LOGS, LOGR>;
+  using PL = PassLayout<LOGS, false, EPW>;
+  constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
+  constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
+  using RF = RoundShape<LOGS, LOGR, FIRST>;
+  __shared__ u64 lds[PL::SUBS * Gm::SUB];
+  const u32 w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const ListView v = list_view<ST>(c, pd);
+  const int n1 = c.log_n - LOGS;
+  const u32 tpl = (1u << n1) / PL::SUBS;
+  const u32 pos = uniform(local % tpl), rest = local / tpl;
+  const u32 limb = uniform(rest % v.nl), z = uniform(rest / v.nl);
+  const u32 mi = ldc(v.limb_mod + limb);
+  const u64 q = ldc(&c.mods[mi].q);
+  const int sub = PL::sub(), tt = PL::tt();
+  const u64 blk0 = (u64)pos * PL::SUBS;
+  const u64* in0 = v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + (blk0 << LOGS);
+  u64* out0 = v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + (blk0 << LOGS);
+  u64* tile = lds + sub * Gm::SUB;
+  u64 x[Gm::R];
+  if constexpr (!FWD) {
 #pragma unroll
-      for (int s = 0; s < 15; ++s) {
-        if (s >= (int)T.ns) break;
-        const u64 y = src[((u64)s << a.log_n) + e];
-        const u32 y0 = (u32)(y & M30), y1 = (u32)(y >> 30);
-        const u32 c0 = C[2 * s], c1 = C[2 * s + 1];
-        sll += (u64)y0 * c0;
-        slh += (u64)y0 * c1;
-        shl += (u64)y1 * c0;
-        shh += (u64)y1 * c1;
-      }
-      x[u * RF::G + i] = conv_finish(sll, slh, shl, shh, m);
+    for (int k = 0; k < Gm::R; ++k) {
+      const int idx = threadIdx.x + k * THREADS;
+      lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))] = in0[idx];
     }
-  }
-  if (a.side && o == a.side_o) {
-    u64* sd = a.side + ((u64)z << a.log_n) + col;
+    __syncthreads();
+    lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
+  } else {
+    const u64* in = in0 + ((u64)sub << LOGS);
 #pragma unroll
     for (int u = 0; u < RF::NG; ++u)
 #pragma unroll
-      for (int i = 0; i < RF::G; ++i) sd[(u64)RF::elem(tt, u, i) << n2] = x[u * RF::G + i];
+      for (int i = 0; i < RF::G; ++i) x[u * RF::G + i] = in[RF::elem(tt, u, i)];
   }
-  u64* out = a.dst + (u64)z * a.dst_z + ((u64)o << a.log_n) + col;
-  sub_transform_regs<true, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, a.tw + ((u64)T.mi << a.log_n), 1, m.q,
-                                               [&](int e, u64 v) { out[(u64)e << n2] = ntt_canon<true>(v, m.q); });
+  u64* out = out0 + ((u64)sub << LOGS);
+  sub_transform_regs<FWD, LOGS, LOGR, FWD>(x, tile, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
+                                           (1ull << n1) + blk0 + sub, q,
+                                           [&](int e, u64 val) { out[e] = ntt_canon<FWD>(val, q); });
+  if constexpr (FWD) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) {
+      const int idx = threadIdx.x + k * THREADS;
+      out0[idx] = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], q);
+    }
+  }
 }
 
-// ---------------------------------------------------------------- K4
-// Forward NTT "blocks" pass of every mod-up limb of target e, evk inner
-// product over the digits, and (special limbs, or limb level-1 when x != 0)
-// the INTT "blocks" pass of the two accumulators.
-// Items: (block tile, e) with e fastest.  ks layout [2][level+K+1][N]:
-// limbs < level hold ks_u in NTT form; limbs level..level+K-1 the INTT
-// blocks-pass output of the special limbs; limb level+K that of limb level-1.
-struct IpArgs {
-  const u64* d2;      // [level][N] NTT form
-  const u64* dtp;     // cols-pass output of the mod-up limbs (compact)
-  const u64* evk;     // [dnum][2][L+K][N]
-  u64* ks;
-  const ModInfo* mods;
-  const Tw2 *tw, *itw;
-  const u32* emod;
-  u32 dt_first[8], lo[8], cnt[8];
-  u32 beta, level, K, L, log_n, nitems, extra_last;
-};
-
-template <int LOGS, int EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_ip(IpArgs a) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
-  using Gm = Geo<LOGS, LOGR>;
-  using PL = PassLayout<LOGS, false, EPW>;
-  constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
-  using RF = RoundShape<LOGS, LOGR, 0>;
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
+// ---------------------------------------------------------------- base conversion
+// Fast base conversion (the matrix form of the paper's iCRT, Algorithm 6,
+// with its delayed modulo): a thread owns CONV_CPT consecutive
+// coefficients, loads each source residue once (split into 30-bit halves),
+// then loops over a group of targets, accumulating four 64-bit sums of
+// 30x30-bit products (no carries for up to 15 sources) and reducing once.
+// Mod up: sources y, outputs dt (jobs = digits).  Mod down: sources the
+// special limbs of ks (coefficient form), outputs zc, one job per polynomial.
+// Items (job or polynomial, target group, coefficient chunk).
+template <bool MD>
+__global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= a.nitems) return;
-  const u32 ne = a.level + a.K;
-  const int n1 = a.log_n - LOGS;
-  const u32 e = w % ne, pos = w / ne;
-  const u32 mi = a.emod[e];
-  const ModInfo m = a.mods[mi];
-  const u64 blk0 = (u64)pos * ((u32)PL::SUBS);
-  const u64 toff = blk0 << LOGS;  // tile offset inside a limb
-  const int sub = PL::sub(), tt = PL::tt();
-  u64* tile = lds + sub * Gm::SUB;
-  const u64 base = (1ull << n1) + blk0 + sub;
-  const u64 nm = a.L + a.K;
-  u64 accb[Gm::R], acca[Gm::R];
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const PlanDev* P = pd.plan;
+  const u32 nch = (1u << c.log_n) / (CONV_THREADS * CONV_CPT);
+  const u32 chunk = uniform(local % nch), rest = local / nch;
+  const u32 grp = uniform(rest % CONV_GROUPS), jz = uniform(rest / CONV_GROUPS);
+  const ConvJobDev J = ldc((MD ? ldc(&P->md_jobs) : ldc(&P->mu_jobs)) + (MD ? 0 : jz));
+  const ConvTarget* tg = MD ? ldc(&P->md_tg) : ldc(&P->mu_tg);
+  const u32* consts = MD ? ldc(&P->md_c) : ldc(&P->mu_c);
+  const u64 N = 1ull << c.log_n;
+  const u64 ne1 = pd.level + c.K + 1;
+  const u64* src = MD ? pd.ks + (u64)jz * ne1 * N : pd.y;
+  u64* dst = MD ? pd.zc + (u64)jz * pd.level * N : pd.dt;
+  const u32 per = (J.nt + CONV_GROUPS - 1) / CONV_GROUPS;
+  const u32 t0 = grp * per, t1 = min(J.nt, t0 + per);
+  const u64 n0 = ((u64)chunk * CONV_THREADS + threadIdx.x) * CONV_CPT;
+  const u64* s0 = src + ((u64)J.src_off << c.log_n) + n0;
+  u32 y0[15][CONV_CPT], y1[15][CONV_CPT];
 #pragma unroll
-  for (int k = 0; k < Gm::R; ++k) accb[k] = acca[k] = 0;
-#pragma unroll 1
-  for (u32 j = 0; j < a.beta; ++j) {
-    u64 x[Gm::R];
-    if (e < a.level && e >= a.lo[j] && e < a.lo[j] + a.cnt[j]) {
-      const u64* p = a.d2 + ((u64)e << a.log_n) + toff;
+  for (int s = 0; s < 15; ++s) {
+    if (s < (int)J.ns) {
 #pragma unroll
-      for (int k = 0; k < Gm::R; ++k) x[k] = p[threadIdx.x + k * THREADS];
-    } else {
-      const u32 o = e < a.lo[j] ? e : e - a.cnt[j];
-      const u64* p = a.dtp + ((u64)(a.dt_first[j] + o) << a.log_n) + toff + ((u64)sub << LOGS);
-#pragma unroll
-      for (int u = 0; u < RF::NG; ++u)
-#pragma unroll
-        for (int i = 0; i < RF::G; ++i) x[u * RF::G + i] = p[RF::elem(tt, u, i)];
-      sub_transform_regs<true, LOGS, LOGR, true>(x, tile, tt, a.tw + ((u64)mi << a.log_n), base, m.q,
-                                                 [](int, u64) {});
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < Gm::R; ++k) {
-        const int idx = threadIdx.x + k * THREADS;
-        x[k] = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], m.q);
+      for (int k = 0; k < CONV_CPT; ++k) {
+        const u64 y = s0[((u64)s << c.log_n) + k];
+        y0[s][k] = (u32)(y & M30);
+        y1[s][k] = (u32)(y >> 30);
       }
-      __syncthreads();
-    }
-    const u64* eb = a.evk + ((((u64)j * 2) * nm + mi) << a.log_n) + toff;
-    const u64* ea = eb + (nm << a.log_n);
-#pragma unroll
-    for (int k = 0; k < Gm::R; ++k) {
-      const int idx = threadIdx.x + k * THREADS;
-      accb[k] = addmod(accb[k], mulmod(x[k], eb[idx], m), m.q);
-      acca[k] = addmod(acca[k], mulmod(x[k], ea[idx], m), m.q);
     }
   }
-  const u64 kz = (u64)(ne + 1) << a.log_n;  // poly stride of ks
-  const bool special = e >= a.level, last = a.extra_last && e == a.level - 1;
-  if (!special) {
-    u64* ob = a.ks + ((u64)e << a.log_n) + toff;
+  for (u32 t = t0; t < t1; ++t) {
+    const ConvTarget T = ldc(tg + J.tg_off + t);
+    const ModInfo m = ldc(c.mods + T.mi);
+    const u32* C = consts + T.c_off;
+    u64 sll[CONV_CPT], slh[CONV_CPT], shl[CONV_CPT], shh[CONV_CPT];
 #pragma unroll
-    for (int k = 0; k < Gm::R; ++k) {
-      const int idx = threadIdx.x + k * THREADS;
-      ob[idx] = accb[k];
-      ob[kz + idx] = acca[k];
-    }
-  }
-  if (!special && !last) return;
-  const u32 dst_limb = special ? e : ne;
-  const Tw2* itw = a.itw + ((u64)mi << a.log_n);
-#pragma unroll 1
-  for (int u = 0; u < 2; ++u) {
+    for (int k = 0; k < CONV_CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
 #pragma unroll
-    for (int k = 0; k < Gm::R; ++k) {
-      const int idx = threadIdx.x + k * THREADS;
-      lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))] = u ? acca[k] : accb[k];
+    for (int s = 0; s < 15; ++s) {
+      if (s < (int)J.ns) {
+        const u32 c0 = ldc(C + 2 * s), c1 = ldc(C + 2 * s + 1);
+#pragma unroll
+        for (int k = 0; k < CONV_CPT; ++k) {
+          sll[k] += (u64)y0[s][k] * c0;
+          slh[k] += (u64)y0[s][k] * c1;
+          shl[k] += (u64)y1[s][k] * c0;
+          shh[k] += (u64)y1[s][k] * c1;
+        }
+      }
     }
-    __syncthreads();
-    u64 x[Gm::R];
-    lds_get<LOGS, LOGR, Gm::NR - 1>(tile, x, tt);
-    u64* out = a.ks + u * kz + ((u64)dst_limb << a.log_n) + toff + ((u64)sub << LOGS);
-    sub_transform_regs<false, LOGS, LOGR, false>(x, tile, tt, itw, base, m.q,
-                                                  [&](int ee, u64 v) { out[ee] = csub(v, m.q); });
-    __syncthreads();
+    u64* o = dst + ((u64)(J.dst_off + t) << c.log_n) + n0;
+#pragma unroll
+    for (int k = 0; k < CONV_CPT; ++k) o[k] = conv_finish(sll[k], slh[k], shl[k], shh[k], m);
   }
 }
 
-// ---------------------------------------------------------------- K7
-// Forward NTT "blocks" pass of z_u[i] and the mod-down combine
-// rl_u[i] = rl_u[i] + (ks_u[i] - Z_u[i]) * [P^-1]_{q_i} (rl holds d_u).
-// Items: (u, i, block tile), tile fastest.
-struct CombineArgs {
-  const u64* zp;   // [2][level][N] cols-pass output
-  const u64* ks;   // [2][level+K+1][N]
-  u64* rl;         // [2][level][N]
-  const u64* pinv; // Shoup pairs per q_i
-  const ModInfo* mods;
-  const Tw2* tw;
-  u32 level, K, log_n, nitems;
-};
+// ---------------------------------------------------------------- inner product
+// ks_u[e] = sum_j dt_j[e] * evk_j.u[e] for every limb e of the extended basis;
+// dt_j[e] = d2[e] when q_e is in digit j, else the NTT-form mod-up limb.
+// When rescaling, the NTT-form ks_u[level-1] is also copied to limb
+// level+K (it is inverse-transformed with the special limbs).
+// Items (e, coefficient chunk).
+__global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
+  const u32 w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const PlanDev* P = pd.plan;
+  const u32 nch = (1u << c.log_n) / (IP_THREADS * IP_CPT);
+  const u32 chunk = uniform(local % nch), e = uniform(local / nch);
+  const u64 n0 = ((u64)chunk * IP_THREADS + threadIdx.x) * IP_CPT;
+  const u32 mi = ldc(ldc(&P->emod) + e);
+  const ModInfo m = ldc(c.mods + mi);
+  const u64 nm = c.L + c.K;
+  const u32 beta = ldc(&P->beta);
+  U128 accb[IP_CPT], acca[IP_CPT];
+#pragma unroll
+  for (int k = 0; k < IP_CPT; ++k) accb[k] = acca[k] = U128{0, 0};
+  for (u32 j = 0; j < beta; ++j) {
+    const u32 lo = ldc(&P->lo[j]), cnt = ldc(&P->cnt[j]);
+    const u64* x;
+    if (e < pd.level && e >= lo && e < lo + cnt) {
+      x = pd.d2 + ((u64)e << c.log_n);
+    } else {
+      const u32 o = e < lo ? e : e - cnt;
+      x = pd.dt + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n);
+    }
+    const u64* eb = c.evk + ((((u64)j * 2) * nm + mi) << c.log_n);
+    const u64* ea = eb + (nm << c.log_n);
+#pragma unroll
+    for (int k = 0; k < IP_CPT; ++k) {
+      const u64 xv = x[n0 + k];
+      add_to(accb[k], mul_wide(xv, eb[n0 + k]));
+      add_to(acca[k], mul_wide(xv, ea[n0 + k]));
+    }
+  }
+  const u64 kz = (u64)(pd.level + c.K + 1) << c.log_n;
+  u64* ob = pd.ks + ((u64)e << c.log_n) + n0;
+  const bool last = pd.rs && e == pd.level - 1;
+  u64* xb = pd.ks + ((u64)(pd.level + c.K) << c.log_n) + n0;
+#pragma unroll
+  for (int k = 0; k < IP_CPT; ++k) {
+    const u64 vb = barrett(accb[k], m), va = barrett(acca[k], m);
+    ob[k] = vb;
+    ob[kz + k] = va;
+    if (last) {
+      xb[k] = vb;
+      xb[kz + k] = va;
+    }
+  }
+}
 
+// ---------------------------------------------------------------- NTT blocks + combine
+// rl_u[i] = rl_u[i] + (ks_u[i] - NTT(z_u[i])) * [P^-1]_{q_i}  (rl holds d_u).
+// Items (u, i, block tile), tile fastest.
 template <int LOGS, int EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(CombineArgs a) {
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
@@ -329,25 +513,28 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Combine
   using RF = RoundShape<LOGS, LOGR, 0>;
   __shared__ u64 lds[PL::SUBS * Gm::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= a.nitems) return;
-  const int n1 = a.log_n - LOGS;
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
-  const u32 pos = w % tpl, ui = w / tpl, i = ui % a.level, u = ui / a.level;
-  const ModInfo m = a.mods[i];
+  const u32 pos = uniform(local % tpl), ui = local / tpl;
+  const u32 i = uniform(ui % pd.level), u = uniform(ui / pd.level);
+  const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   u64 x[Gm::R];
-  const u64* p = a.zp + ((u64)(u * a.level + i) << a.log_n) + toff + ((u64)sub << LOGS);
+  const u64* p = pd.z + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS);
 #pragma unroll
   for (int uu = 0; uu < RF::NG; ++uu)
 #pragma unroll
     for (int ii = 0; ii < RF::G; ++ii) x[uu * RF::G + ii] = p[RF::elem(tt, uu, ii)];
-  sub_transform_regs<true, LOGS, LOGR, true>(x, lds + sub * Gm::SUB, tt, a.tw + ((u64)i << a.log_n),
+  sub_transform_regs<true, LOGS, LOGR, true>(x, lds + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
                                              (1ull << n1) + blk0 + sub, m.q, [](int, u64) {});
   __syncthreads();
-  const u64 pw = a.pinv[2 * i], pws = a.pinv[2 * i + 1];
-  const u64* ksu = a.ks + ((u64)(u * (a.level + a.K + 1) + i) << a.log_n) + toff;
-  u64* rlu = a.rl + ((u64)(u * a.level + i) << a.log_n) + toff;
+  const u64 pw = ldc(c.pinv + 2 * i), pws = ldc(c.pinv + 2 * i + 1);
+  const u64* ksu = pd.ks + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff;
+  u64* rlu = pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff;
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) {
     const int idx = threadIdx.x + k * THREADS;
@@ -357,42 +544,41 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Combine
   }
 }
 
-// ---------------------------------------------------------------- K8
-// Rescale lift + forward NTT "cols" pass.  The dropped limb in coefficient
-// form is either given (r != null: r[u]) or assembled as
-//   r_u = x01_u + (ksx_u - zl_u) * [P^-1]_{q_l}  (mod q_l),
-// i.e. INTT of rl_u[level-1] by linearity.  Then s = centered(r) mod q_i.
-// Items: (u, column tile, i < level-1), i fastest.
-struct LiftArgs {
-  const u64 *r, *x01, *ksx, *zl;
-  u64 ksx_z;        // poly stride of ksx
-  u64* sp;          // [2][level-1][N]
-  const u64* qlmod; // [level-1]: q_l mod q_i
-  const ModInfo* mods;
-  const Tw2* tw;
-  u64 pw, pws;      // [P^-1]_{q_l} Shoup pair
-  u32 level, log_n, nitems;
-};
-
+// ---------------------------------------------------------------- rescale lift + NTT cols
+// The dropped limb in coefficient form is pd.r (stand-alone rescale) or is
+// assembled by linearity of the INTT:
+//   r_u = INTT(d_u[l-1]) + (INTT(ks_u[l-1]) - z_u[l-1]) * [P^-1]_{q_{l-1}},
+// with INTT(d_u[l-1]) = y[level + u], INTT(ks_u[l-1]) = ks_u[level + K],
+// z_u[l-1] = zc_u[level - 1].  Then s = centered(r) mod q_i.
+// Items (u, column tile, i < level-1), i fastest.
 template <int LOGS, int EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(LiftArgs a) {
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
   using RF = RoundShape<LOGS, LOGR, 0>;
   __shared__ u64 lds[PL::SUBS * Gm::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= a.nitems) return;
-  const int n2 = a.log_n - LOGS;
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const PlanDev* P = pd.plan;
+  const int n2 = c.log_n - LOGS;
   const u32 tpc = (1u << n2) / PL::SUBS;
-  const u32 nl = a.level - 1;
-  const u32 i = w % nl, rest = w / nl, pos = rest % tpc, u = rest / tpc;
-  const ModInfo m = a.mods[i];
-  const u64 ql = a.mods[nl].q;
-  const u64 qlm = a.qlmod[i];
+  const u32 nl = pd.level - 1;
+  const u32 i = uniform(local % nl), rest = local / nl;
+  const u32 pos = uniform(rest % tpc), u = uniform(rest / tpc);
+  const ModInfo m = ldc(c.mods + i);
+  const u64 ql = ldc(&c.mods[nl].q);
+  const u64 qlm = ldc(ldc(&P->qlmod) + i);
+  const u64 pw = ldc(&P->pinv_l), pws = ldc(&P->pinv_ls);
   const int sub = PL::sub(), tt = PL::tt();
+  const u64 N = 1ull << c.log_n;
   const u64 col = (u64)pos * PL::SUBS + sub;
-  const u64 uoff = ((u64)u << a.log_n) + col;
+  const u64* rr = pd.r ? pd.r + (u64)u * N + col : nullptr;
+  const u64* dd = pd.y + ((u64)(pd.level + u) << c.log_n) + col;
+  const u64* kk = pd.ks + ((u64)u * (pd.level + c.K + 1) + pd.level + c.K) * N + col;
+  const u64* zz = pd.zc + ((u64)u * pd.level + pd.level - 1) * N + col;
   u64 x[Gm::R];
 #pragma unroll
   for (int uu = 0; uu < RF::NG; ++uu) {
@@ -400,39 +586,26 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(LiftA
     for (int ii = 0; ii < RF::G; ++ii) {
       const u64 e = (u64)RF::elem(tt, uu, ii) << n2;
       u64 r;
-      if (a.r) {
-        r = a.r[uoff + e];
+      if (rr) {
+        r = rr[e];
       } else {
-        const u64 d = a.x01[uoff + e];
-        const u64 k = a.ksx[(u64)u * a.ksx_z + col + e];
-        const u64 zz = a.zl[uoff + e];
-        r = csub(d + csub(shoup_lazy(k + ql - zz, a.pw, a.pws, ql), ql), ql);
+        r = csub(dd[e] + csub(shoup_lazy(kk[e] + ql - zz[e], pw, pws, ql), ql), ql);
       }
       u64 v = csub(r - mulhi(r, m.one_s) * m.q, m.q);  // r mod q_i
       if (2 * r >= ql) v = submod(v, qlm, m.q);
       x[uu * RF::G + ii] = v;
     }
   }
-  u64* out = a.sp + ((u64)(u * nl + i) << a.log_n) + col;
-  sub_transform_regs<true, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, a.tw + ((u64)i << a.log_n), 1, m.q,
+  u64* out = pd.z + ((u64)(u * nl + i) << c.log_n) + col;
+  sub_transform_regs<true, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n), 1, m.q,
                                                [&](int e, u64 v) { out[(u64)e << n2] = ntt_canon<true>(v, m.q); });
 }
 
-// ---------------------------------------------------------------- K9
-// Forward NTT "blocks" pass of s_u[i] and out_u[i] = (c_u[i] - S) * [q_l^-1]_{q_i}.
-// Items: (u, i < level-1, block tile), tile fastest.
-struct RescaleArgs {
-  const u64* sp;   // [2][level-1][N]
-  const u64* c;    // [2][level][N]
-  u64* out;        // [2][level-1][N]
-  const u64* qlinv;
-  const ModInfo* mods;
-  const Tw2* tw;
-  u32 level, log_n, nitems;
-};
-
+// ---------------------------------------------------------------- NTT blocks + rescale combine
+// out_u[i] = (rl_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}; s lives in z.
+// Items (u, i < level-1, block tile), tile fastest.
 template <int LOGS, int EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(RescaleArgs a) {
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
@@ -440,26 +613,31 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Rescale
   using RF = RoundShape<LOGS, LOGR, 0>;
   __shared__ u64 lds[PL::SUBS * Gm::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= a.nitems) return;
-  const int n1 = a.log_n - LOGS;
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const PlanDev* P = pd.plan;
+  const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
-  const u32 nl = a.level - 1;
-  const u32 pos = w % tpl, ui = w / tpl, i = ui % nl, u = ui / nl;
-  const ModInfo m = a.mods[i];
+  const u32 nl = pd.level - 1;
+  const u32 pos = uniform(local % tpl), ui = local / tpl;
+  const u32 i = uniform(ui % nl), u = uniform(ui / nl);
+  const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   u64 x[Gm::R];
-  const u64* p = a.sp + ((u64)(u * nl + i) << a.log_n) + toff + ((u64)sub << LOGS);
+  const u64* p = pd.z + ((u64)(u * nl + i) << c.log_n) + toff + ((u64)sub << LOGS);
 #pragma unroll
   for (int uu = 0; uu < RF::NG; ++uu)
 #pragma unroll
     for (int ii = 0; ii < RF::G; ++ii) x[uu * RF::G + ii] = p[RF::elem(tt, uu, ii)];
-  sub_transform_regs<true, LOGS, LOGR, true>(x, lds + sub * Gm::SUB, tt, a.tw + ((u64)i << a.log_n),
+  sub_transform_regs<true, LOGS, LOGR, true>(x, lds + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
                                              (1ull << n1) + blk0 + sub, m.q, [](int, u64) {});
   __syncthreads();
-  const u64 qw = a.qlinv[2 * i], qws = a.qlinv[2 * i + 1];
-  const u64* cu = a.c + ((u64)(u * a.level + i) << a.log_n) + toff;
-  u64* ou = a.out + ((u64)(u * nl + i) << a.log_n) + toff;
+  const u64* ql = ldc(&P->qlinv);
+  const u64 qw = ldc(ql + 2 * i), qws = ldc(ql + 2 * i + 1);
+  const u64* cu = pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff;
+  u64* ou = pd.out + ((u64)(u * nl + i) << c.log_n) + toff;
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) {
     const int idx = threadIdx.x + k * THREADS;

@@ -73,6 +73,9 @@ struct LevelPlan {
   const u64* y_scale = nullptr;
   const u32* s_mod = nullptr;         // INTT list of the special limbs (+ limb level-1): [K + 1]
   const u64* s_scale = nullptr;
+  size_t o_mu_jobs = 0, o_md_jobs = 0;
+  const ConvJobDev* mu_jobs = nullptr;  // [beta]
+  const ConvJobDev* md_jobs = nullptr;  // [1]
   u32 lo[8] = {}, cnt[8] = {}, dt_first[8] = {};
   size_t o_modup_scale = 0, o_dt_mod = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
   // resolved device pointers
@@ -81,6 +84,9 @@ struct LevelPlan {
   const u32* emod = nullptr;
   const u64* qlinv = nullptr;
   const u64* qlmod = nullptr;
+  size_t o_plan = 0;
+  const PlanDev* plan = nullptr;  // device copy of this level's plan
+  u64 pinv_l = 0;                 // [P^-1]_{q_{level-1}}
 };
 
 }  // namespace
@@ -464,16 +470,42 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
       for (u32 k = 0; k < 2; ++k) { ymod[lvl + k] = lvl - 1; ysc[2 * (lvl + k)] = nql; ysc[2 * (lvl + k) + 1] = shoup(nql, ql); }
       for (u32 k = 0; k < K; ++k) { smod[k] = L + k; ssc[2 * k] = spec_scale[2 * k]; ssc[2 * k + 1] = spec_scale[2 * k + 1]; }
       smod[K] = lvl - 1; ssc[2 * K] = nql; ssc[2 * K + 1] = shoup(nql, ql);
+      std::vector<ConvJobDev> mj(P.beta), dj(1);
+      for (u32 j = 0; j < P.beta; ++j) mj[j] = {jobs[j].src_off, jobs[j].ns, jobs[j].dst_off, jobs[j].nt, jobs[j].dst_off, 0};
+      dj[0] = {lvl, K, 0, lvl, 0, 0};
+      P.o_mu_jobs = B.add(mj); P.o_md_jobs = B.add(dj);
       P.o_mu_tg = B.add(mtg); P.o_mu_c = B.add(mc); P.o_md_tg = B.add(dtg); P.o_md_c = B.add(dc);
       P.o_y_mod = B.add(ymod); P.o_y_scale = B.add(ysc); P.o_s_mod = B.add(smod); P.o_s_scale = B.add(ssc);
     }
     P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_emod = B.add(emod);
     P.o_qlinv = B.add(qlinv); P.o_qlmod = B.add(qlmod);
+    {
+      PlanDev placeholder{};
+      P.o_plan = B.add(&placeholder, sizeof placeholder);
+    }
+    P.pinv_l = invmod(pm[lvl - 1], q[lvl - 1]);
     (void)md;
   }
 
   HIP_TRY(hipSetDevice(device));
   HIP_TRY(hipMalloc(&c->blob, B.bytes.size()));
+  for (u32 lvl = 1; lvl <= L; ++lvl) {
+    LevelPlan& P = c->lv[lvl];
+    uint8_t* d = c->blob;
+    PlanDev pd{};
+    pd.mu_jobs = (const ConvJobDev*)(d + P.o_mu_jobs); pd.mu_tg = (const ConvTarget*)(d + P.o_mu_tg);
+    pd.mu_c = (const u32*)(d + P.o_mu_c);
+    pd.md_jobs = (const ConvJobDev*)(d + P.o_md_jobs); pd.md_tg = (const ConvTarget*)(d + P.o_md_tg);
+    pd.md_c = (const u32*)(d + P.o_md_c);
+    pd.dt_mod = (const u32*)(d + P.o_dt_mod); pd.emod = (const u32*)(d + P.o_emod);
+    pd.y_mod = (const u32*)(d + P.o_y_mod); pd.y_scale = (const u64*)(d + P.o_y_scale);
+    pd.s_mod = (const u32*)(d + P.o_s_mod); pd.s_scale = (const u64*)(d + P.o_s_scale);
+    pd.qlinv = (const u64*)(d + P.o_qlinv); pd.qlmod = (const u64*)(d + P.o_qlmod);
+    pd.pinv_l = P.pinv_l; pd.pinv_ls = shoup(P.pinv_l, q[lvl - 1]);
+    pd.level = lvl; pd.beta = P.beta; pd.dt_limbs = P.dt_limbs;
+    for (u32 j = 0; j < 8; ++j) { pd.dt_first[j] = P.dt_first[j]; pd.lo[j] = P.lo[j]; pd.cnt[j] = P.cnt[j]; }
+    memcpy(B.bytes.data() + P.o_plan, &pd, sizeof pd);
+  }
   {
     hipError_t e = hipMemcpy(c->blob, B.bytes.data(), B.bytes.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -499,6 +531,8 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     P.md_tg = (const ConvTarget*)(b + P.o_md_tg); P.md_c = (const u32*)(b + P.o_md_c);
     P.y_mod = (const u32*)(b + P.o_y_mod); P.y_scale = (const u64*)(b + P.o_y_scale);
     P.s_mod = (const u32*)(b + P.o_s_mod); P.s_scale = (const u64*)(b + P.o_s_scale);
+    P.mu_jobs = (const ConvJobDev*)(b + P.o_mu_jobs); P.md_jobs = (const ConvJobDev*)(b + P.o_md_jobs);
+    P.plan = (const PlanDev*)(b + P.o_plan);
   }
   *out = c.release();
   return HE_OK;
@@ -535,8 +569,8 @@ size_t he_pk_bytes(const he_ctx* c) { return c ? 2ull * c->L * c->N * 8 : 0; }
 
 static size_t mul_ws_limbs(const he_ctx* c, u32 level) {
   const LevelPlan& P = c->lv[level];
-  // D2, Y (+2), DTp, KS (+1 per poly), Zp, ZL, RL
-  return (size_t)level + (level + 2) + P.dt_limbs + 2 * (level + c->K + 1) + 2 * level + 2 + 2 * level;
+  // D2, Y (+2), DT, KS (+1 per poly), Zp, Zc, RL
+  return (size_t)level + (level + 2) + P.dt_limbs + 2 * (level + c->K + 1) + 2 * level + 2 * level + 2 * level;
 }
 static size_t keygen_ws_limbs(const he_ctx* c) {
   // S, S2, E (over L+K) + staging for small vectors (dnum+2 int64 vectors)
@@ -564,102 +598,133 @@ he_status he_ntt(he_ctx* c, uint64_t* d, uint32_t nlimbs, uint32_t first_mod, in
 
 }  // extern "C"
 
-// Fused pass launchers.  EPW: elements per workgroup (cols passes read 16
-// adjacent columns = 128-byte rows; blocks passes use smaller tiles).
-constexpr int EPW_COLS = 4096, EPW_BLOCKS = 2048;
+// ---------------------------------------------------------------- stage launches
+namespace {
 
-static unsigned pad8(u32 n) { return (n + 7u) & ~7u; }
+unsigned pad8(u32 n) { return (n + 7u) & ~7u; }
 
-template <template <int, int> class Launch, class... A>
-static void by_logs(int logs, A&&... args) {
-  switch (logs) {
-    case 6: Launch<6, 0>::go(args...); break;
-    case 7: Launch<7, 0>::go(args...); break;
-    case 8: Launch<8, 0>::go(args...); break;
-    case 9: Launch<9, 0>::go(args...); break;
+template <int LOGS, int EPW>
+void launch_tensor(const Common& c, const Batch& b, hipStream_t st) {
+  hipLaunchKernelGGL((k_tensor_intt<LOGS, EPW>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, c, b);
+}
+template <bool FWD, int LOGS, int ST>
+void launch_lcols(const Common& c, const Batch& b, hipStream_t st) {
+  hipLaunchKernelGGL((k_list_cols<FWD, LOGS, EPW_C, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW_C)), 0,
+                     st, c, b);
+}
+template <bool FWD, int LOGS, int ST>
+void launch_lblocks(const Common& c, const Batch& b, hipStream_t st) {
+  hipLaunchKernelGGL((k_list_blocks<FWD, LOGS, EPW_B, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW_B)), 0,
+                     st, c, b);
+}
+
+// n1 = log_n / 2 (cols passes), n2 = log_n - n1 (blocks passes)
+template <int N1, int N2>
+void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) {
+  switch (stage) {
+    case ST_TENSOR: launch_tensor<N2, EPW_B>(c, b, st); break;
+    case ST_Y_ICOLS: launch_lcols<false, N1, ST_Y_ICOLS>(c, b, st); break;
+    case ST_MU_CONV:
+      hipLaunchKernelGGL(k_conv<false>, dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b);
+      break;
+    case ST_DT_NCOLS: launch_lcols<true, N1, ST_DT_NCOLS>(c, b, st); break;
+    case ST_DT_NBLOCKS: launch_lblocks<true, N2, ST_DT_NBLOCKS>(c, b, st); break;
+    case ST_IP: hipLaunchKernelGGL(k_ip, dim3(pad8(b.nitems)), dim3(IP_THREADS), 0, st, c, b); break;
+    case ST_KS_IBLOCKS: launch_lblocks<false, N2, ST_KS_IBLOCKS>(c, b, st); break;
+    case ST_KS_ICOLS: launch_lcols<false, N1, ST_KS_ICOLS>(c, b, st); break;
+    case ST_MD_CONV:
+      hipLaunchKernelGGL(k_conv<true>, dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b);
+      break;
+    case ST_Z_NCOLS: launch_lcols<true, N1, ST_Z_NCOLS>(c, b, st); break;
+    case ST_COMBINE:
+      hipLaunchKernelGGL((k_ntt_combine<N2, EPW_B>), dim3(pad8(b.nitems)), dim3(pass_threads(N2, EPW_B)), 0, st, c,
+                         b);
+      break;
+    case ST_LIFT:
+      hipLaunchKernelGGL((k_lift_ntt_cols<N1, EPW_C>), dim3(pad8(b.nitems)), dim3(pass_threads(N1, EPW_C)), 0, st,
+                         c, b);
+      break;
+    case ST_RESCALE:
+      hipLaunchKernelGGL((k_ntt_rescale<N2, EPW_B>), dim3(pad8(b.nitems)), dim3(pass_threads(N2, EPW_B)), 0, st, c,
+                         b);
+      break;
   }
 }
 
-template <int LOGS, int>
-struct LTensor {
-  static void go(TensorArgs a, hipStream_t st) {
-    constexpr int EPW = EPW_BLOCKS;
-    a.nitems = (a.level << (a.log_n - LOGS)) / (EPW >> LOGS);
-    hipLaunchKernelGGL((k_tensor_intt<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
-  }
-};
-template <int LOGS, int>
-struct LConv {
-  static void go(ConvNttArgs a, u32 nz, hipStream_t st) {
-    constexpr int EPW = LOGS <= 8 ? EPW_COLS : EPW_BLOCKS;
-    a.nitems = nz * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS)) * a.ntarget;
-    hipLaunchKernelGGL((k_conv_ntt_cols<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
-  }
-};
-template <int LOGS, int>
-struct LIp {
-  static void go(IpArgs a, hipStream_t st) {
-    constexpr int EPW = EPW_BLOCKS;
-    a.nitems = (a.level + a.K) * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
-    hipLaunchKernelGGL((k_ntt_ip<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
-  }
-};
-template <int LOGS, int>
-struct LCombine {
-  static void go(CombineArgs a, hipStream_t st) {
-    constexpr int EPW = EPW_BLOCKS;
-    a.nitems = 2 * a.level * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
-    hipLaunchKernelGGL((k_ntt_combine<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
-  }
-};
-template <int LOGS, int>
-struct LLift {
-  static void go(LiftArgs a, hipStream_t st) {
-    constexpr int EPW = LOGS <= 8 ? EPW_COLS : EPW_BLOCKS;
-    a.nitems = 2 * (a.level - 1) * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
-    hipLaunchKernelGGL((k_lift_ntt_cols<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
-  }
-};
-template <int LOGS, int>
-struct LRescale {
-  static void go(RescaleArgs a, hipStream_t st) {
-    constexpr int EPW = EPW_BLOCKS;
-    a.nitems = 2 * (a.level - 1) * ((1u << (a.log_n - LOGS)) / (EPW >> LOGS));
-    hipLaunchKernelGGL((k_ntt_rescale<LOGS, EPW>), dim3(pad8(a.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, a);
-  }
-};
-
-// Inverse "cols" pass over a limb list (k_ntt_cols, per-limb scale).
-static void intt_cols(const he_ctx* c, u64* data, u64 stride, u64 zstride, const u32* limb_mod,
-                      const u64* scale, u32 nlimbs, u32 npolys, hipStream_t st) {
-  NttArgs a{};
-  a.src = data; a.dst = data; a.src_stride = stride; a.dst_stride = stride;
-  a.src_zstride = zstride; a.dst_zstride = zstride;
-  a.limb_mod = limb_mod; a.mods = c->mods; a.tw = c->itw; a.scale = scale; a.log_n = c->log_n;
-  cols_dispatch<false>(c, (int)c->log_n / 2, a, nlimbs, npolys, st);
+const char* stage_name(int s) {
+  static const char* names[ST_COUNT] = {"tensor_intt", "y_intt_cols", "modup_convert", "modup_ntt_cols",
+                                        "modup_ntt_blocks", "inner_product", "special_intt_blocks",
+                                        "special_intt_cols", "moddown_convert", "moddown_ntt_cols", "ntt_combine",
+                                        "lift_ntt_cols", "ntt_rescale"};
+  return names[s];
 }
 
-// Rescale of rl [2][level][N] into out [2][level-1][N]: lift + NTT cols,
-// then NTT blocks + combine.  Either r (coefficient form of the dropped
-// limb, [2][N]) or (x01, ksx, zl) is given.
-static void rescale_fused(const he_ctx* c, u32 level, const u64* rl, u64* out, const u64* r, const u64* x01,
-                          const u64* ksx, u64 ksx_z, const u64* zl, u64* sp, hipStream_t st) {
+// Algorithmic work of one pair in a stage: (ops, bytes).  ops are
+// butterflies for NTT passes (+N per limb for the inverse cols scaling),
+// 64x64 multiply-accumulates for conversion and inner product, modular
+// products for the element-wise parts; bytes are limbs read + written x 8N.
+void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double& bytes) {
   const LevelPlan& P = c->lv[level];
+  const double N = (double)c->N, hN = N / 2, K = c->K, l = level, ex = rs ? 1 : 0;
   const int n1 = (int)c->log_n / 2, n2 = (int)c->log_n - n1;
-  const u64 N = c->N, tot = (u64)(level - 1) * N;
-  LiftArgs la{};
-  la.r = r; la.x01 = x01; la.ksx = ksx; la.ksx_z = ksx_z; la.zl = zl; la.sp = sp; la.qlmod = P.qlmod;
-  la.mods = c->mods; la.tw = c->tw; la.level = level; la.log_n = c->log_n;
-  const u64 ql = c->mod[level - 1];
-  const u64 pinv = invmod(c->pmod_host[level - 1], ql);
-  la.pw = pinv; la.pws = shoup(pinv, ql);
-  timed(c, "lift_ntt_cols", 2.0 * tot / 2 * n1, 2.0 * tot * 8 + 6.0 * N * 8, st, [&] { by_logs<LLift>(n1, la, st); });
-  RescaleArgs ra{};
-  ra.sp = sp; ra.c = rl; ra.out = out; ra.qlinv = P.qlinv; ra.mods = c->mods; ra.tw = c->tw;
-  ra.level = level; ra.log_n = c->log_n;
-  timed(c, "ntt_rescale", 2.0 * tot / 2 * n2, 2.0 * tot * 8 * 3 + 2.0 * N * 8, st,
-        [&] { by_logs<LRescale>(n2, ra, st); });
+  const double ne = l + K;
+  double macs = 0;
+  for (u32 j = 0; j < P.beta; ++j) macs += (double)P.cnt[j] * (ne - P.cnt[j]);
+  switch (st) {
+    case ST_TENSOR: ops = (l + 2 * ex) * hN * n2 + 4 * l * N; bytes = (4 * l + 3 * l + l + 2 * ex) * N * 8; break;
+    case ST_Y_ICOLS: ops = (l + 2 * ex) * (hN * n1 + N); bytes = 2 * (l + 2 * ex) * N * 8; break;
+    case ST_MU_CONV: ops = macs * N; bytes = (l + P.dt_limbs) * N * 8; break;
+    case ST_DT_NCOLS: ops = P.dt_limbs * hN * n1; bytes = 2.0 * P.dt_limbs * N * 8; break;
+    case ST_DT_NBLOCKS: ops = P.dt_limbs * hN * n2; bytes = 2.0 * P.dt_limbs * N * 8; break;
+    case ST_IP: ops = 2.0 * P.beta * ne * N; bytes = (3.0 * P.beta + 2) * ne * N * 8; break;
+    case ST_KS_IBLOCKS: ops = 2 * (K + ex) * hN * n2; bytes = 4 * (K + ex) * N * 8; break;
+    case ST_KS_ICOLS: ops = 2 * (K + ex) * (hN * n1 + N); bytes = 4 * (K + ex) * N * 8; break;
+    case ST_MD_CONV: ops = 2 * K * l * N; bytes = 2 * (K + l) * N * 8; break;
+    case ST_Z_NCOLS: ops = 2 * l * hN * n1; bytes = 4 * l * N * 8; break;
+    case ST_COMBINE: ops = 2 * l * hN * n2 + 2 * l * N; bytes = 2 * l * 4 * N * 8; break;
+    case ST_LIFT: ops = rs ? 2 * (l - 1) * hN * n1 : 0; bytes = rs ? (2 * (l - 1) + 6) * N * 8 : 0; break;
+    case ST_RESCALE: ops = rs ? 2 * (l - 1) * hN * n2 : 0; bytes = rs ? 2 * (l - 1) * 3 * N * 8 : 0; break;
+    default: ops = bytes = 0;
+  }
 }
+
+void launch_stage(const he_ctx* c, int stage, const Common& cm, const Batch& b, double ops, double bytes,
+                  hipStream_t st) {
+  if (!b.nitems) return;
+  timed(c, stage_name(stage), ops, bytes, st, [&] {
+    switch (c->log_n) {
+      case 12: launch_stage_n<6, 6>(stage, cm, b, st); break;
+      case 13: launch_stage_n<6, 7>(stage, cm, b, st); break;
+      case 14: launch_stage_n<7, 7>(stage, cm, b, st); break;
+      case 15: launch_stage_n<7, 8>(stage, cm, b, st); break;
+      case 16: launch_stage_n<8, 8>(stage, cm, b, st); break;
+      case 17: launch_stage_n<8, 9>(stage, cm, b, st); break;
+    }
+  });
+}
+
+Common make_common(const he_ctx* c, const u64* evk) {
+  Common cm{};
+  cm.mods = c->mods; cm.tw = c->tw; cm.itw = c->itw; cm.evk = evk; cm.pinv = c->pinv; cm.iota = c->iota;
+  cm.L = c->L; cm.K = c->K; cm.log_n = c->log_n;
+  return cm;
+}
+
+// Lay out one pair's workspace starting at ws; returns words used.
+u64 pair_layout(const he_ctx* c, u32 level, u64* ws, PairDesc& pd) {
+  const LevelPlan& P = c->lv[level];
+  const u64 N = c->N;
+  u64* w = ws;
+  pd.d2 = w; w += (u64)level * N;
+  pd.y = w; w += (u64)(level + 2) * N;
+  pd.dt = w; w += (u64)P.dt_limbs * N;
+  pd.ks = w; w += 2ull * (level + c->K + 1) * N;
+  pd.z = w; w += 2ull * level * N;
+  pd.zc = w; w += 2ull * level * N;
+  return (u64)(w - ws);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -683,67 +748,21 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const LevelPlan& P = c->lv[level];
-  const u32 K = c->K, ne = level + K;
-  const int n1 = (int)c->log_n / 2, n2 = (int)c->log_n - n1;
-  const bool rs = out != nullptr;
-  u64* w = (u64*)ws;
-  u64* D2 = w;  w += (u64)level * N;
-  u64* Y = w;   w += (u64)(level + 2) * N;
-  u64* DT = w;  w += (u64)P.dt_limbs * N;
-  u64* KS = w;  w += 2ull * (ne + 1) * N;
-  u64* Z = w;   w += 2ull * level * N;
-  u64* ZL = w;  w += 2ull * N;
-  u64* RL = relin ? relin : w;
-  const u64 tot = (u64)level * N;
-  const double hN = (double)N / 2;
-
-  // 1. tensor product + INTT blocks pass of d2 (and of d0, d1 of the last limb)
-  TensorArgs ta{};
-  ta.ct1 = ct1; ta.ct2 = ct2; ta.rl = RL; ta.d2o = D2; ta.yp = Y; ta.x01 = rs ? Y + tot : nullptr;
-  ta.mods = c->mods; ta.itw = c->itw; ta.level = level; ta.log_n = c->log_n;
-  timed(c, "tensor_intt", tot / 2.0 * n2 + 3.0 * tot, 8.0 * tot * 8, st, [&] { by_logs<LTensor>(n2, ta, st); });
-  // 2. INTT cols pass: y_i = INTT(d2_i) * [(Qt_j/q_i)^-1]
-  const u32 ny = level + (rs ? 2 : 0);
-  timed(c, "intt_cols", ny * (hN * n1 + N), 2.0 * ny * N * 8, st,
-        [&] { intt_cols(c, Y, N, 0, P.y_mod, P.y_scale, ny, 1, st); });
-  // 3. mod up: conversion + NTT cols pass of every converted limb
-  ConvNttArgs ca{};
-  ca.src = Y; ca.dst = DT; ca.src_z = 0; ca.dst_z = 0; ca.tg = P.mu_tg; ca.consts = P.mu_c; ca.mods = c->mods;
-  ca.tw = c->tw; ca.side = nullptr; ca.side_o = 0; ca.ntarget = P.dt_limbs; ca.log_n = c->log_n;
-  {
-    double macs = 0;
-    for (u32 j = 0; j < P.beta; ++j) macs += (double)P.cnt[j] * (ne - P.cnt[j]) * N;
-    timed(c, "modup_ntt_cols", macs + P.dt_limbs * hN * n1, (level + P.dt_limbs) * (double)N * 8, st,
-          [&] { by_logs<LConv>(n1, ca, 1u, st); });
+  PairDesc pd{};
+  pd.ct1 = ct1; pd.ct2 = ct2; pd.out = out; pd.r = nullptr; pd.plan = P.plan; pd.level = level;
+  pd.rs = out ? 1 : 0;
+  const u64 used = pair_layout(c, level, (u64*)ws, pd);
+  pd.rl = relin ? relin : (u64*)ws + used;
+  const Common cm = make_common(c, evk);
+  for (int s = 0; s < ST_COUNT; ++s) {
+    Batch b{};
+    b.one = pd;
+    b.npairs = 1;
+    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, pd.rs != 0);
+    double ops = 0, bytes = 0;
+    if (c->timing) stage_work(c, s, level, pd.rs != 0, ops, bytes);
+    launch_stage(c, s, cm, b, ops, bytes, st);
   }
-  // 4. NTT blocks pass + evk inner product (+ INTT blocks pass of special limbs)
-  IpArgs ia{};
-  ia.d2 = D2; ia.dtp = DT; ia.evk = evk; ia.ks = KS; ia.mods = c->mods; ia.tw = c->tw; ia.itw = c->itw;
-  ia.emod = P.emod;
-  for (u32 j = 0; j < P.beta; ++j) { ia.dt_first[j] = P.dt_first[j]; ia.lo[j] = P.lo[j]; ia.cnt[j] = P.cnt[j]; }
-  ia.beta = P.beta; ia.level = level; ia.K = K; ia.L = c->L; ia.log_n = c->log_n; ia.extra_last = rs ? 1 : 0;
-  timed(c, "ntt_ip", P.dt_limbs * hN * n2 + 2.0 * P.beta * ne * N + (2.0 * K + (rs ? 2 : 0)) * hN * n2,
-        ((double)P.dt_limbs + 2.0 * P.beta * ne + 2.0 * ne) * N * 8, st, [&] { by_logs<LIp>(n2, ia, st); });
-  // 5. INTT cols pass of the special limbs (scaled by [(P/p_k)^-1]) and of limb level-1
-  const u32 nsl = K + (rs ? 1 : 0);
-  timed(c, "intt_cols", 2.0 * nsl * (hN * n1 + N), 4.0 * nsl * N * 8, st,
-        [&] { intt_cols(c, KS + (u64)level * N, N, (u64)(ne + 1) * N, P.s_mod, P.s_scale, nsl, 2, st); });
-  // 6. mod down: conversion + NTT cols pass
-  ConvNttArgs da{};
-  da.src = KS; da.dst = Z; da.src_z = (u64)(ne + 1) * N; da.dst_z = tot; da.tg = P.md_tg; da.consts = P.md_c;
-  da.mods = c->mods; da.tw = c->tw; da.side = rs ? ZL : nullptr; da.side_o = level - 1; da.ntarget = level;
-  da.log_n = c->log_n;
-  timed(c, "moddown_ntt_cols", 2.0 * K * tot + 2.0 * tot / 2 * n1, 2.0 * (K + level) * N * 8, st,
-        [&] { by_logs<LConv>(n1, da, 2u, st); });
-  // 7. NTT blocks pass + combine
-  CombineArgs cb{};
-  cb.zp = Z; cb.ks = KS; cb.rl = RL; cb.pinv = c->pinv; cb.mods = c->mods; cb.tw = c->tw; cb.level = level;
-  cb.K = K; cb.log_n = c->log_n;
-  timed(c, "ntt_combine", 2.0 * tot / 2 * n2 + 2.0 * tot, 2.0 * tot * 4 * 8, st,
-        [&] { by_logs<LCombine>(n2, cb, st); });
-  // 8-9. rescale
-  if (rs)
-    rescale_fused(c, level, RL, out, nullptr, Y + tot, KS + (u64)ne * N, (u64)(ne + 1) * N, ZL, Z, st);
   HIP_TRY(hipGetLastError());
   return HE_OK;
 }
@@ -757,13 +776,186 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
   hipStream_t st = (hipStream_t)stream;
   const u64 N = c->N;
   u64* R = (u64*)ws;
-  u64* S = R + 2 * N;
+  // coefficient form of the dropped limb of both polynomials
   ntt_launch(c, false, d_in + (u64)(level - 1) * N, R, N, N, (u64)level * N, N, c->iota + (level - 1), nullptr, 1,
              2, st);
-  rescale_fused(c, level, d_in, d_out, R, nullptr, nullptr, 0, nullptr, S, st);
+  const LevelPlan& P = c->lv[level];
+  PairDesc pd{};
+  pd.rl = const_cast<u64*>(d_in);  // read only by the rescale stages
+  pd.out = d_out; pd.r = R; pd.z = R + 2 * N; pd.plan = P.plan; pd.level = level; pd.rs = 1;
+  const Common cm = make_common(c, nullptr);
+  for (int s : {(int)ST_LIFT, (int)ST_RESCALE}) {
+    Batch b{};
+    b.one = pd;
+    b.npairs = 1;
+    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, true);
+    double ops = 0, bytes = 0;
+    if (c->timing) stage_work(c, s, level, true, ops, bytes);
+    launch_stage(c, s, cm, b, ops, bytes, st);
+  }
   HIP_TRY(hipGetLastError());
   return HE_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+struct he_batch {
+  he_ctx* ctx = nullptr;
+  u32 n = 0;
+  void* dev = nullptr;                 // descriptors + offsets (device)
+  const PairDesc* pairs = nullptr;
+  const u32* offs[ST_COUNT] = {};
+  u32 nitems[ST_COUNT] = {};
+  std::vector<u32> levels;
+  std::vector<uint8_t> rs;
+  // cached graph of the whole batched HE Mul
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const u64* graph_evk = nullptr;
+};
+
+static size_t batch_ws_words(const he_ctx* c, const he_batch_item* items, u32 n) {
+  size_t w = 0;
+  for (u32 i = 0; i < n; ++i) {
+    PairDesc tmp{};
+    w += pair_layout(c, items[i].level, nullptr, tmp);
+    if (!items[i].relin) w += 2ull * items[i].level * c->N;
+  }
+  return w;
+}
+
+extern "C" {
+
+size_t he_batch_workspace_bytes(const he_ctx* c, const he_batch_item* items, uint32_t n) {
+  if (!c || (!items && n)) return 0;
+  for (u32 i = 0; i < n; ++i)
+    if (items[i].level < 1 || items[i].level > c->L) return 0;
+  return batch_ws_words(c, items, n) * 8;
+}
+
+he_status he_batch_create(he_ctx* c, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
+                          he_batch** out) {
+  if (!c || !items || !ws || !out || n == 0) return fail(HE_EINVAL, "he_batch_create: bad arguments");
+  *out = nullptr;
+  for (u32 i = 0; i < n; ++i) {
+    const he_batch_item& it = items[i];
+    if (!it.ct1 || !it.ct2 || (!it.relin && !it.out)) return fail(HE_EINVAL, "he_batch_create: item %u incomplete", i);
+    if (it.level < 1 || it.level > c->L) return fail(HE_ELEVEL, "he_batch_create: item %u level %u", i, it.level);
+    if (it.out && it.level < 2) return fail(HE_ELEVEL, "he_batch_create: item %u: rescale needs level >= 2", i);
+  }
+  if (ws_bytes < batch_ws_words(c, items, n) * 8) return fail(HE_ENOMEM, "he_batch_create: workspace too small");
+  HIP_TRY(hipSetDevice(c->device));
+  std::unique_ptr<he_batch> bt(new he_batch);
+  bt->ctx = c;
+  bt->n = n;
+  std::vector<PairDesc> pds(n);
+  std::vector<u32> offs((size_t)ST_COUNT * (n + 1));
+  u64* w = (u64*)ws;
+  for (u32 i = 0; i < n; ++i) {
+    const he_batch_item& it = items[i];
+    PairDesc& pd = pds[i];
+    pd.ct1 = it.ct1; pd.ct2 = it.ct2; pd.out = it.out; pd.r = nullptr;
+    pd.plan = c->lv[it.level].plan; pd.level = it.level; pd.rs = it.out ? 1 : 0;
+    w += pair_layout(c, it.level, w, pd);
+    if (it.relin) {
+      pd.rl = it.relin;
+    } else {
+      pd.rl = w;
+      w += 2ull * it.level * c->N;
+    }
+    bt->levels.push_back(it.level);
+    bt->rs.push_back(pd.rs);
+  }
+  for (int s = 0; s < ST_COUNT; ++s) {
+    u64 acc = 0;
+    for (u32 i = 0; i < n; ++i) {
+      offs[(size_t)s * (n + 1) + i] = (u32)acc;
+      const LevelPlan& P = c->lv[items[i].level];
+      acc += stage_items(s, c->log_n, items[i].level, c->K, P.beta, P.dt_limbs, pds[i].rs != 0);
+    }
+    if (acc > 0xffffff00ull) return fail(HE_EUNSUPPORTED, "he_batch_create: batch too large");
+    offs[(size_t)s * (n + 1) + n] = (u32)acc;
+    bt->nitems[s] = (u32)acc;
+  }
+  const size_t pbytes = sizeof(PairDesc) * n, obytes = sizeof(u32) * offs.size();
+  HIP_TRY(hipMalloc(&bt->dev, pbytes + obytes));
+  std::vector<uint8_t> host(pbytes + obytes);
+  memcpy(host.data(), pds.data(), pbytes);
+  memcpy(host.data() + pbytes, offs.data(), obytes);
+  {
+    hipError_t e = hipMemcpy(bt->dev, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(bt->dev);
+      return fail(HE_EDEVICE, "he_batch_create: upload failed: %s", hipGetErrorString(e));
+    }
+  }
+  bt->pairs = (const PairDesc*)bt->dev;
+  for (int s = 0; s < ST_COUNT; ++s) bt->offs[s] = (const u32*)((uint8_t*)bt->dev + pbytes) + (size_t)s * (n + 1);
+  *out = bt.release();
+  return HE_OK;
+}
+
+static void batch_launch_all(he_ctx* c, he_batch* bt, const u64* evk, hipStream_t st) {
+  const Common cm = make_common(c, evk);
+  for (int s = 0; s < ST_COUNT; ++s) {
+    Batch b{};
+    b.pairs = bt->pairs;
+    b.offs = bt->offs[s];
+    b.npairs = bt->n;
+    b.nitems = bt->nitems[s];
+    double ops = 0, bytes = 0;
+    if (c->timing)
+      for (u32 i = 0; i < bt->n; ++i) {
+        double o = 0, by = 0;
+        stage_work(c, s, bt->levels[i], bt->rs[i] != 0, o, by);
+        ops += o;
+        bytes += by;
+      }
+    launch_stage(c, s, cm, b, ops, bytes, st);
+  }
+}
+
+he_status he_mul_batch(he_ctx* c, he_batch* bt, const uint64_t* evk, int use_graph, he_stream stream) {
+  if (!c || !bt || !evk || bt->ctx != c) return fail(HE_EINVAL, "he_mul_batch: bad arguments");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph || c->timing) {
+    batch_launch_all(c, bt, evk, st);
+    HIP_TRY(hipGetLastError());
+    return HE_OK;
+  }
+  if (!bt->exec || bt->graph_evk != evk) {
+    if (bt->exec) { (void)hipGraphExecDestroy(bt->exec); bt->exec = nullptr; }
+    if (bt->graph) { (void)hipGraphDestroy(bt->graph); bt->graph = nullptr; }
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      batch_launch_all(c, bt, evk, cap);
+      e = hipStreamEndCapture(cap, &bt->graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(HE_EDEVICE, "he_mul_batch: graph capture failed: %s", hipGetErrorString(e));
+    bt->graph_evk = evk;
+  }
+  HIP_TRY(hipGraphLaunch(bt->exec, st));
+  return HE_OK;
+}
+
+void he_batch_destroy(he_batch* bt) {
+  if (!bt) return;
+  (void)hipSetDevice(bt->ctx->device);
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  if (bt->dev) (void)hipFree(bt->dev);
+  delete bt;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 // ---------------------------------------------------------------- keys & encryption
 static he_status upload_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {

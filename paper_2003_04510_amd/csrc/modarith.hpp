@@ -24,8 +24,18 @@ typedef uint32_t u32;
 // no kernel writes while it runs (moduli, twiddles, conversion constants).
 template <class T>
 __device__ __forceinline__ T ldc(const T* p) {
-  return *(const __attribute__((address_space(4))) T*)p;
+  static_assert(sizeof(T) % 4 == 0, "word-sized table entries");
+  typedef const __attribute__((address_space(4))) uint32_t* cptr;
+  const cptr src = (cptr)p;
+  T r;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) d[i] = src[i];
+  return r;
 }
+
+// A value every lane of the wavefront holds, moved to a scalar register.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 struct U128 {
   u64 lo, hi;

@@ -350,237 +350,4 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_blocks(NttArgs 
   }
 }
 
-// ------------------------------------------------------------------ persistent passes
-// A grid of G workgroups walks the tiles t = blockIdx.x, +G, ...; while one
-// tile is transformed, the next tile's operands are already in flight
-// (register double buffer), so HBM traffic overlaps the butterflies.
-// Tile t of a launch over nl limbs x np polynomials: z = t / (nl * TPL),
-// limb = (t / TPL) % nl, position = t % TPL (TPL tiles per limb).
-struct TileId {
-  u32 z, limb, pos;
-};
-__device__ __forceinline__ u32 uniform(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ TileId tile_id(u32 t, u32 nl, u32 tpl) {
-  TileId r;
-  r.pos = uniform(t % tpl);
-  const u32 lz = t / tpl;
-  r.limb = uniform(lz % nl);
-  r.z = uniform(lz / nl);
-  return r;
-}
-
-template <bool FWD, int LOGS, int EPW = NTT_EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols_p(NttArgs a, u32 nl, u32 ntiles) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
-  using Gm = Geo<LOGS, LOGR>;
-  using PL = PassLayout<LOGS, true, EPW>;
-  constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
-  using RF = RoundShape<LOGS, LOGR, FIRST>;
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
-  const int n2 = a.log_n - LOGS;
-  const u32 tpl = (1u << n2) / PL::SUBS;
-  const int sub = PL::sub(), tt = PL::tt();
-  u32 t = blockIdx.x;
-  if (t >= ntiles) return;
-  u64 nx[Gm::R];
-  auto fetch = [&](u32 tile) {
-    const TileId id = tile_id(tile, nl, tpl);
-    const u64* in = a.src + (u64)id.limb * a.src_stride + (u64)id.z * a.src_zstride + (u64)id.pos * PL::SUBS + sub;
-#pragma unroll
-    for (int u = 0; u < RF::NG; ++u)
-#pragma unroll
-      for (int i = 0; i < RF::G; ++i) nx[u * RF::G + i] = in[(u64)RF::elem(tt, u, i) << n2];
-  };
-  fetch(t);
-  for (; t < ntiles; t += gridDim.x) {
-    u64 x[Gm::R];
-#pragma unroll
-    for (int i = 0; i < Gm::R; ++i) x[i] = nx[i];
-    if (t + gridDim.x < ntiles) fetch(t + gridDim.x);
-    const TileId id = tile_id(t, nl, tpl);
-    const u32 mi = a.limb_mod[id.limb];
-    const u64 q = a.mods[mi].q;
-    u64* out = a.dst + (u64)id.limb * a.dst_stride + (u64)id.z * a.dst_zstride + (u64)id.pos * PL::SUBS + sub;
-    u64 w = a.mods[mi].ninv, ws = a.mods[mi].ninvs;
-    if (!FWD && a.scale) {
-      w = a.scale[2 * (u64)id.limb];
-      ws = a.scale[2 * (u64)id.limb + 1];
-    }
-    sub_transform_regs<FWD, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, a.tw + ((u64)mi << a.log_n), 1, q,
-        [&](int e, u64 v) {
-          out[(u64)e << n2] = FWD ? ntt_canon<true>(v, q) : csub(shoup_lazy(v, w, ws, q), q);
-        });
-    __syncthreads();  // the tile's LDS area is reused by the next tile
-  }
-}
-
-template <bool FWD, int LOGS, int EPW = NTT_EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_blocks_p(NttArgs a, u32 nl, u32 ntiles) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
-  using Gm = Geo<LOGS, LOGR>;
-  using PL = PassLayout<LOGS, false, EPW>;
-  constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
-  constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
-  using RF = RoundShape<LOGS, LOGR, FIRST>;
-  constexpr bool IN_LDS = !FWD, OUT_LDS = FWD;  // coalesce the thread-contiguous side through LDS
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
-  const int n1 = a.log_n - LOGS;
-  const u32 tpl = (1u << n1) / PL::SUBS;
-  const int sub = PL::sub(), tt = PL::tt();
-  u32 t = blockIdx.x;
-  if (t >= ntiles) return;
-  u64 nx[Gm::R];
-  auto fetch = [&](u32 tile) {
-    const TileId id = tile_id(tile, nl, tpl);
-    const u64* in0 = a.src + (u64)id.limb * a.src_stride + (u64)id.z * a.src_zstride + ((u64)id.pos * PL::SUBS << LOGS);
-    if constexpr (IN_LDS) {
-#pragma unroll
-      for (int k = 0; k < Gm::R; ++k) nx[k] = in0[threadIdx.x + k * THREADS];
-    } else {
-      const u64* in = in0 + ((u64)sub << LOGS);
-#pragma unroll
-      for (int u = 0; u < RF::NG; ++u)
-#pragma unroll
-        for (int i = 0; i < RF::G; ++i) nx[u * RF::G + i] = in[RF::elem(tt, u, i)];
-    }
-  };
-  fetch(t);
-  for (; t < ntiles; t += gridDim.x) {
-    u64 x[Gm::R];
-    if constexpr (IN_LDS) {
-#pragma unroll
-      for (int k = 0; k < Gm::R; ++k) {
-        const int idx = threadIdx.x + k * THREADS;
-        lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))] = nx[k];
-      }
-      __syncthreads();
-      lds_get<LOGS, LOGR, FIRST>(lds + sub * Gm::SUB, x, tt);
-    } else {
-#pragma unroll
-      for (int i = 0; i < Gm::R; ++i) x[i] = nx[i];
-    }
-    if (t + gridDim.x < ntiles) fetch(t + gridDim.x);
-    const TileId id = tile_id(t, nl, tpl);
-    const u32 mi = a.limb_mod[id.limb];
-    const u64 q = a.mods[mi].q;
-    const u64 blk0 = (u64)id.pos * PL::SUBS;
-    u64* out0 = a.dst + (u64)id.limb * a.dst_stride + (u64)id.z * a.dst_zstride + (blk0 << LOGS);
-    u64* out = out0 + ((u64)sub << LOGS);
-    sub_transform_regs<FWD, LOGS, LOGR, OUT_LDS>(x, lds + sub * Gm::SUB, tt, a.tw + ((u64)mi << a.log_n),
-                                                 (1ull << n1) + blk0 + sub, q,
-                                                 [&](int e, u64 v) { out[e] = ntt_canon<FWD>(v, q); });
-    if constexpr (OUT_LDS) {
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < Gm::R; ++k) {
-        const int idx = threadIdx.x + k * THREADS;
-        out0[idx] = ntt_canon<FWD>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], q);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Experimental: "cols" pass with the (shared) twiddles W[0, S) staged in LDS.
-template <bool FWD, int LOGS, int EPW = NTT_EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols_twlds(NttArgs a) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
-  using Gm = Geo<LOGS, LOGR>;
-  using PL = PassLayout<LOGS, true, EPW>;
-  constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
-  __shared__ Tw2 tws[Gm::S];
-  const int limb = blockIdx.y;
-  const u32 mi = a.limb_mod[limb];
-  const u64 q = a.mods[mi].q;
-  const int n2 = a.log_n - LOGS;
-  const int sub = PL::sub(), tt = PL::tt();
-  const u64 col = (u64)blockIdx.x * PL::SUBS + sub;
-  const u64* in = a.src + (u64)limb * a.src_stride + (u64)blockIdx.z * a.src_zstride + col;
-  u64* out = a.dst + (u64)limb * a.dst_stride + (u64)blockIdx.z * a.dst_zstride + col;
-  const Tw2* twg = a.tw + ((u64)mi << a.log_n);
-  for (int i = threadIdx.x; i < Gm::S; i += THREADS) tws[i] = twg[i];
-  u64 w = a.mods[mi].ninv, ws = a.mods[mi].ninvs;
-  if (!FWD && a.scale) {
-    w = a.scale[2 * (u64)limb];
-    ws = a.scale[2 * (u64)limb + 1];
-  }
-  u64 x[Gm::R];
-  {
-    constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
-    using RS = RoundShape<LOGS, LOGR, FIRST>;
-#pragma unroll
-    for (int u = 0; u < RS::NG; ++u)
-#pragma unroll
-      for (int i = 0; i < RS::G; ++i) x[u * RS::G + i] = in[(u64)RS::elem(tt, u, i) << n2];
-  }
-  __syncthreads();
-  sub_transform_regs<FWD, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, tws, 1, q,
-      [&](int e, u64 v) {
-        out[(u64)e << n2] = FWD ? ntt_canon<true>(v, q) : csub(shoup_lazy(v, w, ws, q), q);
-      });
-}
-
-// Experimental: persistent "cols" pass, twiddles of the tile's prime staged
-// in LDS, next tile (data + twiddles) prefetched into registers.  Workgroup
-// g owns the contiguous tile range [g*n/G, (g+1)*n/G).
-template <bool FWD, int LOGS, int EPW = NTT_EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols_pp(NttArgs a, u32 nl, u32 ntiles) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
-  using Gm = Geo<LOGS, LOGR>;
-  using PL = PassLayout<LOGS, true, EPW>;
-  constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
-  constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
-  using RF = RoundShape<LOGS, LOGR, FIRST>;
-  constexpr int TWPT = (Gm::S + THREADS - 1) / THREADS;  // twiddles per thread
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
-  __shared__ Tw2 tws[Gm::S];
-  const int n2 = a.log_n - LOGS;
-  const u32 tpl = (1u << n2) / PL::SUBS;
-  const int sub = PL::sub(), tt = PL::tt();
-  const u32 t0 = (u32)(((u64)blockIdx.x * ntiles) / gridDim.x);
-  const u32 t1 = (u32)(((u64)(blockIdx.x + 1) * ntiles) / gridDim.x);
-  if (t0 >= t1) return;
-  u64 nx[Gm::R];
-  u64 ntw0 = 0, ntw1 = 0;  // one twiddle pair per thread (S <= THREADS)
-  static_assert(TWPT == 1, "one twiddle pair per thread");
-#define HE_FETCH_COLS(tile)                                                                                  \
-  {                                                                                                          \
-    const TileId id_ = tile_id(tile, nl, tpl);                                                               \
-    const u32 mi_ = ldc(a.limb_mod + id_.limb);                                                              \
-    const u64* in_ = a.src + (u64)id_.limb * a.src_stride + (u64)id_.z * a.src_zstride + (u64)id_.pos * PL::SUBS + sub; \
-    _Pragma("unroll") for (int u = 0; u < RF::NG; ++u)                                                       \
-    _Pragma("unroll") for (int i = 0; i < RF::G; ++i) nx[u * RF::G + i] = in_[(u64)RF::elem(tt, u, i) << n2]; \
-    if (threadIdx.x < Gm::S) {                                                                               \
-      const Tw2 tv_ = a.tw[((u64)mi_ << a.log_n) + threadIdx.x];                                             \
-      ntw0 = tv_.w;                                                                                          \
-      ntw1 = tv_.ws;                                                                                         \
-    }                                                                                                        \
-  }
-  HE_FETCH_COLS(t0)
-  for (u32 t = t0; t < t1; ++t) {
-    u64 x[Gm::R];
-#pragma unroll
-    for (int i = 0; i < Gm::R; ++i) x[i] = nx[i];
-    if (threadIdx.x < Gm::S) tws[threadIdx.x] = Tw2{ntw0, ntw1};
-    __syncthreads();
-    if (t + 1 < t1) HE_FETCH_COLS(t + 1)
-    const TileId id = tile_id(t, nl, tpl);
-    const u32 mi = ldc(a.limb_mod + id.limb);
-    const u64 q = ldc(&a.mods[mi].q);
-    u64* out = a.dst + (u64)id.limb * a.dst_stride + (u64)id.z * a.dst_zstride + (u64)id.pos * PL::SUBS + sub;
-    u64 w = ldc(&a.mods[mi].ninv), ws = ldc(&a.mods[mi].ninvs);
-    if (!FWD && a.scale) {
-      w = ldc(a.scale + 2 * (u64)id.limb);
-      ws = ldc(a.scale + 2 * (u64)id.limb + 1);
-    }
-    sub_transform_regs<FWD, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, tws, 1, q,
-        [&](int e, u64 v) {
-          out[(u64)e << n2] = FWD ? ntt_canon<true>(v, q) : csub(shoup_lazy(v, w, ws, q), q);
-        });
-    __syncthreads();
-  }
-#undef HE_FETCH_COLS
-}
-
 }  // namespace he
