@@ -143,7 +143,47 @@ size_t he_batch_workspace_bytes(const he_ctx* ctx, const he_batch_item* items, u
 he_status he_batch_create(he_ctx* ctx, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
                           he_batch** out);
 he_status he_mul_batch(he_ctx* ctx, he_batch* batch, const uint64_t* d_evk, int use_graph, he_stream stream);
+/* As he_batch_create, but the descriptors go to caller-provided device
+ * memory d_desc (at least he_batch_desc_bytes(n) bytes) through an
+ * asynchronous copy on `stream` (no device allocation, no host
+ * synchronization); the batch must then run on that same stream, and
+ * d_desc must not be reused until the batch's work has finished. */
+size_t he_batch_desc_bytes(uint32_t n);
+he_status he_batch_create_async(he_ctx* ctx, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
+                                void* d_desc, size_t desc_bytes, he_stream stream, he_batch** out);
 void he_batch_destroy(he_batch* batch);
+
+/* Serving: a request loop with continuous batching (host side, native).
+ * he_server_add_ring registers a context with its resident evk and a
+ * workspace arena of arena_bytes (device memory the server allocates; the
+ * sum over rings must not exceed cfg->hbm_budget).  he_server_submit queues
+ * one HE Mul with rescale (level >= 2) on operands ct1, ct2 [2][level][N]
+ * into out [2][level-1][N] (device buffers owned by the caller, untouched
+ * until the request completes); the arrival time is taken at submission.
+ * he_server_progress never blocks: it retires batches whose work finished
+ * and, per ring, admits queued requests in arrival order while their
+ * workspace fits the arena (HBM footprint) and at most max_batch per batch,
+ * launching each group as one batched HE Mul on the ring's stream while at
+ * most max_inflight batches of that ring are in flight.  he_server_poll
+ * returns completed request ids with their latency (seconds from
+ * submission to the moment progress observed completion).  Errors are
+ * he_status codes; a failed launch leaves the request queue untouched. */
+typedef struct he_server he_server;
+typedef struct he_server_cfg {
+  size_t hbm_budget;     /* bytes of workspace arenas over all rings */
+  uint32_t max_batch;    /* requests per batch */
+  uint32_t max_inflight; /* batches in flight per ring */
+} he_server_cfg;
+he_status he_server_create(const he_server_cfg* cfg, he_server** out);
+he_status he_server_add_ring(he_server* srv, he_ctx* ctx, const uint64_t* d_evk, size_t arena_bytes,
+                             uint32_t* ring_id);
+he_status he_server_submit(he_server* srv, uint32_t ring, uint64_t id, uint32_t level, const uint64_t* d_ct1,
+                           const uint64_t* d_ct2, uint64_t* d_out);
+he_status he_server_progress(he_server* srv, uint32_t* launched);
+he_status he_server_poll(he_server* srv, uint64_t* ids, double* latency_s, uint32_t max, uint32_t* n);
+he_status he_server_stats(const he_server* srv, uint64_t* queued, uint64_t* inflight, uint64_t* batches,
+                          uint64_t* completed);
+void he_server_destroy(he_server* srv);
 
 /* Rescale (Sec. III-A, division by the last prime, rounded to nearest):
  * d_in [2][level][N] -> d_out [2][level-1][N].  level >= 2. */

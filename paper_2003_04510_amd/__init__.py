@@ -5,4 +5,4 @@ include/he_mi355x.h).  This package only marshals arguments: PyTorch supplies
 device memory and streams.  There is no CPU fallback: if the library is not
 built, importing the binding raises.
 """
-from .binding import Context, HeError, load_library, workload_primes  # noqa: F401
+from .binding import Batch, Context, HeError, Server, load_library, workload_primes  # noqa: F401

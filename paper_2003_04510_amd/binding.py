@@ -30,6 +30,10 @@ class BatchItem(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("ct1", vp), ("ct2", vp), ("relin", vp), ("out", vp)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint32), ("ms", ctypes.c_double),
                 ("ops", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -71,12 +75,22 @@ def load_library():
     L.he_mul_batch.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     L.he_batch_destroy.argtypes = [vp]
     L.he_batch_destroy.restype = None
+    L.he_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
+    L.he_server_add_ring.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(u32)]
+    L.he_server_submit.argtypes = [vp, u32, ctypes.c_uint64, u32, vp, vp, vp]
+    L.he_server_progress.argtypes = [vp, ctypes.POINTER(u32)]
+    L.he_server_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), u32,
+                                 ctypes.POINTER(u32)]
+    L.he_server_stats.argtypes = [vp] + [ctypes.POINTER(ctypes.c_uint64)] * 4
+    L.he_server_destroy.argtypes = [vp]
+    L.he_server_destroy.restype = None
     L.he_status_str.argtypes = [st]
     L.he_status_str.restype = ctypes.c_char_p
     L.he_last_error.restype = ctypes.c_char_p
     for f in ("he_gen_primes", "he_ctx_create", "he_keygen", "he_encrypt", "he_decrypt", "he_mul",
               "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read", "he_batch_create",
-              "he_mul_batch"):
+              "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
+              "he_server_poll", "he_server_stats"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -304,6 +318,57 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load_library().he_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching HE Mul server (the loop runs in the native library)."""
+
+    def __init__(self, hbm_budget: int, max_batch: int = 64, max_inflight: int = 2):
+        L = load_library()
+        h = vp()
+        cfg = ServerCfg(hbm_budget, max_batch, max_inflight)
+        _check(L.he_server_create(ctypes.byref(cfg), ctypes.byref(h)), "he_server_create")
+        self._h = h
+        self._keep = []
+
+    def add_ring(self, ctx: "Context", evk, arena_bytes: int) -> int:
+        rid = u32(0)
+        _check(load_library().he_server_add_ring(self._h, ctx._h, vp(evk.data_ptr()), arena_bytes, ctypes.byref(rid)),
+               "he_server_add_ring")
+        self._keep.append((ctx, evk))
+        return rid.value
+
+    def submit(self, ring: int, rid: int, level: int, ct1, ct2, out):
+        _check(load_library().he_server_submit(self._h, ring, rid, level, vp(ct1.data_ptr()), vp(ct2.data_ptr()),
+                                               vp(out.data_ptr())), "he_server_submit")
+
+    def progress(self) -> int:
+        n = u32(0)
+        _check(load_library().he_server_progress(self._h, ctypes.byref(n)), "he_server_progress")
+        return n.value
+
+    def poll(self, maxn: int = 4096):
+        ids = (ctypes.c_uint64 * maxn)()
+        lat = (ctypes.c_double * maxn)()
+        n = u32(0)
+        _check(load_library().he_server_poll(self._h, ids, lat, maxn, ctypes.byref(n)), "he_server_poll")
+        return [(ids[i], lat[i]) for i in range(n.value)]
+
+    def stats(self) -> dict:
+        v = [ctypes.c_uint64(0) for _ in range(4)]
+        _check(load_library().he_server_stats(self._h, *[ctypes.byref(x) for x in v]), "he_server_stats")
+        return dict(zip(("queued", "inflight", "batches", "completed"), [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().he_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -804,6 +804,8 @@ struct he_batch {
   he_ctx* ctx = nullptr;
   u32 n = 0;
   void* dev = nullptr;                 // descriptors + offsets (device)
+  bool owns_dev = true;                // false: caller-provided descriptor memory
+  std::vector<uint8_t> host;           // staging copy (kept until destroy for async uploads)
   const PairDesc* pairs = nullptr;
   const u32* offs[ST_COUNT] = {};
   u32 nitems[ST_COUNT] = {};
@@ -834,10 +836,13 @@ size_t he_batch_workspace_bytes(const he_ctx* c, const he_batch_item* items, uin
   return batch_ws_words(c, items, n) * 8;
 }
 
-he_status he_batch_create(he_ctx* c, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
-                          he_batch** out) {
-  if (!c || !items || !ws || !out || n == 0) return fail(HE_EINVAL, "he_batch_create: bad arguments");
-  *out = nullptr;
+size_t he_batch_desc_bytes(uint32_t n) {
+  return (sizeof(PairDesc) * (size_t)n + sizeof(u32) * (size_t)ST_COUNT * (n + 1) + 255) & ~size_t(255);
+}
+
+static he_status batch_build(he_ctx* c, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
+                             std::unique_ptr<he_batch>& bt) {
+  if (!c || !items || !ws || n == 0) return fail(HE_EINVAL, "he_batch_create: bad arguments");
   for (u32 i = 0; i < n; ++i) {
     const he_batch_item& it = items[i];
     if (!it.ct1 || !it.ct2 || (!it.relin && !it.out)) return fail(HE_EINVAL, "he_batch_create: item %u incomplete", i);
@@ -845,8 +850,7 @@ he_status he_batch_create(he_ctx* c, const he_batch_item* items, uint32_t n, voi
     if (it.out && it.level < 2) return fail(HE_ELEVEL, "he_batch_create: item %u: rescale needs level >= 2", i);
   }
   if (ws_bytes < batch_ws_words(c, items, n) * 8) return fail(HE_ENOMEM, "he_batch_create: workspace too small");
-  HIP_TRY(hipSetDevice(c->device));
-  std::unique_ptr<he_batch> bt(new he_batch);
+  bt.reset(new he_batch);
   bt->ctx = c;
   bt->n = n;
   std::vector<PairDesc> pds(n);
@@ -879,19 +883,52 @@ he_status he_batch_create(he_ctx* c, const he_batch_item* items, uint32_t n, voi
     bt->nitems[s] = (u32)acc;
   }
   const size_t pbytes = sizeof(PairDesc) * n, obytes = sizeof(u32) * offs.size();
-  HIP_TRY(hipMalloc(&bt->dev, pbytes + obytes));
-  std::vector<uint8_t> host(pbytes + obytes);
-  memcpy(host.data(), pds.data(), pbytes);
-  memcpy(host.data() + pbytes, offs.data(), obytes);
-  {
-    hipError_t e = hipMemcpy(bt->dev, host.data(), host.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(bt->dev);
-      return fail(HE_EDEVICE, "he_batch_create: upload failed: %s", hipGetErrorString(e));
-    }
+  bt->host.resize(pbytes + obytes);
+  memcpy(bt->host.data(), pds.data(), pbytes);
+  memcpy(bt->host.data() + pbytes, offs.data(), obytes);
+  return HE_OK;
+}
+
+static void batch_bind(he_batch* bt, void* dev) {
+  bt->dev = dev;
+  bt->pairs = (const PairDesc*)dev;
+  const size_t pbytes = sizeof(PairDesc) * bt->n;
+  for (int s = 0; s < ST_COUNT; ++s)
+    bt->offs[s] = (const u32*)((uint8_t*)dev + pbytes) + (size_t)s * (bt->n + 1);
+}
+
+he_status he_batch_create(he_ctx* c, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
+                          he_batch** out) {
+  if (!out) return fail(HE_EINVAL, "he_batch_create: null output");
+  *out = nullptr;
+  std::unique_ptr<he_batch> bt;
+  he_status r = batch_build(c, items, n, ws, ws_bytes, bt);
+  if (r != HE_OK) return r;
+  HIP_TRY(hipSetDevice(c->device));
+  void* dev = nullptr;
+  HIP_TRY(hipMalloc(&dev, bt->host.size()));
+  const hipError_t e = hipMemcpy(dev, bt->host.data(), bt->host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    return fail(HE_EDEVICE, "he_batch_create: upload failed: %s", hipGetErrorString(e));
   }
-  bt->pairs = (const PairDesc*)bt->dev;
-  for (int s = 0; s < ST_COUNT; ++s) bt->offs[s] = (const u32*)((uint8_t*)bt->dev + pbytes) + (size_t)s * (n + 1);
+  batch_bind(bt.get(), dev);
+  *out = bt.release();
+  return HE_OK;
+}
+
+he_status he_batch_create_async(he_ctx* c, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
+                                void* d_desc, size_t desc_bytes, he_stream stream, he_batch** out) {
+  if (!out || !d_desc) return fail(HE_EINVAL, "he_batch_create_async: null pointer");
+  *out = nullptr;
+  if (desc_bytes < he_batch_desc_bytes(n)) return fail(HE_ENOMEM, "he_batch_create_async: descriptor memory too small");
+  std::unique_ptr<he_batch> bt;
+  he_status r = batch_build(c, items, n, ws, ws_bytes, bt);
+  if (r != HE_OK) return r;
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(d_desc, bt->host.data(), bt->host.size(), hipMemcpyHostToDevice, (hipStream_t)stream));
+  bt->owns_dev = false;
+  batch_bind(bt.get(), d_desc);
   *out = bt.release();
   return HE_OK;
 }
@@ -949,7 +986,7 @@ void he_batch_destroy(he_batch* bt) {
   (void)hipSetDevice(bt->ctx->device);
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
-  if (bt->dev) (void)hipFree(bt->dev);
+  if (bt->dev && bt->owns_dev) (void)hipFree(bt->dev);
   delete bt;
 }
 
