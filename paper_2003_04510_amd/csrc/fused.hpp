@@ -93,7 +93,7 @@ struct Common {
   const u64* evk;   // [dnum][2][L+K][N]
   const u64* pinv;  // Shoup pairs [P^-1]_{q_i}
   const u32* iota;  // 0, 1, 2, ...
-  u32 L, K, log_n, pad;
+  u32 L, K, log_n, dnum;
 };
 
 // Which pairs a launch covers.
@@ -212,32 +212,58 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
   const u64 blk0 = (u64)pos * PL::SUBS;
   const u64 off = ((u64)i << c.log_n) + (blk0 << LOGS);
   const int sub = PL::sub(), tt = PL::tt();
-#pragma unroll
-  for (int k = 0; k < Gm::R; ++k) {
-    const u64 idx = off + threadIdx.x + k * THREADS;
-    const u64 b1 = pd.ct1[idx], a1 = pd.ct1[tot + idx], b2 = pd.ct2[idx], a2 = pd.ct2[tot + idx];
-    u64 v;
-    if (which == 2) {
-      const u64 d0 = barrett(mul_wide(b1, b2), m);
-      U128 s1 = mul_wide(a1, b2);
-      add_to(s1, mul_wide(a2, b1));
-      const u64 d1 = barrett(s1, m);
-      v = barrett(mul_wide(a1, a2), m);
-      pd.rl[idx] = d0;
-      pd.rl[tot + idx] = d1;
-      pd.d2[idx] = v;
-    } else if (which == 0) {
-      v = barrett(mul_wide(b1, b2), m);
-    } else {
-      U128 s1 = mul_wide(a1, b2);
-      add_to(s1, mul_wide(a2, b1));
-      v = barrett(s1, m);
-    }
+  const auto ct1 = gbl(pd.ct1 + off), ct2 = gbl(pd.ct2 + off);
+  const auto put = [&](int k, u64 v) {
     const int e = threadIdx.x + k * THREADS;
     lds[(e >> LOGS) * Gm::SUB + Gm::pad(e & (Gm::S - 1))] = v;
+  };
+  // Operands are loaded TG elements at a time before any result is stored,
+  // so each thread keeps 4 TG loads in flight.
+  constexpr int TG = Gm::R < 8 ? Gm::R : 8;
+  if (which == 2) {
+    const auto rl0 = gbl(pd.rl + off), rl1 = gbl(pd.rl + tot + off), d2 = gbl(pd.d2 + off);
+#pragma unroll
+    for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+      u64 b1[TG], a1[TG], b2[TG], a2[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const u64 idx = threadIdx.x + (k0 + g) * THREADS;
+        b1[g] = ct1[idx]; a1[g] = ct1[tot + idx]; b2[g] = ct2[idx]; a2[g] = ct2[tot + idx];
+      }
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const u64 idx = threadIdx.x + (k0 + g) * THREADS;
+        U128 s1 = mul_wide(a1[g], b2[g]);
+        add_to(s1, mul_wide(a2[g], b1[g]));
+        const u64 v = barrett(mul_wide(a1[g], a2[g]), m);
+        rl0[idx] = barrett(mul_wide(b1[g], b2[g]), m);
+        rl1[idx] = barrett(s1, m);
+        d2[idx] = v;
+        put(k0 + g, v);
+      }
+    }
+  } else {  // d0 (which 0) or d1 (which 1) of limb level-1, for the rescale
+    const u64 h = which == 0 ? 0 : tot;
+#pragma unroll
+    for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+      u64 x1[TG], x2[TG], y1[TG], y2[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const u64 idx = threadIdx.x + (k0 + g) * THREADS;
+        x1[g] = ct1[h + idx]; y2[g] = ct2[idx];
+        y1[g] = ct1[idx]; x2[g] = ct2[h + idx];
+      }
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        // which 0: b1 b2; which 1: a1 b2 + a2 b1
+        U128 s1 = mul_wide(x1[g], y2[g]);
+        if (which == 1) add_to(s1, mul_wide(x2[g], y1[g]));
+        put(k0 + g, barrett(s1, m));
+      }
+    }
   }
   __syncthreads();
-  u64* out = pd.y + ((u64)r << c.log_n) + (blk0 << LOGS) + ((u64)sub << LOGS);
+  const auto out = gbl(pd.y + ((u64)r << c.log_n) + (blk0 << LOGS) + ((u64)sub << LOGS));
   u64* tile = lds + sub * Gm::SUB;
   u64 x[Gm::R];
   lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
@@ -300,8 +326,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c,
   const u64 q = ldc(&c.mods[mi].q);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 col = (u64)pos * PL::SUBS + sub;
-  const u64* in = v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + col;
-  u64* out = v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + col;
+  const auto in = gbl(v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + col);
+  const auto out = gbl(v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + col);
   u64 sw = ldc(&c.mods[mi].ninv), sws = ldc(&c.mods[mi].ninvs);
   if (!FWD && v.scale) {
     sw = ldc(v.scale + 2 * (u64)limb);
@@ -344,8 +370,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
   const u64 q = ldc(&c.mods[mi].q);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 blk0 = (u64)pos * PL::SUBS;
-  const u64* in0 = v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + (blk0 << LOGS);
-  u64* out0 = v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + (blk0 << LOGS);
+  const auto in0 = gbl(v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + (blk0 << LOGS));
+  const auto out0 = gbl(v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + (blk0 << LOGS));
   u64* tile = lds + sub * Gm::SUB;
   u64 x[Gm::R];
   if constexpr (!FWD) {
@@ -357,13 +383,13 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
     __syncthreads();
     lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
   } else {
-    const u64* in = in0 + ((u64)sub << LOGS);
+    const auto in = in0 + ((u64)sub << LOGS);
 #pragma unroll
     for (int u = 0; u < RF::NG; ++u)
 #pragma unroll
       for (int i = 0; i < RF::G; ++i) x[u * RF::G + i] = in[RF::elem(tt, u, i)];
   }
-  u64* out = out0 + ((u64)sub << LOGS);
+  const auto out = out0 + ((u64)sub << LOGS);
   sub_transform_regs<FWD, LOGS, LOGR, FWD>(x, tile, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
                                            (1ull << n1) + blk0 + sub, q,
                                            [&](int e, u64 val) { out[e] = ntt_canon<FWD>(val, q); });
@@ -386,7 +412,11 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
 // Mod up: sources y, outputs dt (jobs = digits).  Mod down: sources the
 // special limbs of ks (coefficient form), outputs zc, one job per polynomial.
 // Items (job or polynomial, target group, coefficient chunk).
-template <bool MD>
+// NSMAX bounds the number of sources (the digit size for mod up, K for mod
+// down): all NSMAX source loads are issued unconditionally (index clamped to
+// the job's ns, constants of unused sources zero), so each thread waits for
+// its loads once instead of once per source.
+template <bool MD, int NSMAX>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
@@ -406,17 +436,16 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 per = (J.nt + CONV_GROUPS - 1) / CONV_GROUPS;
   const u32 t0 = grp * per, t1 = min(J.nt, t0 + per);
   const u64 n0 = ((u64)chunk * CONV_THREADS + threadIdx.x) * CONV_CPT;
-  const u64* s0 = src + ((u64)J.src_off << c.log_n) + n0;
-  u32 y0[15][CONV_CPT], y1[15][CONV_CPT];
+  const auto s0 = gbl(src + ((u64)J.src_off << c.log_n) + n0);
+  u32 y0[NSMAX][CONV_CPT], y1[NSMAX][CONV_CPT];
 #pragma unroll
-  for (int s = 0; s < 15; ++s) {
-    if (s < (int)J.ns) {
+  for (int s = 0; s < NSMAX; ++s) {
+    const u32 sc = min((u32)s, J.ns - 1);
 #pragma unroll
-      for (int k = 0; k < CONV_CPT; ++k) {
-        const u64 y = s0[((u64)s << c.log_n) + k];
-        y0[s][k] = (u32)(y & M30);
-        y1[s][k] = (u32)(y >> 30);
-      }
+    for (int k = 0; k < CONV_CPT; ++k) {
+      const u64 y = s0[((u64)sc << c.log_n) + k];
+      y0[s][k] = (u32)(y & M30);
+      y1[s][k] = (u32)(y >> 30);
     }
   }
   for (u32 t = t0; t < t1; ++t) {
@@ -427,23 +456,26 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
 #pragma unroll
-    for (int s = 0; s < 15; ++s) {
-      if (s < (int)J.ns) {
-        const u32 c0 = ldc(C + 2 * s), c1 = ldc(C + 2 * s + 1);
+    for (int s = 0; s < NSMAX; ++s) {
+      const u32 sc = min((u32)s, T.ns - 1);
+      const bool use = (u32)s < T.ns;
+      const u32 c0 = use ? ldc(C + 2 * sc) : 0u, c1 = use ? ldc(C + 2 * sc + 1) : 0u;
 #pragma unroll
-        for (int k = 0; k < CONV_CPT; ++k) {
-          sll[k] += (u64)y0[s][k] * c0;
-          slh[k] += (u64)y0[s][k] * c1;
-          shl[k] += (u64)y1[s][k] * c0;
-          shh[k] += (u64)y1[s][k] * c1;
-        }
+      for (int k = 0; k < CONV_CPT; ++k) {
+        sll[k] += (u64)y0[s][k] * c0;
+        slh[k] += (u64)y0[s][k] * c1;
+        shl[k] += (u64)y1[s][k] * c0;
+        shh[k] += (u64)y1[s][k] * c1;
       }
     }
-    u64* o = dst + ((u64)(J.dst_off + t) << c.log_n) + n0;
+    const auto o = gbl(dst + ((u64)(J.dst_off + t) << c.log_n) + n0);
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) o[k] = conv_finish(sll[k], slh[k], shl[k], shh[k], m);
   }
 }
+
+// Smallest source bound bucket covering ns (ns <= 15).
+inline int conv_bucket(u32 ns) { return ns <= 4 ? 4 : ns <= 8 ? 8 : ns <= 12 ? 12 : 15; }
 
 // ---------------------------------------------------------------- inner product
 // ks_u[e] = sum_j dt_j[e] * evk_j.u[e] for every limb e of the extended basis;
@@ -467,28 +499,46 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
   U128 accb[IP_CPT], acca[IP_CPT];
 #pragma unroll
   for (int k = 0; k < IP_CPT; ++k) accb[k] = acca[k] = U128{0, 0};
-  for (u32 j = 0; j < beta; ++j) {
-    const u32 lo = ldc(&P->lo[j]), cnt = ldc(&P->cnt[j]);
-    const u64* x;
-    if (e < pd.level && e >= lo && e < lo + cnt) {
-      x = pd.d2 + ((u64)e << c.log_n);
-    } else {
-      const u32 o = e < lo ? e : e - cnt;
-      x = pd.dt + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n);
-    }
-    const u64* eb = c.evk + ((((u64)j * 2) * nm + mi) << c.log_n);
-    const u64* ea = eb + (nm << c.log_n);
+  // Digits are taken JG at a time; all their loads are issued before any
+  // accumulation (indices of digits past beta are clamped, their terms zeroed).
+  constexpr int JG = 3;
+  for (u32 j0 = 0; j0 < beta; j0 += JG) {
+    u64 xv[JG][IP_CPT], bv[JG][IP_CPT], av[JG][IP_CPT];
 #pragma unroll
-    for (int k = 0; k < IP_CPT; ++k) {
-      const u64 xv = x[n0 + k];
-      add_to(accb[k], mul_wide(xv, eb[n0 + k]));
-      add_to(acca[k], mul_wide(xv, ea[n0 + k]));
+    for (int jj = 0; jj < JG; ++jj) {
+      const u32 j = min(j0 + jj, beta - 1);
+      const u32 lo = ldc(&P->lo[j]), cnt = ldc(&P->cnt[j]);
+      gptr<const u64> x;
+      if (e < pd.level && e >= lo && e < lo + cnt) {
+        x = gbl(pd.d2 + ((u64)e << c.log_n));
+      } else {
+        const u32 o = e < lo ? e : e - cnt;
+        x = gbl(pd.dt + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n));
+      }
+      const auto eb = gbl(c.evk + ((((u64)j * 2) * nm + mi) << c.log_n));
+      const auto ea = eb + (nm << c.log_n);
+#pragma unroll
+      for (int k = 0; k < IP_CPT; ++k) {
+        xv[jj][k] = x[n0 + k];
+        bv[jj][k] = eb[n0 + k];
+        av[jj][k] = ea[n0 + k];
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JG; ++jj) {
+      const bool use = j0 + jj < beta;  // a select, not a branch, keeps the loads above
+#pragma unroll
+      for (int k = 0; k < IP_CPT; ++k) {
+        const u64 xm = use ? xv[jj][k] : 0;
+        add_to(accb[k], mul_wide(xm, bv[jj][k]));
+        add_to(acca[k], mul_wide(xm, av[jj][k]));
+      }
     }
   }
   const u64 kz = (u64)(pd.level + c.K + 1) << c.log_n;
-  u64* ob = pd.ks + ((u64)e << c.log_n) + n0;
+  const auto ob = gbl(pd.ks + ((u64)e << c.log_n) + n0);
   const bool last = pd.rs && e == pd.level - 1;
-  u64* xb = pd.ks + ((u64)(pd.level + c.K) << c.log_n) + n0;
+  const auto xb = gbl(pd.ks + ((u64)(pd.level + c.K) << c.log_n) + n0);
 #pragma unroll
   for (int k = 0; k < IP_CPT; ++k) {
     const u64 vb = barrett(accb[k], m), va = barrett(acca[k], m);
@@ -524,7 +574,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   u64 x[Gm::R];
-  const u64* p = pd.z + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS);
+  const auto p = gbl(pd.z + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS));
 #pragma unroll
   for (int uu = 0; uu < RF::NG; ++uu)
 #pragma unroll
@@ -533,14 +583,25 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
                                              (1ull << n1) + blk0 + sub, m.q, [](int, u64) {});
   __syncthreads();
   const u64 pw = ldc(c.pinv + 2 * i), pws = ldc(c.pinv + 2 * i + 1);
-  const u64* ksu = pd.ks + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff;
-  u64* rlu = pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff;
+  const auto ksu = gbl(pd.ks + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff);
+  const auto rlu = gbl(pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff);
+  constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
 #pragma unroll
-  for (int k = 0; k < Gm::R; ++k) {
-    const int idx = threadIdx.x + k * THREADS;
-    const u64 Z = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], m.q);
-    const u64 md = shoup_lazy(ksu[idx] + m.q - Z, pw, pws, m.q);
-    rlu[idx] = csub(csub(rlu[idx] + md, m.q << 1), m.q);
+  for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+    u64 kv[TG], dv[TG];
+#pragma unroll
+    for (int g = 0; g < TG; ++g) {
+      const int idx = threadIdx.x + (k0 + g) * THREADS;
+      kv[g] = ksu[idx];
+      dv[g] = rlu[idx];
+    }
+#pragma unroll
+    for (int g = 0; g < TG; ++g) {
+      const int idx = threadIdx.x + (k0 + g) * THREADS;
+      const u64 Z = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], m.q);
+      const u64 md = shoup_lazy(kv[g] + m.q - Z, pw, pws, m.q);
+      rlu[idx] = csub(csub(dv[g] + md, m.q << 1), m.q);
+    }
   }
 }
 
@@ -575,28 +636,41 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
   const int sub = PL::sub(), tt = PL::tt();
   const u64 N = 1ull << c.log_n;
   const u64 col = (u64)pos * PL::SUBS + sub;
-  const u64* rr = pd.r ? pd.r + (u64)u * N + col : nullptr;
-  const u64* dd = pd.y + ((u64)(pd.level + u) << c.log_n) + col;
-  const u64* kk = pd.ks + ((u64)u * (pd.level + c.K + 1) + pd.level + c.K) * N + col;
-  const u64* zz = pd.zc + ((u64)u * pd.level + pd.level - 1) * N + col;
+  const bool given = pd.r != nullptr;
+  const auto rr = gbl(pd.r + (given ? (u64)u * N + col : 0));
+  const auto dd = gbl(pd.y + ((u64)(pd.level + u) << c.log_n) + col);
+  const auto kk = gbl(pd.ks + ((u64)u * (pd.level + c.K + 1) + pd.level + c.K) * N + col);
+  const auto zz = gbl(pd.zc + ((u64)u * pd.level + pd.level - 1) * N + col);
+  // r = pd.r, or INTT(d) plus the correction; loads are grouped so that no
+  // element waits for its own loads alone.
   u64 x[Gm::R];
+  const auto first = given ? rr : dd;
 #pragma unroll
-  for (int uu = 0; uu < RF::NG; ++uu) {
+  for (int k = 0; k < Gm::R; ++k) x[k] = first[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
+  if (!given) {
+    constexpr int TG = Gm::R < 8 ? Gm::R : 8;
 #pragma unroll
-    for (int ii = 0; ii < RF::G; ++ii) {
-      const u64 e = (u64)RF::elem(tt, uu, ii) << n2;
-      u64 r;
-      if (rr) {
-        r = rr[e];
-      } else {
-        r = csub(dd[e] + csub(shoup_lazy(kk[e] + ql - zz[e], pw, pws, ql), ql), ql);
+    for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+      u64 kv[TG], zv[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const u64 e = (u64)RF::elem(tt, (k0 + g) / RF::G, (k0 + g) % RF::G) << n2;
+        kv[g] = kk[e];
+        zv[g] = zz[e];
       }
-      u64 v = csub(r - mulhi(r, m.one_s) * m.q, m.q);  // r mod q_i
-      if (2 * r >= ql) v = submod(v, qlm, m.q);
-      x[uu * RF::G + ii] = v;
+#pragma unroll
+      for (int g = 0; g < TG; ++g)
+        x[k0 + g] = csub(x[k0 + g] + csub(shoup_lazy(kv[g] + ql - zv[g], pw, pws, ql), ql), ql);
     }
   }
-  u64* out = pd.z + ((u64)(u * nl + i) << c.log_n) + col;
+#pragma unroll
+  for (int k = 0; k < Gm::R; ++k) {
+    const u64 r = x[k];
+    u64 v = csub(r - mulhi(r, m.one_s) * m.q, m.q);  // r mod q_i
+    if (2 * r >= ql) v = submod(v, qlm, m.q);
+    x[k] = v;
+  }
+  const auto out = gbl(pd.z + ((u64)(u * nl + i) << c.log_n) + col);
   sub_transform_regs<true, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n), 1, m.q,
                                                [&](int e, u64 v) { out[(u64)e << n2] = ntt_canon<true>(v, m.q); });
 }
@@ -626,7 +700,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   u64 x[Gm::R];
-  const u64* p = pd.z + ((u64)(u * nl + i) << c.log_n) + toff + ((u64)sub << LOGS);
+  const auto p = gbl(pd.z + ((u64)(u * nl + i) << c.log_n) + toff + ((u64)sub << LOGS));
 #pragma unroll
   for (int uu = 0; uu < RF::NG; ++uu)
 #pragma unroll
@@ -636,13 +710,20 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
   __syncthreads();
   const u64* ql = ldc(&P->qlinv);
   const u64 qw = ldc(ql + 2 * i), qws = ldc(ql + 2 * i + 1);
-  const u64* cu = pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff;
-  u64* ou = pd.out + ((u64)(u * nl + i) << c.log_n) + toff;
+  const auto cu = gbl(pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff);
+  const auto ou = gbl(pd.out + ((u64)(u * nl + i) << c.log_n) + toff);
+  constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
 #pragma unroll
-  for (int k = 0; k < Gm::R; ++k) {
-    const int idx = threadIdx.x + k * THREADS;
-    const u64 S = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], m.q);
-    ou[idx] = csub(shoup_lazy(cu[idx] + m.q - S, qw, qws, m.q), m.q);
+  for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+    u64 cv[TG];
+#pragma unroll
+    for (int g = 0; g < TG; ++g) cv[g] = cu[threadIdx.x + (k0 + g) * THREADS];
+#pragma unroll
+    for (int g = 0; g < TG; ++g) {
+      const int idx = threadIdx.x + (k0 + g) * THREADS;
+      const u64 S = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], m.q);
+      ou[idx] = csub(shoup_lazy(cv[g] + m.q - S, qw, qws, m.q), m.q);
+    }
   }
 }
 

@@ -618,23 +618,29 @@ void launch_lblocks(const Common& c, const Batch& b, hipStream_t st) {
                      st, c, b);
 }
 
+template <bool MD>
+void launch_conv(int bucket, const Common& c, const Batch& b, hipStream_t st) {
+  switch (bucket) {
+    case 4: hipLaunchKernelGGL((k_conv<MD, 4>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+    case 8: hipLaunchKernelGGL((k_conv<MD, 8>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+    case 12: hipLaunchKernelGGL((k_conv<MD, 12>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+    default: hipLaunchKernelGGL((k_conv<MD, 15>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+  }
+}
+
 // n1 = log_n / 2 (cols passes), n2 = log_n - n1 (blocks passes)
 template <int N1, int N2>
 void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) {
   switch (stage) {
     case ST_TENSOR: launch_tensor<N2, EPW_B>(c, b, st); break;
     case ST_Y_ICOLS: launch_lcols<false, N1, ST_Y_ICOLS>(c, b, st); break;
-    case ST_MU_CONV:
-      hipLaunchKernelGGL(k_conv<false>, dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b);
-      break;
+    case ST_MU_CONV: launch_conv<false>(conv_bucket((c.L + c.dnum - 1) / c.dnum), c, b, st); break;
     case ST_DT_NCOLS: launch_lcols<true, N1, ST_DT_NCOLS>(c, b, st); break;
     case ST_DT_NBLOCKS: launch_lblocks<true, N2, ST_DT_NBLOCKS>(c, b, st); break;
     case ST_IP: hipLaunchKernelGGL(k_ip, dim3(pad8(b.nitems)), dim3(IP_THREADS), 0, st, c, b); break;
     case ST_KS_IBLOCKS: launch_lblocks<false, N2, ST_KS_IBLOCKS>(c, b, st); break;
     case ST_KS_ICOLS: launch_lcols<false, N1, ST_KS_ICOLS>(c, b, st); break;
-    case ST_MD_CONV:
-      hipLaunchKernelGGL(k_conv<true>, dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b);
-      break;
+    case ST_MD_CONV: launch_conv<true>(conv_bucket(c.K), c, b, st); break;
     case ST_Z_NCOLS: launch_lcols<true, N1, ST_Z_NCOLS>(c, b, st); break;
     case ST_COMBINE:
       hipLaunchKernelGGL((k_ntt_combine<N2, EPW_B>), dim3(pad8(b.nitems)), dim3(pass_threads(N2, EPW_B)), 0, st, c,
@@ -706,7 +712,7 @@ void launch_stage(const he_ctx* c, int stage, const Common& cm, const Batch& b, 
 Common make_common(const he_ctx* c, const u64* evk) {
   Common cm{};
   cm.mods = c->mods; cm.tw = c->tw; cm.itw = c->itw; cm.evk = evk; cm.pinv = c->pinv; cm.iota = c->iota;
-  cm.L = c->L; cm.K = c->K; cm.log_n = c->log_n;
+  cm.L = c->L; cm.K = c->K; cm.log_n = c->log_n; cm.dnum = c->dnum;
   return cm;
 }
 

@@ -34,6 +34,18 @@ __device__ __forceinline__ T ldc(const T* p) {
   return r;
 }
 
+// HBM pointers that reach a kernel inside a struct are generic pointers to
+// the compiler, which then emits flat accesses: those count against the LDS
+// counter too and must be ordered against LDS accesses that might alias, so
+// a load followed by an LDS store waits for the load.  Accessing HBM through
+// the global address space avoids both.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gbl(T* p) {
+  return (gptr<T>)p;
+}
+
 // A value every lane of the wavefront holds, moved to a scalar register.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 

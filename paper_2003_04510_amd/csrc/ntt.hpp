@@ -298,8 +298,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols(NttArgs a)
   const int n2 = a.log_n - LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   const u64 col = (u64)blockIdx.x * PL::SUBS + sub;
-  const u64* in = a.src + (u64)limb * a.src_stride + (u64)blockIdx.z * a.src_zstride + col;
-  u64* out = a.dst + (u64)limb * a.dst_stride + (u64)blockIdx.z * a.dst_zstride + col;
+  const auto in = gbl(a.src + (u64)limb * a.src_stride + (u64)blockIdx.z * a.src_zstride + col);
+  const auto out = gbl(a.dst + (u64)limb * a.dst_stride + (u64)blockIdx.z * a.dst_zstride + col);
   u64 w = a.mods[mi].ninv, ws = a.mods[mi].ninvs;
   if (!FWD && a.scale) {
     w = a.scale[2 * (u64)limb];
@@ -330,10 +330,10 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_blocks(NttArgs 
   const int sub = PL::sub(), tt = PL::tt();
   const u64 blk0 = (u64)blockIdx.x * PL::SUBS;
   const u64 blk = blk0 + sub;
-  const u64* in0 = a.src + (u64)limb * a.src_stride + (u64)blockIdx.z * a.src_zstride + (blk0 << LOGS);
-  u64* out0 = a.dst + (u64)limb * a.dst_stride + (u64)blockIdx.z * a.dst_zstride + (blk0 << LOGS);
-  const u64* in = in0 + ((u64)sub << LOGS);
-  u64* out = out0 + ((u64)sub << LOGS);
+  const auto in0 = gbl(a.src + (u64)limb * a.src_stride + (u64)blockIdx.z * a.src_zstride + (blk0 << LOGS));
+  const auto out0 = gbl(a.dst + (u64)limb * a.dst_stride + (u64)blockIdx.z * a.dst_zstride + (blk0 << LOGS));
+  const auto in = in0 + ((u64)sub << LOGS);
+  const auto out = out0 + ((u64)sub << LOGS);
   constexpr bool IN_LDS = LDS_IO && !FWD, OUT_LDS = LDS_IO && FWD;
   if constexpr (IN_LDS) {
     for (int idx = threadIdx.x; idx < PL::SUBS * Gm::S; idx += THREADS)
