@@ -11,7 +11,8 @@ LIB = os.path.join(HERE, "libhe_mi355x.so")
 SOURCES = ["he_lib.hip", "host_math.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off", "-fno-strict-aliasing",
+         "-Wall", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:

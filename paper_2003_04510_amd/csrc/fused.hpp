@@ -262,13 +262,21 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
   const auto out = gbl(pd.y + ((u64)r << c.log_n) + (blk0 << LOGS) + ((u64)sub << LOGS));
-  u64* tile = lds + sub * Gm::SUB;
-  u64 x[Gm::R];
-  lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
-  sub_transform_regs<false, LOGS, LOGR, false>(x, tile, tt, c.itw + ((u64)i << c.log_n), (1ull << n1) + blk0 + sub,
-                                                m.q, [&](int e, u64 v) { out[e] = csub(v, m.q); });
+  u64 xi[Gm::R];
+  lds_get<LOGS, LOGR, FIRST>(lds + sub * Gm::SUB, xi, tt);
+  // the transform writes only tile positions this thread has just read
+  with_arith(m.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(m.q, m.qinv);
+    typename A::V x[Gm::R];
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    sub_transform_regs<A, false, LOGS, LOGR, false>(
+        x, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, c.itw + ((u64)i << c.log_n),
+        (1ull << n1) + blk0 + sub, M, [&](int e, typename A::V v) { out[e] = A::template out<false>(v, M); });
+  });
 }
 
 // ---------------------------------------------------------------- NTT passes over limb lists
@@ -323,26 +331,32 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c,
   const u32 pos = uniform(local % tpc), rest = local / tpc;
   const u32 limb = uniform(rest % v.nl), z = uniform(rest / v.nl);
   const u32 mi = ldc(v.limb_mod + limb);
-  const u64 q = ldc(&c.mods[mi].q);
+  const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 col = (u64)pos * PL::SUBS + sub;
   const auto in = gbl(v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + col);
   const auto out = gbl(v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + col);
-  u64 sw = ldc(&c.mods[mi].ninv), sws = ldc(&c.mods[mi].ninvs);
+  u64 sw = mo.ninv, sws = mo.ninvs;
   if (!FWD && v.scale) {
     sw = ldc(v.scale + 2 * (u64)limb);
     sws = ldc(v.scale + 2 * (u64)limb + 1);
   }
-  u64 x[Gm::R];
+  u64 xi[Gm::R];
 #pragma unroll
-  for (int u = 0; u < RF::NG; ++u)
+  for (int k = 0; k < Gm::R; ++k) xi[k] = in[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
+  with_arith(mo.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(mo.q, mo.qinv);
+    const typename A::Scale sc = A::scale(sw, sws, M);
+    typename A::V x[Gm::R];
 #pragma unroll
-    for (int i = 0; i < RF::G; ++i) x[u * RF::G + i] = in[(u64)RF::elem(tt, u, i) << n2];
-  sub_transform_regs<FWD, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n), 1,
-                                             q, [&](int e, u64 val) {
-                                               out[(u64)e << n2] =
-                                                   FWD ? ntt_canon<true>(val, q) : csub(shoup_lazy(val, sw, sws, q), q);
-                                             });
+    for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    sub_transform_regs<A, FWD, LOGS, LOGR, false>(
+        x, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n), 1,
+        M, [&](int e, typename A::V val) {
+          out[(u64)e << n2] = FWD ? A::template out<true>(val, M) : A::out_scaled(val, sc, M);
+        });
+  });
 }
 
 // Blocks pass; the side whose register layout is thread-contiguous
@@ -367,40 +381,46 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
   const u32 pos = uniform(local % tpl), rest = local / tpl;
   const u32 limb = uniform(rest % v.nl), z = uniform(rest / v.nl);
   const u32 mi = ldc(v.limb_mod + limb);
-  const u64 q = ldc(&c.mods[mi].q);
+  const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 blk0 = (u64)pos * PL::SUBS;
   const auto in0 = gbl(v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + (blk0 << LOGS));
   const auto out0 = gbl(v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + (blk0 << LOGS));
-  u64* tile = lds + sub * Gm::SUB;
-  u64 x[Gm::R];
+  u64 xi[Gm::R];
   if constexpr (!FWD) {
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) {
       const int idx = threadIdx.x + k * THREADS;
       lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))] = in0[idx];
     }
-    __syncthreads();
-    lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
+    lds_barrier();
+    // the transform writes only tile positions this thread has just read
+    lds_get<LOGS, LOGR, FIRST>(lds + sub * Gm::SUB, xi, tt);
   } else {
     const auto in = in0 + ((u64)sub << LOGS);
 #pragma unroll
-    for (int u = 0; u < RF::NG; ++u)
-#pragma unroll
-      for (int i = 0; i < RF::G; ++i) x[u * RF::G + i] = in[RF::elem(tt, u, i)];
+    for (int k = 0; k < Gm::R; ++k) xi[k] = in[RF::elem(tt, k / RF::G, k % RF::G)];
   }
   const auto out = out0 + ((u64)sub << LOGS);
-  sub_transform_regs<FWD, LOGS, LOGR, FWD>(x, tile, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
-                                           (1ull << n1) + blk0 + sub, q,
-                                           [&](int e, u64 val) { out[e] = ntt_canon<FWD>(val, q); });
-  if constexpr (FWD) {
-    __syncthreads();
+  with_arith(mo.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(mo.q, mo.qinv);
+    typename A::V* tl = reinterpret_cast<typename A::V*>(lds);
+    typename A::V x[Gm::R];
 #pragma unroll
-    for (int k = 0; k < Gm::R; ++k) {
-      const int idx = threadIdx.x + k * THREADS;
-      out0[idx] = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], q);
+    for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    sub_transform_regs<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
+                                                (1ull << n1) + blk0 + sub, M,
+                                                [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); });
+    if constexpr (FWD) {
+      lds_barrier();
+#pragma unroll
+      for (int k = 0; k < Gm::R; ++k) {
+        const int idx = threadIdx.x + k * THREADS;
+        out0[idx] = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
+      }
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------- base conversion
@@ -573,36 +593,42 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
-  u64 x[Gm::R];
+  u64 xi[Gm::R];
   const auto p = gbl(pd.z + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS));
 #pragma unroll
-  for (int uu = 0; uu < RF::NG; ++uu)
-#pragma unroll
-    for (int ii = 0; ii < RF::G; ++ii) x[uu * RF::G + ii] = p[RF::elem(tt, uu, ii)];
-  sub_transform_regs<true, LOGS, LOGR, true>(x, lds + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
-                                             (1ull << n1) + blk0 + sub, m.q, [](int, u64) {});
-  __syncthreads();
+  for (int k = 0; k < Gm::R; ++k) xi[k] = p[RF::elem(tt, k / RF::G, k % RF::G)];
   const u64 pw = ldc(c.pinv + 2 * i), pws = ldc(c.pinv + 2 * i + 1);
   const auto ksu = gbl(pd.ks + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff);
   const auto rlu = gbl(pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff);
-  constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
+  with_arith(m.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(m.q, m.qinv);
+    typename A::V* tl = reinterpret_cast<typename A::V*>(lds);
+    typename A::V x[Gm::R];
 #pragma unroll
-  for (int k0 = 0; k0 < Gm::R; k0 += TG) {
-    u64 kv[TG], dv[TG];
+    for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
+                                                  (1ull << n1) + blk0 + sub, M, [](int, typename A::V) {});
+    lds_barrier();
+    constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
 #pragma unroll
-    for (int g = 0; g < TG; ++g) {
-      const int idx = threadIdx.x + (k0 + g) * THREADS;
-      kv[g] = ksu[idx];
-      dv[g] = rlu[idx];
+    for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+      u64 kv[TG], dv[TG];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const int idx = threadIdx.x + (k0 + g) * THREADS;
+        kv[g] = ksu[idx];
+        dv[g] = rlu[idx];
+      }
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const int idx = threadIdx.x + (k0 + g) * THREADS;
+        const u64 Z = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
+        const u64 md = shoup_lazy(kv[g] + m.q - Z, pw, pws, m.q);
+        rlu[idx] = csub(csub(dv[g] + md, m.q << 1), m.q);
+      }
     }
-#pragma unroll
-    for (int g = 0; g < TG; ++g) {
-      const int idx = threadIdx.x + (k0 + g) * THREADS;
-      const u64 Z = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], m.q);
-      const u64 md = shoup_lazy(kv[g] + m.q - Z, pw, pws, m.q);
-      rlu[idx] = csub(csub(dv[g] + md, m.q << 1), m.q);
-    }
-  }
+  });
 }
 
 // ---------------------------------------------------------------- rescale lift + NTT cols
@@ -671,8 +697,16 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
     x[k] = v;
   }
   const auto out = gbl(pd.z + ((u64)(u * nl + i) << c.log_n) + col);
-  sub_transform_regs<true, LOGS, LOGR, false>(x, lds + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n), 1, m.q,
-                                               [&](int e, u64 v) { out[(u64)e << n2] = ntt_canon<true>(v, m.q); });
+  with_arith(m.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(m.q, m.qinv);
+    typename A::V xa[Gm::R];
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) xa[k] = A::in(x[k], M);
+    sub_transform_regs<A, true, LOGS, LOGR, false>(
+        xa, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n), 1, M,
+        [&](int e, typename A::V v) { out[(u64)e << n2] = A::template out<true>(v, M); });
+  });
 }
 
 // ---------------------------------------------------------------- NTT blocks + rescale combine
@@ -699,32 +733,38 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
   const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
-  u64 x[Gm::R];
+  u64 xi[Gm::R];
   const auto p = gbl(pd.z + ((u64)(u * nl + i) << c.log_n) + toff + ((u64)sub << LOGS));
 #pragma unroll
-  for (int uu = 0; uu < RF::NG; ++uu)
-#pragma unroll
-    for (int ii = 0; ii < RF::G; ++ii) x[uu * RF::G + ii] = p[RF::elem(tt, uu, ii)];
-  sub_transform_regs<true, LOGS, LOGR, true>(x, lds + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
-                                             (1ull << n1) + blk0 + sub, m.q, [](int, u64) {});
-  __syncthreads();
+  for (int k = 0; k < Gm::R; ++k) xi[k] = p[RF::elem(tt, k / RF::G, k % RF::G)];
   const u64* ql = ldc(&P->qlinv);
   const u64 qw = ldc(ql + 2 * i), qws = ldc(ql + 2 * i + 1);
   const auto cu = gbl(pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff);
   const auto ou = gbl(pd.out + ((u64)(u * nl + i) << c.log_n) + toff);
-  constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
+  with_arith(m.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(m.q, m.qinv);
+    typename A::V* tl = reinterpret_cast<typename A::V*>(lds);
+    typename A::V x[Gm::R];
 #pragma unroll
-  for (int k0 = 0; k0 < Gm::R; k0 += TG) {
-    u64 cv[TG];
+    for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
+                                                  (1ull << n1) + blk0 + sub, M, [](int, typename A::V) {});
+    lds_barrier();
+    constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
 #pragma unroll
-    for (int g = 0; g < TG; ++g) cv[g] = cu[threadIdx.x + (k0 + g) * THREADS];
+    for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+      u64 cv[TG];
 #pragma unroll
-    for (int g = 0; g < TG; ++g) {
-      const int idx = threadIdx.x + (k0 + g) * THREADS;
-      const u64 S = ntt_canon<true>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], m.q);
-      ou[idx] = csub(shoup_lazy(cv[g] + m.q - S, qw, qws, m.q), m.q);
+      for (int g = 0; g < TG; ++g) cv[g] = cu[threadIdx.x + (k0 + g) * THREADS];
+#pragma unroll
+      for (int g = 0; g < TG; ++g) {
+        const int idx = threadIdx.x + (k0 + g) * THREADS;
+        const u64 S = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
+        ou[idx] = csub(shoup_lazy(cv[g] + m.q - S, qw, qws, m.q), m.q);
+      }
     }
-  }
+  });
 }
 
 }  // namespace he

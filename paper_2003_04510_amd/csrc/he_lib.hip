@@ -223,10 +223,23 @@ void ntt_launch(const he_ctx* c, bool fwd, const u64* src, u64* dst, u64 src_str
 dim3 ew_grid(u64 total) { return dim3((unsigned)ceil_div(total, EW_THREADS)); }
 
 // ---------------------------------------------------------------- tables
+// Twiddle table entry of w mod m in the arithmetic the kernels use for m.
+Tw2 tw_entry(u64 w, u64 m) {
+  if (f64_mod(m)) {
+    const double wd = (double)w, wq = wd / (double)m;  // both exact / correctly rounded
+    Tw2 t;
+    memcpy(&t.w, &wd, 8);
+    memcpy(&t.ws, &wq, 8);
+    return t;
+  }
+  return Tw2{w, shoup63(w, m)};
+}
+
 ModInfo make_modinfo(u64 q, u64 N) {
   ModInfo m{};
   m.q = q;
   m.b = bitlen(q);
+  m.qinv = 1.0 / (double)q;
   m.mu = (u64)(((u128)1 << (2 * m.b)) / q);
   m.r64 = (u64)(((u128)1 << 64) % q);
   m.r64s = shoup(m.r64, q);
@@ -363,8 +376,8 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     for (u64 k = 1; k < N; ++k) { pw[k] = mulmod(pw[k - 1], psi, m); ipw[k] = mulmod(ipw[k - 1], psii, m); }
     for (u64 k = 0; k < N; ++k) {
       const unsigned e = bitrev((unsigned)k, log_n);
-      tw[i * N + k] = {pw[e], shoup63(pw[e], m)};
-      itw[i * N + k] = {ipw[e], shoup63(ipw[e], m)};
+      tw[i * N + k] = tw_entry(pw[e], m);
+      itw[i * N + k] = tw_entry(ipw[e], m);
     }
   }
   const size_t o_tw = B.add(tw), o_itw = B.add(itw);

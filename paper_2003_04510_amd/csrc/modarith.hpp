@@ -91,6 +91,7 @@ struct ModInfo {
   u64 ninvs;   // Shoup companion of ninv
   u32 b;       // bit length of q
   u32 pad;
+  double qinv; // fl(1/q)
 };
 
 // x < 2^(2b+2): canonical x mod q.

@@ -19,32 +19,151 @@
 // butterflies with TB_invW, stages in reverse order): "blocks" first, then
 // "cols", then the factor N^{-1} (merged with any per-limb constant).
 //
-// Lazy ranges (registers and LDS only): forward values live in [0, 4q)
-// (Harvey's butterfly), inverse values in [0, 2q).  Every value handed to a
-// consumer is canonical unless the consumer asks for the lazy value.
+// Butterfly arithmetic is chosen per modulus (IntA on the 32-bit integer
+// multipliers, F64A on FP64 FMAs for q < 2^50); lazy ranges live in
+// registers and LDS only, every value written to HBM is canonical.
 #pragma once
 #include "modarith.hpp"
 
 #ifndef NTT_EPW_DEFAULT
 #define NTT_EPW_DEFAULT 2048
 #endif
-#ifndef NTT_BLOCKS_LDS_IO
-#define NTT_BLOCKS_LDS_IO 1
-#endif
 
 namespace he {
 
-// Twiddle tables are interleaved pairs {W, floor(W 2^63 / q)} per index
-// (2^63-scaled Shoup companions, see shoup63_lazy).
+// Twiddle tables hold one 16-byte entry per index.  Its meaning depends on
+// the modulus (see IntA / F64A): for q >= 2^50 the pair {W, floor(W 2^63/q)}
+// (2^63-scaled Shoup companion, see shoup63_lazy); for q < 2^50 the bit
+// patterns of the doubles {W, fl(W/q)}.
 struct Tw2 {
   u64 w, ws;
 };
 
-// Modulus constants of the butterflies.
-struct NttMod {
-  u64 q, q2, nq, n2q;  // q, 2q, 2^64 - q, 2^64 - 2q
-  __device__ __forceinline__ explicit NttMod(u64 m) : q(m), q2(m << 1), nq(0 - m), n2q(0 - (m << 1)) {}
+// Moduli below this bound run their butterflies in FP64 (F64A), the rest on
+// the 32-bit integer multipliers (IntA).  Both give the same canonical
+// results; only the instruction mix differs.
+constexpr u64 F64_QLIM = 1ull << 50;
+__host__ __device__ constexpr bool f64_mod(u64 q) { return q < F64_QLIM; }
+
+// ---------------------------------------------------------------- integer arithmetic
+// Values are u64.  Forward values live in [0, 4q) (Harvey's butterfly),
+// inverse values in [0, 2q).
+struct IntA {
+  using V = u64;
+  struct Mod {
+    u64 q, q2, nq, n2q;  // q, 2q, 2^64 - q, 2^64 - 2q
+  };
+  struct Scale {
+    u64 w, ws;  // Shoup pair (2^64-scaled companion)
+  };
+  __device__ static __forceinline__ Mod mod(u64 q, double) { return Mod{q, q << 1, 0 - q, 0 - (q << 1)}; }
+  __device__ static __forceinline__ V in(u64 x, const Mod&) { return x; }
+  // Harvey forward butterfly: x, y in [0, 4q) -> x + w y, x - w y in [0, 4q).
+  __device__ static __forceinline__ void fwd(V& x, V& y, const Tw2 t, const Mod& M) {
+    const u64 X = sub_if_ge(x, M.n2q);
+    const u64 T = shoup63_lazy(y, t.w, t.ws, M.nq);
+    y = (X + M.q2) - T;
+    x = X + T;
+  }
+  // Gentleman-Sande inverse butterfly: x, y in [0, 2q) -> x + y, (x - y) w in [0, 2q).
+  __device__ static __forceinline__ void inv(V& x, V& y, const Tw2 t, const Mod& M) {
+    const u64 X = x, Y = y;
+    x = sub_if_ge(X + Y, M.n2q);
+    y = shoup63_lazy((X + M.q2) - Y, t.w, t.ws, M.nq);
+  }
+  // canonical value of a lazy transform output
+  template <bool FWD>
+  __device__ static __forceinline__ u64 out(V x, const Mod& M) {
+    if constexpr (FWD) x = csub(x, M.q2);
+    return csub(x, M.q);
+  }
+  __device__ static __forceinline__ Scale scale(u64 w, u64 ws, const Mod&) { return Scale{w, ws}; }
+  // canonical x s for an inverse output x in [0, 2q)
+  __device__ static __forceinline__ u64 out_scaled(V x, const Scale s, const Mod& M) {
+    return csub(shoup_lazy(x, s.w, s.ws, M.q), M.q);
+  }
 };
+
+// ---------------------------------------------------------------- FP64 arithmetic
+// For q < 2^50, values are doubles holding integers, kept centred: every
+// butterfly input satisfies |v| < 1.2 q.  A product y w mod q is formed
+// exactly from FMAs:
+//   k  = round(y fl(w/q))            (|y fl(w/q)| < 2^51; the FMA with
+//                                     1.5 2^52 rounds it to an integer)
+//   hi = fl(y w),  lo = y w - hi     (exact: two-product by FMA)
+//   t  = (hi - k q) + lo             (both steps exact: integers < 2^53)
+// so t = y w - k q exactly, with |t| <= (1/2 + |y| 2^-53) q < 0.65 q.
+// A reduction x - round(x fl(1/q)) q leaves |x| <= 0.51 q.  Forward:
+// x' = red(x) + t, y' = red(x) - t (|.| < 1.2 q).  Inverse: x' = red(x + y),
+// y' = (x - y) w with |x|, |y| < 0.7 q, so |x - y| < 1.4 q and the same
+// bounds hold.  The build disables FP contraction, so each step is exactly
+// one rounding as written.
+struct F64A {
+  using V = double;
+  struct Mod {
+    double q, qinv;  // q and fl(1/q)
+  };
+  struct Scale {
+    double w, wq;  // w and fl(w/q)
+  };
+  static constexpr double RND = 6755399441055744.0;  // 1.5 * 2^52
+  static constexpr double TWO52 = 4503599627370496.0;
+  static constexpr u64 TWO52_BITS = 0x4330000000000000ull;
+  __device__ static __forceinline__ Mod mod(u64 q, double qinv) { return Mod{(double)q, qinv}; }
+  // x < 2^52 to double (exact)
+  __device__ static __forceinline__ V in(u64 x, const Mod&) {
+    return __longlong_as_double((long long)(x | TWO52_BITS)) - TWO52;
+  }
+  __device__ static __forceinline__ double red(double x, const Mod& M) {
+    const double k = __fma_rn(x, M.qinv, RND) - RND;
+    return __fma_rn(-k, M.q, x);
+  }
+  __device__ static __forceinline__ double mulw(double y, double w, double wq, const Mod& M) {
+    const double k = __fma_rn(y, wq, RND) - RND;
+    const double hi = __dmul_rn(y, w);
+    const double lo = __fma_rn(y, w, -hi);
+    const double r = __fma_rn(-k, M.q, hi);
+    return __dadd_rn(r, lo);
+  }
+  __device__ static __forceinline__ void fwd(V& x, V& y, const Tw2 t, const Mod& M) {
+    const double X = red(x, M);
+    const double T = mulw(y, __longlong_as_double((long long)t.w), __longlong_as_double((long long)t.ws), M);
+    x = X + T;
+    y = X - T;
+  }
+  __device__ static __forceinline__ void inv(V& x, V& y, const Tw2 t, const Mod& M) {
+    const double X = x, Y = y;
+    x = red(X + Y, M);
+    y = mulw(X - Y, __longlong_as_double((long long)t.w), __longlong_as_double((long long)t.ws), M);
+  }
+  // |c| <= 0.7 q, c integral -> canonical u64
+  __device__ static __forceinline__ u64 to_u64(double c, const Mod& M) {
+    const double v = c < 0.0 ? c + M.q : c;
+    return (u64)__double_as_longlong(v + TWO52) - TWO52_BITS;
+  }
+  template <bool FWD>
+  __device__ static __forceinline__ u64 out(V x, const Mod& M) {
+    return to_u64(red(x, M), M);
+  }
+  // w < q; fl(w/q) once per thread
+  __device__ static __forceinline__ Scale scale(u64 w, u64, const Mod& M) {
+    const double wd = (double)w;
+    return Scale{wd, __ddiv_rn(wd, M.q)};
+  }
+  __device__ static __forceinline__ u64 out_scaled(V x, const Scale s, const Mod& M) {
+    return to_u64(mulw(x, s.w, s.wq, M), M);
+  }
+};
+
+// Workgroup barrier ordering LDS accesses only: unlike __syncthreads() it
+// does not wait for outstanding global loads and stores, so prefetches and
+// stores stay in flight across the LDS exchanges of a transform.  Kernels
+// never pass data between threads through global memory.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 template <int LOGS, int LOGR>
 struct Geo {
@@ -74,31 +193,16 @@ struct RoundShape {
   __device__ static __forceinline__ int blk(int tt, int u) { return (tt + u * Gm::T) / cnt_c; }
 };
 
-// Harvey forward butterfly: x, y in [0, 4q) -> x + w y, x - w y in [0, 4q).
-__device__ __forceinline__ void bfly_fwd(u64& x, u64& y, const Tw2 t, const NttMod& M) {
-  const u64 X = sub_if_ge(x, M.n2q);
-  const u64 T = shoup63_lazy(y, t.w, t.ws, M.nq);
-  y = (X + M.q2) - T;
-  x = X + T;
-}
-// Gentleman-Sande inverse butterfly: x, y in [0, 2q) -> x + y, (x - y) w in [0, 2q).
-__device__ __forceinline__ void bfly_inv(u64& x, u64& y, const Tw2 t, const NttMod& M) {
-  const u64 X = x, Y = y;
-  x = sub_if_ge(X + Y, M.n2q);
-  y = shoup63_lazy((X + M.q2) - Y, t.w, t.ws, M.nq);
-}
-
 // Butterflies of round RD on the registers x[0..R) of thread tt.
-template <bool FWD, int LOGS, int LOGR, int RD>
-__device__ __forceinline__ void round_math(u64 (&x)[1 << LOGR], int tt, const Tw2* __restrict__ tw, u64 base,
-                                           u64 q) {
+template <class A, bool FWD, int LOGS, int LOGR, int RD>
+__device__ __forceinline__ void round_math(typename A::V (&x)[1 << LOGR], int tt, const Tw2* __restrict__ tw,
+                                           u64 base, const typename A::Mod& M) {
   using RS = RoundShape<LOGS, LOGR, RD>;
   constexpr int G = RS::G, rr = RS::rr, st = RS::st;
-  const NttMod M(q);
 #pragma unroll
   for (int u = 0; u < RS::NG; ++u) {
     const u64 blk = (u64)RS::blk(tt, u);
-    u64* v = x + u * G;
+    typename A::V* v = x + u * G;
     if constexpr (FWD) {
 #pragma unroll
       for (int k = 0; k < rr; ++k) {
@@ -107,7 +211,7 @@ __device__ __forceinline__ void round_math(u64 (&x)[1 << LOGR], int tt, const Tw
 #pragma unroll
         for (int i = 0; i < G; ++i) {
           if (i & half) continue;
-          bfly_fwd(v[i], v[i + half], tw[mloc * base + (blk << k) + (u64)(i >> (rr - k))], M);
+          A::fwd(v[i], v[i + half], tw[mloc * base + (blk << k) + (u64)(i >> (rr - k))], M);
         }
       }
     } else {
@@ -118,23 +222,23 @@ __device__ __forceinline__ void round_math(u64 (&x)[1 << LOGR], int tt, const Tw
 #pragma unroll
         for (int i = 0; i < G; ++i) {
           if (i & half) continue;
-          bfly_inv(v[i], v[i + half], tw[mloc * base + (blk << k) + (u64)(i >> (rr - k))], M);
+          A::inv(v[i], v[i + half], tw[mloc * base + (blk << k) + (u64)(i >> (rr - k))], M);
         }
       }
     }
   }
 }
 
-template <int LOGS, int LOGR, int RD>
-__device__ __forceinline__ void lds_put(u64* tile, const u64 (&x)[1 << LOGR], int tt) {
+template <int LOGS, int LOGR, int RD, class V>
+__device__ __forceinline__ void lds_put(V* tile, const V (&x)[1 << LOGR], int tt) {
   using RS = RoundShape<LOGS, LOGR, RD>;
 #pragma unroll
   for (int u = 0; u < RS::NG; ++u)
 #pragma unroll
     for (int i = 0; i < RS::G; ++i) tile[Geo<LOGS, LOGR>::pad(RS::elem(tt, u, i))] = x[u * RS::G + i];
 }
-template <int LOGS, int LOGR, int RD>
-__device__ __forceinline__ void lds_get(const u64* tile, u64 (&x)[1 << LOGR], int tt) {
+template <int LOGS, int LOGR, int RD, class V>
+__device__ __forceinline__ void lds_get(const V* tile, V (&x)[1 << LOGR], int tt) {
   using RS = RoundShape<LOGS, LOGR, RD>;
 #pragma unroll
   for (int u = 0; u < RS::NG; ++u)
@@ -143,55 +247,46 @@ __device__ __forceinline__ void lds_get(const u64* tile, u64 (&x)[1 << LOGR], in
 }
 
 // Middle rounds 1 .. NR-2 (forward order) through LDS.
-template <bool FWD, int LOGS, int LOGR, int K>
-__device__ __forceinline__ void mid_rounds(u64 (&x)[1 << LOGR], u64* tile, int tt, const Tw2* __restrict__ tw,
-                                           u64 base, u64 q) {
+template <class A, bool FWD, int LOGS, int LOGR, int K>
+__device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
+                                           const Tw2* __restrict__ tw, u64 base, const typename A::Mod& M) {
   constexpr int NR = Geo<LOGS, LOGR>::NR;
   if constexpr (K < NR - 1) {
     constexpr int RD = FWD ? K : NR - 1 - K;
     constexpr int PREV = FWD ? RD - 1 : RD + 1;
     lds_put<LOGS, LOGR, PREV>(tile, x, tt);
-    __syncthreads();
+    lds_barrier();
     lds_get<LOGS, LOGR, RD>(tile, x, tt);
-    round_math<FWD, LOGS, LOGR, RD>(x, tt, tw, base, q);
+    round_math<A, FWD, LOGS, LOGR, RD>(x, tt, tw, base, M);
     // no barrier needed before the next lds_put: within one round every LDS
     // position belongs to exactly one thread
-    mid_rounds<FWD, LOGS, LOGR, K + 1>(x, tile, tt, tw, base, q);
+    mid_rounds<A, FWD, LOGS, LOGR, K + 1>(x, tile, tt, tw, base, M);
   }
 }
 
-// Whole sub-transform.  The first round takes its operands from load(e)
-// (or, when IN_LDS, from the tile, already filled in the first round's
-// element order); the last round hands element e to store(e, v) (or, when
-// OUT_LDS, leaves it in the tile for a coalesced copy-out after a barrier).
-// `tile` is this sub-transform's LDS area (Geo::SUB words).  A caller that
-// runs several sub-transforms on the same tile back to back must place a
-// barrier between them.
-template <bool FWD, int LOGS, int LOGR, bool IN_LDS, bool OUT_LDS, class Load, class Store>
-__device__ __forceinline__ void sub_transform(u64* tile, int tt, const Tw2* __restrict__ tw, u64 base, u64 q,
-                                              Load&& load, Store&& store) {
+// Whole sub-transform with the first round's operands already in x (in the
+// first round's element order).  The last round hands element e to
+// store(e, v) (lazy value of arithmetic A), or, when OUT_LDS, leaves it in
+// the tile for a coalesced copy-out after a barrier.  `tile` is this
+// sub-transform's LDS area (Geo::SUB words).  A caller that runs several
+// sub-transforms on the same tile back to back must place a barrier between
+// them.
+template <class A, bool FWD, int LOGS, int LOGR, bool OUT_LDS, class Store>
+__device__ __forceinline__ void sub_transform_regs(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
+                                                   const Tw2* __restrict__ tw, u64 base, const typename A::Mod& M,
+                                                   Store&& store) {
   using Gm = Geo<LOGS, LOGR>;
   constexpr int NR = Gm::NR;
   constexpr int FIRST = FWD ? 0 : NR - 1;
   constexpr int LAST = FWD ? NR - 1 : 0;
-  u64 x[Gm::R];
-  if constexpr (IN_LDS) {
-    lds_get<LOGS, LOGR, FIRST>(tile, x, tt);
-  } else {
-    using RS = RoundShape<LOGS, LOGR, FIRST>;
-#pragma unroll
-    for (int u = 0; u < RS::NG; ++u)
-#pragma unroll
-      for (int i = 0; i < RS::G; ++i) x[u * RS::G + i] = load(RS::elem(tt, u, i));
-  }
-  round_math<FWD, LOGS, LOGR, FIRST>(x, tt, tw, base, q);
+  round_math<A, FWD, LOGS, LOGR, FIRST>(x, tt, tw, base, M);
   if constexpr (NR > 1) {
-    mid_rounds<FWD, LOGS, LOGR, 1>(x, tile, tt, tw, base, q);
+    mid_rounds<A, FWD, LOGS, LOGR, 1>(x, tile, tt, tw, base, M);
     constexpr int PREV = FWD ? LAST - 1 : LAST + 1;
     lds_put<LOGS, LOGR, PREV>(tile, x, tt);
-    __syncthreads();
+    lds_barrier();
     lds_get<LOGS, LOGR, LAST>(tile, x, tt);
-    round_math<FWD, LOGS, LOGR, LAST>(x, tt, tw, base, q);
+    round_math<A, FWD, LOGS, LOGR, LAST>(x, tt, tw, base, M);
   }
   if constexpr (OUT_LDS) {
     lds_put<LOGS, LOGR, LAST>(tile, x, tt);
@@ -204,39 +299,11 @@ __device__ __forceinline__ void sub_transform(u64* tile, int tt, const Tw2* __re
   }
 }
 
-// As sub_transform, with the first round's operands already in x.
-template <bool FWD, int LOGS, int LOGR, bool OUT_LDS, class Store>
-__device__ __forceinline__ void sub_transform_regs(u64 (&x)[1 << LOGR], u64* tile, int tt, const Tw2* __restrict__ tw,
-                                                   u64 base, u64 q, Store&& store) {
-  using Gm = Geo<LOGS, LOGR>;
-  constexpr int NR = Gm::NR;
-  constexpr int FIRST = FWD ? 0 : NR - 1;
-  constexpr int LAST = FWD ? NR - 1 : 0;
-  round_math<FWD, LOGS, LOGR, FIRST>(x, tt, tw, base, q);
-  if constexpr (NR > 1) {
-    mid_rounds<FWD, LOGS, LOGR, 1>(x, tile, tt, tw, base, q);
-    constexpr int PREV = FWD ? LAST - 1 : LAST + 1;
-    lds_put<LOGS, LOGR, PREV>(tile, x, tt);
-    __syncthreads();
-    lds_get<LOGS, LOGR, LAST>(tile, x, tt);
-    round_math<FWD, LOGS, LOGR, LAST>(x, tt, tw, base, q);
-  }
-  if constexpr (OUT_LDS) {
-    lds_put<LOGS, LOGR, LAST>(tile, x, tt);
-  } else {
-    using RS = RoundShape<LOGS, LOGR, LAST>;
-#pragma unroll
-    for (int u = 0; u < RS::NG; ++u)
-#pragma unroll
-      for (int i = 0; i < RS::G; ++i) store(RS::elem(tt, u, i), x[u * RS::G + i]);
-  }
-}
-
-// Canonical value of a lazy transform output.
-template <bool FWD>
-__device__ __forceinline__ u64 ntt_canon(u64 x, u64 q) {
-  if constexpr (FWD) x = csub(x, q << 1);
-  return csub(x, q);
+// Runs body(IntA{}) or body(F64A{}) by the modulus (uniform per workgroup).
+template <class Body>
+__device__ __forceinline__ void with_arith(u64 q, Body&& body) {
+  if (f64_mod(q)) body(F64A{});
+  else body(IntA{});
 }
 
 // Radix per sub-transform size.
@@ -291,63 +358,95 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols(NttArgs a)
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
+  constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
+  using RF = RoundShape<LOGS, LOGR, FIRST>;
   __shared__ u64 lds[PL::SUBS * Gm::SUB];
   const int limb = blockIdx.y;
   const u32 mi = a.limb_mod[limb];
-  const u64 q = a.mods[mi].q;
+  const ModInfo mo = ldc(a.mods + mi);
   const int n2 = a.log_n - LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   const u64 col = (u64)blockIdx.x * PL::SUBS + sub;
   const auto in = gbl(a.src + (u64)limb * a.src_stride + (u64)blockIdx.z * a.src_zstride + col);
   const auto out = gbl(a.dst + (u64)limb * a.dst_stride + (u64)blockIdx.z * a.dst_zstride + col);
-  u64 w = a.mods[mi].ninv, ws = a.mods[mi].ninvs;
+  u64 sw = mo.ninv, sws = mo.ninvs;
   if (!FWD && a.scale) {
-    w = a.scale[2 * (u64)limb];
-    ws = a.scale[2 * (u64)limb + 1];
+    sw = a.scale[2 * (u64)limb];
+    sws = a.scale[2 * (u64)limb + 1];
   }
-  sub_transform<FWD, LOGS, LOGR, false, false>(
-      lds + sub * Gm::SUB, tt, a.tw + ((u64)mi << a.log_n), 1, q,
-      [&](int e) { return in[(u64)e << n2]; },
-      [&](int e, u64 v) {
-        out[(u64)e << n2] = FWD ? ntt_canon<true>(v, q) : csub(shoup_lazy(v, w, ws, q), q);
-      });
+  u64 xi[Gm::R];
+#pragma unroll
+  for (int k = 0; k < Gm::R; ++k) xi[k] = in[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
+  with_arith(mo.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(mo.q, mo.qinv);
+    const typename A::Scale sc = A::scale(sw, sws, M);
+    typename A::V x[Gm::R];
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    sub_transform_regs<A, FWD, LOGS, LOGR, false>(
+        x, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, a.tw + ((u64)mi << a.log_n), 1, M,
+        [&](int e, typename A::V v) {
+          out[(u64)e << n2] = FWD ? A::template out<true>(v, M) : A::out_scaled(v, sc, M);
+        });
+  });
 }
 
-// Blocks pass.  With LDS_IO the side whose register layout is
-// thread-contiguous (forward output, inverse input) goes through LDS so that
-// every global access is coalesced.
-template <bool FWD, int LOGS, int EPW = NTT_EPW, bool LDS_IO = NTT_BLOCKS_LDS_IO>
+// Blocks pass.  The side whose register layout is thread-contiguous
+// (forward output, inverse input) goes through LDS so that every global
+// access is coalesced.
+template <bool FWD, int LOGS, int EPW = NTT_EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_blocks(NttArgs a) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
   constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
+  constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
+  using RF = RoundShape<LOGS, LOGR, FIRST>;
   __shared__ u64 lds[PL::SUBS * Gm::SUB];
   const int limb = blockIdx.y;
   const u32 mi = a.limb_mod[limb];
-  const u64 q = a.mods[mi].q;
+  const ModInfo mo = ldc(a.mods + mi);
   const int n1 = a.log_n - LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   const u64 blk0 = (u64)blockIdx.x * PL::SUBS;
-  const u64 blk = blk0 + sub;
   const auto in0 = gbl(a.src + (u64)limb * a.src_stride + (u64)blockIdx.z * a.src_zstride + (blk0 << LOGS));
   const auto out0 = gbl(a.dst + (u64)limb * a.dst_stride + (u64)blockIdx.z * a.dst_zstride + (blk0 << LOGS));
   const auto in = in0 + ((u64)sub << LOGS);
   const auto out = out0 + ((u64)sub << LOGS);
-  constexpr bool IN_LDS = LDS_IO && !FWD, OUT_LDS = LDS_IO && FWD;
-  if constexpr (IN_LDS) {
-    for (int idx = threadIdx.x; idx < PL::SUBS * Gm::S; idx += THREADS)
+  u64 xi[Gm::R];
+  if constexpr (!FWD) {
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) {
+      const int idx = threadIdx.x + k * THREADS;
       lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))] = in0[idx];
-    __syncthreads();
+    }
+    lds_barrier();
+    // the transform writes only tile positions this thread has just read
+    lds_get<LOGS, LOGR, FIRST>(lds + sub * Gm::SUB, xi, tt);
+  } else {
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) xi[k] = in[RF::elem(tt, k / RF::G, k % RF::G)];
   }
-  sub_transform<FWD, LOGS, LOGR, IN_LDS, OUT_LDS>(
-      lds + sub * Gm::SUB, tt, a.tw + ((u64)mi << a.log_n), (1ull << n1) + blk, q,
-      [&](int e) { return in[e]; }, [&](int e, u64 v) { out[e] = ntt_canon<FWD>(v, q); });
-  if constexpr (OUT_LDS) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < PL::SUBS * Gm::S; idx += THREADS)
-      out0[idx] = ntt_canon<FWD>(lds[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], q);
-  }
+  with_arith(mo.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(mo.q, mo.qinv);
+    typename A::V* tl = reinterpret_cast<typename A::V*>(lds);
+    typename A::V x[Gm::R];
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    sub_transform_regs<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, a.tw + ((u64)mi << a.log_n),
+                                                (1ull << n1) + blk0 + sub, M,
+                                                [&](int e, typename A::V v) { out[e] = A::template out<FWD>(v, M); });
+    if constexpr (FWD) {
+      lds_barrier();
+#pragma unroll
+      for (int k = 0; k < Gm::R; ++k) {
+        const int idx = threadIdx.x + k * THREADS;
+        out0[idx] = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
+      }
+    }
+  });
 }
 
 }  // namespace he
