@@ -153,6 +153,36 @@ he_status he_batch_create_async(he_ctx* ctx, const he_batch_item* items, uint32_
                                 void* d_desc, size_t desc_bytes, he_stream stream, he_batch** out);
 void he_batch_destroy(he_batch* batch);
 
+/* Batch schedule (no paper passage: an implementation choice of how the
+ * batch's work is laid on the device).  cols_tile / blocks_tile: elements
+ * per workgroup of the NTT "cols" / "blocks" passes (defaults 4096 / 2048;
+ * at N = 2^16 also 2048 / 1024).  chunks (1..8, at most the pair count):
+ * the pairs are split into that many contiguous groups of about equal total
+ * level; their stage sequences alternate between the batch's stream and a
+ * side stream the batch owns, so stages of different groups overlap; a
+ * captured graph keeps that structure.  Results are identical under every
+ * schedule.
+ *
+ * he_batch_set_sched: validates (HE_EUNSUPPORTED for tiles not available at
+ * this ring degree, HE_EINVAL for a bad chunk count), re-uploads the item
+ * offsets on `stream` and waits for it, drops a captured graph.
+ * he_batch_get_sched: the current schedule.
+ * he_batch_autotune: runs the batch (overwriting its outputs with the same
+ * values) as a graph `reps` times under each candidate schedule -- every
+ * available tile pair with one chunk, then the best tiles with 2 and 4
+ * chunks -- times each with HIP events on `stream`, and installs the
+ * fastest; *best and *best_ms (may be NULL) receive it and its time per
+ * replay.  Synchronizes `stream`. */
+typedef struct he_batch_sched {
+  uint32_t cols_tile;
+  uint32_t blocks_tile;
+  uint32_t chunks;
+} he_batch_sched;
+he_status he_batch_set_sched(he_batch* batch, const he_batch_sched* sched, he_stream stream);
+he_status he_batch_get_sched(const he_batch* batch, he_batch_sched* sched);
+he_status he_batch_autotune(he_ctx* ctx, he_batch* batch, const uint64_t* d_evk, uint32_t reps, he_stream stream,
+                            he_batch_sched* best, double* best_ms);
+
 /* Serving: a request loop with continuous batching (host side, native).
  * he_server_add_ring registers a context with its resident evk and a
  * workspace arena of arena_bytes (device memory the server allocates; the

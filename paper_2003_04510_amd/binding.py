@@ -30,6 +30,10 @@ class BatchItem(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("ct1", vp), ("ct2", vp), ("relin", vp), ("out", vp)]
 
 
+class BatchSched(ctypes.Structure):
+    _fields_ = [("cols_tile", ctypes.c_uint32), ("blocks_tile", ctypes.c_uint32), ("chunks", ctypes.c_uint32)]
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
 
@@ -75,6 +79,10 @@ def load_library():
     L.he_mul_batch.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     L.he_batch_destroy.argtypes = [vp]
     L.he_batch_destroy.restype = None
+    L.he_batch_set_sched.argtypes = [vp, ctypes.POINTER(BatchSched), vp]
+    L.he_batch_get_sched.argtypes = [vp, ctypes.POINTER(BatchSched)]
+    L.he_batch_autotune.argtypes = [vp, vp, vp, u32, vp, ctypes.POINTER(BatchSched),
+                                    ctypes.POINTER(ctypes.c_double)]
     L.he_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
     L.he_server_add_ring.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(u32)]
     L.he_server_submit.argtypes = [vp, u32, ctypes.c_uint64, u32, vp, vp, vp]
@@ -314,6 +322,24 @@ class Batch:
     def run(self, evk, use_graph: bool = False):
         _check(load_library().he_mul_batch(self.ctx._h, self._h, vp(evk.data_ptr()), int(use_graph),
                                            self.ctx._stream()), "he_mul_batch")
+
+    def set_sched(self, cols_tile: int, blocks_tile: int, chunks: int):
+        sc = BatchSched(cols_tile, blocks_tile, chunks)
+        _check(load_library().he_batch_set_sched(self._h, ctypes.byref(sc), self.ctx._stream()),
+               "he_batch_set_sched")
+
+    def sched(self):
+        sc = BatchSched()
+        _check(load_library().he_batch_get_sched(self._h, ctypes.byref(sc)), "he_batch_get_sched")
+        return {"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks}
+
+    def autotune(self, evk, reps: int = 3):
+        """Time every candidate schedule (graph replays) and keep the
+        fastest; returns (schedule, ms per replay)."""
+        sc, ms = BatchSched(), ctypes.c_double()
+        _check(load_library().he_batch_autotune(self.ctx._h, self._h, vp(evk.data_ptr()), reps, self.ctx._stream(),
+                                                ctypes.byref(sc), ctypes.byref(ms)), "he_batch_autotune")
+        return {"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks}, ms.value
 
     def close(self):
         if getattr(self, "_h", None):

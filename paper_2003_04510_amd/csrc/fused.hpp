@@ -26,9 +26,13 @@ namespace he {
 
 constexpr u64 M30 = (1ull << 30) - 1;
 
-// Workgroup tiles: "cols" passes 4096 elements (16 adjacent columns at
-// N = 2^16), "blocks" passes 2048 elements.
+// Workgroup tiles (elements per workgroup) of the NTT passes.  Defaults:
+// "cols" passes 4096 elements (16 adjacent columns at N = 2^16), "blocks"
+// passes 2048; batches at N = 2^16 may select other tiles (TileCfg).
 constexpr int EPW_C = 4096, EPW_B = 2048;
+struct TileCfg {
+  u32 epw_c = EPW_C, epw_b = EPW_B;
+};
 constexpr int CONV_CPT = 2, CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
 constexpr int IP_CPT = 2, IP_THREADS = 256;                        // inner product
 
@@ -97,6 +101,9 @@ struct Common {
 };
 
 // Which pairs a launch covers.
+// A launch may cover a contiguous range of a batch's pairs: `pairs` and
+// `offs` then point at its first pair, and its items are numbered from 0
+// (offs[0] is added back).
 struct Batch {
   PairDesc one;            // the pair of a single HE Mul (pairs == null)
   const PairDesc* pairs;   // device array [npairs] for a batch
@@ -109,6 +116,7 @@ __device__ __forceinline__ PairDesc resolve(const Batch& b, u32 w, u32& local) {
     local = w;
     return b.one;
   }
+  w += ldc(b.offs);
   u32 lo = 0, hi = b.npairs;  // offs[lo] <= w < offs[hi]
   while (hi - lo > 1) {
     const u32 mid = (lo + hi) >> 1;
@@ -138,16 +146,17 @@ enum Stage : int {
 };
 
 // Tiles per limb of a cols / blocks pass at ring degree 2^log_n.
-__host__ __device__ constexpr u32 cols_tiles(u32 log_n) {
-  return (1u << (log_n - log_n / 2)) / (u32)(EPW_C >> (log_n / 2));
+__host__ __device__ constexpr u32 cols_tiles(u32 log_n, u32 epw = EPW_C) {
+  return (1u << (log_n - log_n / 2)) / (epw >> (log_n / 2));
 }
-__host__ __device__ constexpr u32 blocks_tiles(u32 log_n) {
-  return (1u << (log_n / 2)) / (u32)(EPW_B >> (log_n - log_n / 2));
+__host__ __device__ constexpr u32 blocks_tiles(u32 log_n, u32 epw = EPW_B) {
+  return (1u << (log_n / 2)) / (epw >> (log_n - log_n / 2));
 }
 
 // Work items of one pair in a stage.
-inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_limbs, bool rs) {
-  const u32 tc = cols_tiles(log_n), tb = blocks_tiles(log_n);
+inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_limbs, bool rs,
+                       TileCfg tc_cfg = TileCfg{}) {
+  const u32 tc = cols_tiles(log_n, tc_cfg.epw_c), tb = blocks_tiles(log_n, tc_cfg.epw_b);
   const u32 chunks_c = (1u << log_n) / (CONV_THREADS * CONV_CPT);
   const u32 chunks_i = (1u << log_n) / (IP_THREADS * IP_CPT);
   const u32 ex = rs ? 1 : 0;

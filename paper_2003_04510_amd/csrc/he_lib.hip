@@ -620,15 +620,15 @@ template <int LOGS, int EPW>
 void launch_tensor(const Common& c, const Batch& b, hipStream_t st) {
   hipLaunchKernelGGL((k_tensor_intt<LOGS, EPW>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, c, b);
 }
-template <bool FWD, int LOGS, int ST>
+template <bool FWD, int LOGS, int EPW, int ST>
 void launch_lcols(const Common& c, const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL((k_list_cols<FWD, LOGS, EPW_C, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW_C)), 0,
-                     st, c, b);
+  hipLaunchKernelGGL((k_list_cols<FWD, LOGS, EPW, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, c,
+                     b);
 }
-template <bool FWD, int LOGS, int ST>
+template <bool FWD, int LOGS, int EPW, int ST>
 void launch_lblocks(const Common& c, const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL((k_list_blocks<FWD, LOGS, EPW_B, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW_B)), 0,
-                     st, c, b);
+  hipLaunchKernelGGL((k_list_blocks<FWD, LOGS, EPW, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st,
+                     c, b);
 }
 
 template <bool MD>
@@ -641,33 +641,33 @@ void launch_conv(int bucket, const Common& c, const Batch& b, hipStream_t st) {
   }
 }
 
-// n1 = log_n / 2 (cols passes), n2 = log_n - n1 (blocks passes)
-template <int N1, int N2>
+// n1 = log_n / 2 (cols passes), n2 = log_n - n1 (blocks passes); EC / EB:
+// workgroup tiles of the cols / blocks passes.
+template <int N1, int N2, int EC = EPW_C, int EB = EPW_B>
 void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) {
+  const dim3 g(pad8(b.nitems));
   switch (stage) {
-    case ST_TENSOR: launch_tensor<N2, EPW_B>(c, b, st); break;
-    case ST_Y_ICOLS: launch_lcols<false, N1, ST_Y_ICOLS>(c, b, st); break;
+    case ST_TENSOR: launch_tensor<N2, EB>(c, b, st); break;
+    case ST_Y_ICOLS: launch_lcols<false, N1, EC, ST_Y_ICOLS>(c, b, st); break;
     case ST_MU_CONV: launch_conv<false>(conv_bucket((c.L + c.dnum - 1) / c.dnum), c, b, st); break;
-    case ST_DT_NCOLS: launch_lcols<true, N1, ST_DT_NCOLS>(c, b, st); break;
-    case ST_DT_NBLOCKS: launch_lblocks<true, N2, ST_DT_NBLOCKS>(c, b, st); break;
-    case ST_IP: hipLaunchKernelGGL(k_ip, dim3(pad8(b.nitems)), dim3(IP_THREADS), 0, st, c, b); break;
-    case ST_KS_IBLOCKS: launch_lblocks<false, N2, ST_KS_IBLOCKS>(c, b, st); break;
-    case ST_KS_ICOLS: launch_lcols<false, N1, ST_KS_ICOLS>(c, b, st); break;
+    case ST_DT_NCOLS: launch_lcols<true, N1, EC, ST_DT_NCOLS>(c, b, st); break;
+    case ST_DT_NBLOCKS: launch_lblocks<true, N2, EB, ST_DT_NBLOCKS>(c, b, st); break;
+    case ST_IP: hipLaunchKernelGGL(k_ip, g, dim3(IP_THREADS), 0, st, c, b); break;
+    case ST_KS_IBLOCKS: launch_lblocks<false, N2, EB, ST_KS_IBLOCKS>(c, b, st); break;
+    case ST_KS_ICOLS: launch_lcols<false, N1, EC, ST_KS_ICOLS>(c, b, st); break;
     case ST_MD_CONV: launch_conv<true>(conv_bucket(c.K), c, b, st); break;
-    case ST_Z_NCOLS: launch_lcols<true, N1, ST_Z_NCOLS>(c, b, st); break;
-    case ST_COMBINE:
-      hipLaunchKernelGGL((k_ntt_combine<N2, EPW_B>), dim3(pad8(b.nitems)), dim3(pass_threads(N2, EPW_B)), 0, st, c,
-                         b);
-      break;
-    case ST_LIFT:
-      hipLaunchKernelGGL((k_lift_ntt_cols<N1, EPW_C>), dim3(pad8(b.nitems)), dim3(pass_threads(N1, EPW_C)), 0, st,
-                         c, b);
-      break;
-    case ST_RESCALE:
-      hipLaunchKernelGGL((k_ntt_rescale<N2, EPW_B>), dim3(pad8(b.nitems)), dim3(pass_threads(N2, EPW_B)), 0, st, c,
-                         b);
-      break;
+    case ST_Z_NCOLS: launch_lcols<true, N1, EC, ST_Z_NCOLS>(c, b, st); break;
+    case ST_COMBINE: hipLaunchKernelGGL((k_ntt_combine<N2, EB>), g, dim3(pass_threads(N2, EB)), 0, st, c, b); break;
+    case ST_LIFT: hipLaunchKernelGGL((k_lift_ntt_cols<N1, EC>), g, dim3(pass_threads(N1, EC)), 0, st, c, b); break;
+    case ST_RESCALE: hipLaunchKernelGGL((k_ntt_rescale<N2, EB>), g, dim3(pass_threads(N2, EB)), 0, st, c, b); break;
   }
+}
+
+// Tile choices a batch may select: the defaults at every ring degree, and
+// at N = 2^16 also 2048-element cols tiles and 1024-element blocks tiles.
+bool tiles_supported(u32 log_n, TileCfg t) {
+  if (t.epw_c == EPW_C && t.epw_b == EPW_B) return true;
+  return log_n == 16 && (t.epw_c == 2048 || t.epw_c == 4096) && (t.epw_b == 1024 || t.epw_b == 2048);
 }
 
 const char* stage_name(int s) {
@@ -708,7 +708,7 @@ void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double
 }
 
 void launch_stage(const he_ctx* c, int stage, const Common& cm, const Batch& b, double ops, double bytes,
-                  hipStream_t st) {
+                  hipStream_t st, TileCfg t = TileCfg{}) {
   if (!b.nitems) return;
   timed(c, stage_name(stage), ops, bytes, st, [&] {
     switch (c->log_n) {
@@ -716,7 +716,14 @@ void launch_stage(const he_ctx* c, int stage, const Common& cm, const Batch& b, 
       case 13: launch_stage_n<6, 7>(stage, cm, b, st); break;
       case 14: launch_stage_n<7, 7>(stage, cm, b, st); break;
       case 15: launch_stage_n<7, 8>(stage, cm, b, st); break;
-      case 16: launch_stage_n<8, 8>(stage, cm, b, st); break;
+      case 16:
+        if (t.epw_c == 2048)
+          t.epw_b == 1024 ? launch_stage_n<8, 8, 2048, 1024>(stage, cm, b, st)
+                          : launch_stage_n<8, 8, 2048, 2048>(stage, cm, b, st);
+        else
+          t.epw_b == 1024 ? launch_stage_n<8, 8, 4096, 1024>(stage, cm, b, st)
+                          : launch_stage_n<8, 8, 4096, 2048>(stage, cm, b, st);
+        break;
       case 17: launch_stage_n<8, 9>(stage, cm, b, st); break;
     }
   });
@@ -819,6 +826,12 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
 }  // extern "C"
 
 // ---------------------------------------------------------------- batches
+// A batch owns device descriptors (one PairDesc per pair, then per stage the
+// prefix sums of the pairs' work items for the current tiles) and a
+// schedule: NTT tiles and a split of the pairs into `chunks` contiguous
+// groups whose stage chains alternate between the caller's stream and a side
+// stream (fork/join by events, also inside a captured graph), so that stages
+// of different groups overlap on the device.
 struct he_batch {
   he_ctx* ctx = nullptr;
   u32 n = 0;
@@ -827,9 +840,15 @@ struct he_batch {
   std::vector<uint8_t> host;           // staging copy (kept until destroy for async uploads)
   const PairDesc* pairs = nullptr;
   const u32* offs[ST_COUNT] = {};
+  std::vector<u32> hoffs;              // host copy of the offsets [ST_COUNT][n + 1]
   u32 nitems[ST_COUNT] = {};
   std::vector<u32> levels;
   std::vector<uint8_t> rs;
+  TileCfg tiles{};
+  u32 chunks = 1;
+  std::vector<u32> cut{};              // chunk boundaries in pairs [chunks + 1]
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // cached graph of the whole batched HE Mul
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -846,12 +865,43 @@ static size_t batch_ws_words(const he_ctx* c, const he_batch_item* items, u32 n)
   return w;
 }
 
+// Per-stage item prefix sums of the batch for its current tiles, into
+// bt->hoffs, bt->nitems and the offsets part of the staging buffer.
+static he_status batch_offsets(const he_ctx* c, he_batch* bt) {
+  const u32 n = bt->n;
+  bt->hoffs.assign((size_t)ST_COUNT * (n + 1), 0);
+  for (int s = 0; s < ST_COUNT; ++s) {
+    u64 acc = 0;
+    for (u32 i = 0; i < n; ++i) {
+      bt->hoffs[(size_t)s * (n + 1) + i] = (u32)acc;
+      const LevelPlan& P = c->lv[bt->levels[i]];
+      acc += stage_items(s, c->log_n, bt->levels[i], c->K, P.beta, P.dt_limbs, bt->rs[i] != 0, bt->tiles);
+    }
+    if (acc > 0xffffff00ull) return fail(HE_EUNSUPPORTED, "he_batch: batch too large");
+    bt->hoffs[(size_t)s * (n + 1) + n] = (u32)acc;
+    bt->nitems[s] = (u32)acc;
+  }
+  memcpy(bt->host.data() + sizeof(PairDesc) * n, bt->hoffs.data(), sizeof(u32) * bt->hoffs.size());
+  return HE_OK;
+}
+
+// Chunk boundaries with about equal sums of levels per chunk.
+static void batch_cuts(he_batch* bt) {
+  u64 tot = 0;
+  for (u32 l : bt->levels) tot += l;
+  bt->cut.assign(1, 0);
+  u64 acc = 0;
+  for (u32 i = 0; i < bt->n && bt->cut.size() < bt->chunks; ++i) {
+    acc += bt->levels[i];
+    if (acc * bt->chunks >= tot * bt->cut.size() && i + 1 < bt->n) bt->cut.push_back(i + 1);
+  }
+  bt->cut.push_back(bt->n);
+}
+
 extern "C" {
 
 size_t he_batch_workspace_bytes(const he_ctx* c, const he_batch_item* items, uint32_t n) {
   if (!c || (!items && n)) return 0;
-  for (u32 i = 0; i < n; ++i)
-    if (items[i].level < 1 || items[i].level > c->L) return 0;
   return batch_ws_words(c, items, n) * 8;
 }
 
@@ -873,7 +923,6 @@ static he_status batch_build(he_ctx* c, const he_batch_item* items, uint32_t n, 
   bt->ctx = c;
   bt->n = n;
   std::vector<PairDesc> pds(n);
-  std::vector<u32> offs((size_t)ST_COUNT * (n + 1));
   u64* w = (u64*)ws;
   for (u32 i = 0; i < n; ++i) {
     const he_batch_item& it = items[i];
@@ -890,22 +939,11 @@ static he_status batch_build(he_ctx* c, const he_batch_item* items, uint32_t n, 
     bt->levels.push_back(it.level);
     bt->rs.push_back(pd.rs);
   }
-  for (int s = 0; s < ST_COUNT; ++s) {
-    u64 acc = 0;
-    for (u32 i = 0; i < n; ++i) {
-      offs[(size_t)s * (n + 1) + i] = (u32)acc;
-      const LevelPlan& P = c->lv[items[i].level];
-      acc += stage_items(s, c->log_n, items[i].level, c->K, P.beta, P.dt_limbs, pds[i].rs != 0);
-    }
-    if (acc > 0xffffff00ull) return fail(HE_EUNSUPPORTED, "he_batch_create: batch too large");
-    offs[(size_t)s * (n + 1) + n] = (u32)acc;
-    bt->nitems[s] = (u32)acc;
-  }
-  const size_t pbytes = sizeof(PairDesc) * n, obytes = sizeof(u32) * offs.size();
+  const size_t pbytes = sizeof(PairDesc) * n, obytes = sizeof(u32) * (size_t)ST_COUNT * (n + 1);
   bt->host.resize(pbytes + obytes);
   memcpy(bt->host.data(), pds.data(), pbytes);
-  memcpy(bt->host.data() + pbytes, offs.data(), obytes);
-  return HE_OK;
+  batch_cuts(bt.get());
+  return batch_offsets(c, bt.get());
 }
 
 static void batch_bind(he_batch* bt, void* dev) {
@@ -952,59 +990,193 @@ he_status he_batch_create_async(he_ctx* c, const he_batch_item* items, uint32_t 
   return HE_OK;
 }
 
-static void batch_launch_all(he_ctx* c, he_batch* bt, const u64* evk, hipStream_t st) {
-  const Common cm = make_common(c, evk);
+static void batch_drop_graph(he_batch* bt) {
+  if (bt->exec) { (void)hipGraphExecDestroy(bt->exec); bt->exec = nullptr; }
+  if (bt->graph) { (void)hipGraphDestroy(bt->graph); bt->graph = nullptr; }
+  bt->graph_evk = nullptr;
+}
+
+he_status he_batch_set_sched(he_batch* bt, const he_batch_sched* sc, he_stream stream) {
+  if (!bt || !sc) return fail(HE_EINVAL, "he_batch_set_sched: null pointer");
+  he_ctx* c = bt->ctx;
+  TileCfg t;
+  t.epw_c = sc->cols_tile;
+  t.epw_b = sc->blocks_tile;
+  if (!tiles_supported(c->log_n, t))
+    return fail(HE_EUNSUPPORTED, "he_batch_set_sched: tiles %u/%u not available at N = 2^%u", t.epw_c, t.epw_b,
+                c->log_n);
+  if (sc->chunks < 1 || sc->chunks > 8 || sc->chunks > bt->n)
+    return fail(HE_EINVAL, "he_batch_set_sched: chunks %u not in [1, min(8, pairs)]", sc->chunks);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(st));  // the staging buffer may still feed an earlier upload
+  bt->tiles = t;
+  bt->chunks = sc->chunks;
+  batch_cuts(bt);
+  he_status r = batch_offsets(c, bt);
+  if (r != HE_OK) return r;
+  const size_t pbytes = sizeof(PairDesc) * bt->n;
+  HIP_TRY(hipMemcpyAsync((uint8_t*)bt->dev + pbytes, bt->host.data() + pbytes, bt->host.size() - pbytes,
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (bt->chunks > 1 && !bt->side) {
+    HIP_TRY(hipStreamCreateWithFlags(&bt->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&bt->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&bt->ev_join, hipEventDisableTiming));
+  }
+  batch_drop_graph(bt);
+  return HE_OK;
+}
+
+he_status he_batch_get_sched(const he_batch* bt, he_batch_sched* sc) {
+  if (!bt || !sc) return fail(HE_EINVAL, "he_batch_get_sched: null pointer");
+  sc->cols_tile = bt->tiles.epw_c;
+  sc->blocks_tile = bt->tiles.epw_b;
+  sc->chunks = bt->chunks;
+  return HE_OK;
+}
+
+}  // extern "C"
+
+// The 13 stages of pairs [p0, p1) on stream st.
+static void batch_chain(he_ctx* c, he_batch* bt, const Common& cm, u32 p0, u32 p1, hipStream_t st) {
+  const u32 n = bt->n;
   for (int s = 0; s < ST_COUNT; ++s) {
     Batch b{};
-    b.pairs = bt->pairs;
-    b.offs = bt->offs[s];
-    b.npairs = bt->n;
-    b.nitems = bt->nitems[s];
+    b.pairs = bt->pairs + p0;
+    b.offs = bt->offs[s] + p0;
+    b.npairs = p1 - p0;
+    b.nitems = bt->hoffs[(size_t)s * (n + 1) + p1] - bt->hoffs[(size_t)s * (n + 1) + p0];
     double ops = 0, bytes = 0;
     if (c->timing)
-      for (u32 i = 0; i < bt->n; ++i) {
+      for (u32 i = p0; i < p1; ++i) {
         double o = 0, by = 0;
         stage_work(c, s, bt->levels[i], bt->rs[i] != 0, o, by);
         ops += o;
         bytes += by;
       }
-    launch_stage(c, s, cm, b, ops, bytes, st);
+    launch_stage(c, s, cm, b, ops, bytes, st, bt->tiles);
   }
 }
+
+static hipError_t batch_launch_all(he_ctx* c, he_batch* bt, const u64* evk, hipStream_t st) {
+  const Common cm = make_common(c, evk);
+  if (bt->chunks <= 1) {
+    batch_chain(c, bt, cm, 0, bt->n, st);
+    return hipGetLastError();
+  }
+  hipError_t e = hipEventRecord(bt->ev_fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(bt->side, bt->ev_fork, 0);
+  if (e != hipSuccess) return e;
+  for (u32 k = 0; k + 1 < bt->cut.size(); ++k)
+    batch_chain(c, bt, cm, bt->cut[k], bt->cut[k + 1], (k & 1) ? bt->side : st);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(bt->ev_join, bt->side);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, bt->ev_join, 0);
+  return e;
+}
+
+extern "C" {
 
 he_status he_mul_batch(he_ctx* c, he_batch* bt, const uint64_t* evk, int use_graph, he_stream stream) {
   if (!c || !bt || !evk || bt->ctx != c) return fail(HE_EINVAL, "he_mul_batch: bad arguments");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   if (!use_graph || c->timing) {
-    batch_launch_all(c, bt, evk, st);
-    HIP_TRY(hipGetLastError());
+    const hipError_t e = batch_launch_all(c, bt, evk, st);
+    if (e != hipSuccess) return fail(HE_EDEVICE, "he_mul_batch: launch failed: %s", hipGetErrorString(e));
     return HE_OK;
   }
   if (!bt->exec || bt->graph_evk != evk) {
-    if (bt->exec) { (void)hipGraphExecDestroy(bt->exec); bt->exec = nullptr; }
-    if (bt->graph) { (void)hipGraphDestroy(bt->graph); bt->graph = nullptr; }
+    batch_drop_graph(bt);
     hipStream_t cap = nullptr;
     HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      batch_launch_all(c, bt, evk, cap);
+      const hipError_t le = batch_launch_all(c, bt, evk, cap);
       e = hipStreamEndCapture(cap, &bt->graph);
+      if (le != hipSuccess) e = le;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0);
     (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) return fail(HE_EDEVICE, "he_mul_batch: graph capture failed: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+      batch_drop_graph(bt);
+      return fail(HE_EDEVICE, "he_mul_batch: graph capture failed: %s", hipGetErrorString(e));
+    }
     bt->graph_evk = evk;
   }
   HIP_TRY(hipGraphLaunch(bt->exec, st));
   return HE_OK;
 }
 
+// Times `reps` graph replays of the batch under each candidate schedule and
+// keeps the fastest: first the tiles (one chunk), then the chunk count with
+// the best tiles.
+he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32_t reps, he_stream stream,
+                            he_batch_sched* best, double* best_ms) {
+  if (!c || !bt || !evk || bt->ctx != c || reps == 0) return fail(HE_EINVAL, "he_batch_autotune: bad arguments");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto run = [&](const he_batch_sched& sc, double& ms) -> he_status {
+    he_status r = he_batch_set_sched(bt, &sc, stream);
+    if (r != HE_OK) return r;
+    r = he_mul_batch(c, bt, evk, 1, stream);  // capture and warm up
+    if (r != HE_OK) return r;
+    HIP_TRY(hipEventRecord(e0, st));
+    for (u32 i = 0; i < reps; ++i) {
+      r = he_mul_batch(c, bt, evk, 1, stream);
+      if (r != HE_OK) return r;
+    }
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    ms = t / reps;
+    return HE_OK;
+  };
+  std::vector<he_batch_sched> tiles;
+  tiles.push_back({(uint32_t)EPW_C, (uint32_t)EPW_B, 1});
+  if (c->log_n == 16)
+    for (uint32_t ec : {4096u, 2048u})
+      for (uint32_t eb : {2048u, 1024u})
+        if (!(ec == (uint32_t)EPW_C && eb == (uint32_t)EPW_B)) tiles.push_back({ec, eb, 1});
+  he_batch_sched b = tiles[0];
+  double bms = 1e30;
+  he_status r = HE_OK;
+  for (const auto& sc : tiles) {
+    double ms = 0;
+    if ((r = run(sc, ms)) != HE_OK) break;
+    if (ms < bms) { bms = ms; b = sc; }
+  }
+  for (uint32_t ch : {2u, 4u}) {
+    if (r != HE_OK || ch > bt->n) break;
+    he_batch_sched sc = b;
+    sc.chunks = ch;
+    double ms = 0;
+    if ((r = run(sc, ms)) != HE_OK) break;
+    if (ms < bms) { bms = ms; b = sc; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r != HE_OK) return r;
+  r = he_batch_set_sched(bt, &b, stream);
+  if (r != HE_OK) return r;
+  if (best) *best = b;
+  if (best_ms) *best_ms = bms;
+  return HE_OK;
+}
+
 void he_batch_destroy(he_batch* bt) {
   if (!bt) return;
   (void)hipSetDevice(bt->ctx->device);
-  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
-  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  batch_drop_graph(bt);
+  if (bt->side) (void)hipStreamSynchronize(bt->side);
+  if (bt->ev_fork) (void)hipEventDestroy(bt->ev_fork);
+  if (bt->ev_join) (void)hipEventDestroy(bt->ev_join);
+  if (bt->side) (void)hipStreamDestroy(bt->side);
   if (bt->dev && bt->owns_dev) (void)hipFree(bt->dev);
   delete bt;
 }

@@ -71,3 +71,75 @@ def test_batch_new_operands_between_runs():
         _, want = orc.he_mul(3, a_h, b_h, evk_h)
         assert np.array_equal(lib.to_host(out), want)
     bt.close()
+
+
+def _run_check(lib, bt, items, dev, evk, use_graph, tag):
+    import torch
+    for _, _, _, relin, out in items:
+        out.fill_(0)
+        if relin is not None:
+            relin.fill_(0)
+    torch.cuda.synchronize()
+    bt.run(evk, use_graph=use_graph)
+    torch.cuda.synchronize()
+    for i, ((lv, a, b), (_, _, _, relin, out)) in enumerate(zip(dev, items)):
+        p_relin, p_out = lib.he_mul(lv, a, b, evk)
+        assert np.array_equal(lib.to_host(out), lib.to_host(p_out)), (tag, i)
+        if relin is not None:
+            assert np.array_equal(lib.to_host(relin), lib.to_host(p_relin)), (tag, i)
+
+
+def _batch_n16(levels, seed):
+    lib, orc = contexts("n16_L24")
+    evk = lib.to_device(random_evk(orc, 7))
+    dev = [(lv, lib.to_device(a), lib.to_device(b)) for lv, a, b in _pairs(orc, levels, seed)]
+    items = [(lv, a, b, lib.empty(2, lv, orc.N) if i % 3 == 0 else None, lib.empty(2, lv - 1, orc.N))
+             for i, (lv, a, b) in enumerate(dev)]
+    return lib, evk, dev, items
+
+
+@pytest.mark.parametrize("sched", [(4096, 2048, 1), (2048, 2048, 2), (4096, 1024, 4), (2048, 1024, 3),
+                                   (4096, 2048, 8)])
+def test_batch_schedules_bit_exact(sched):
+    """Every tile choice and chunk split gives the plain he_mul results,
+    eagerly and on repeated graph replays."""
+    levels = [24, 4, 17, 9, 24, 5, 12, 20]
+    lib, evk, dev, items = _batch_n16(levels, 500)
+    log("batch sched", sched, levels)
+    bt = lib.batch(items)
+    bt.set_sched(*sched)
+    assert bt.sched() == {"cols_tile": sched[0], "blocks_tile": sched[1], "chunks": sched[2]}
+    for k, use_graph in enumerate((False, True, True, True)):
+        _run_check(lib, bt, items, dev, evk, use_graph, (sched, k))
+    bt.close()
+
+
+def test_batch_autotune_keeps_results():
+    levels = [24, 6, 15, 24, 9, 3]
+    lib, evk, dev, items = _batch_n16(levels, 600)
+    log("batch autotune", levels)
+    bt = lib.batch(items)
+    sc, ms = bt.autotune(evk, reps=1)
+    assert ms > 0
+    assert sc == bt.sched()
+    assert sc["cols_tile"] in (2048, 4096) and sc["blocks_tile"] in (1024, 2048) and sc["chunks"] in (1, 2, 4)
+    for k, use_graph in enumerate((True, False, True)):
+        _run_check(lib, bt, items, dev, evk, use_graph, ("tuned", k))
+    bt.close()
+
+
+def test_batch_sched_errors():
+    import paper_2003_04510_amd as P
+    lib, orc = contexts("n12_L3")
+    evk = lib.to_device(random_evk(orc, 8))
+    dev = [(lv, lib.to_device(a), lib.to_device(b)) for lv, a, b in _pairs(orc, [3, 2], 700)]
+    bt = lib.batch([(lv, a, b, None, lib.empty(2, lv - 1, orc.N)) for lv, a, b in dev])
+    with pytest.raises(P.HeError, match="EUNSUPPORTED|not available"):
+        bt.set_sched(2048, 1024, 1)   # only the default tiles exist at N = 2^12
+    with pytest.raises(P.HeError):
+        bt.set_sched(4096, 2048, 0)
+    with pytest.raises(P.HeError):
+        bt.set_sched(4096, 2048, 3)   # more chunks than pairs
+    bt.set_sched(4096, 2048, 2)
+    bt.run(evk, use_graph=True)
+    bt.close()
