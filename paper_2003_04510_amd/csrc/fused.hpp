@@ -20,6 +20,8 @@
 // kernels decode items in the same order.  Grids are padded to a multiple
 // of 8 and items are handed out so that each XCD walks a contiguous range.
 #pragma once
+#include <type_traits>
+
 #include "ntt.hpp"
 
 namespace he {
@@ -231,26 +233,45 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
   constexpr int TG = Gm::R < 8 ? Gm::R : 8;
   if (which == 2) {
     const auto rl0 = gbl(pd.rl + off), rl1 = gbl(pd.rl + tot + off), d2 = gbl(pd.d2 + off);
+    // the products in FP64 for q < 2^50 (exact, see F64A::mulv), else on
+    // the integer multipliers; both canonical
+    const auto products = [&](auto f64) {
+      constexpr bool F = decltype(f64)::value;
+      const F64A::Mod M = F64A::mod(m.q, m.qinv);
 #pragma unroll
-    for (int k0 = 0; k0 < Gm::R; k0 += TG) {
-      u64 b1[TG], a1[TG], b2[TG], a2[TG];
+      for (int k0 = 0; k0 < Gm::R; k0 += TG) {
+        u64 b1[TG], a1[TG], b2[TG], a2[TG];
 #pragma unroll
-      for (int g = 0; g < TG; ++g) {
-        const u64 idx = threadIdx.x + (k0 + g) * THREADS;
-        b1[g] = ct1[idx]; a1[g] = ct1[tot + idx]; b2[g] = ct2[idx]; a2[g] = ct2[tot + idx];
+        for (int g = 0; g < TG; ++g) {
+          const u64 idx = threadIdx.x + (k0 + g) * THREADS;
+          b1[g] = ct1[idx]; a1[g] = ct1[tot + idx]; b2[g] = ct2[idx]; a2[g] = ct2[tot + idx];
+        }
+#pragma unroll
+        for (int g = 0; g < TG; ++g) {
+          const u64 idx = threadIdx.x + (k0 + g) * THREADS;
+          u64 v0, v1, v;
+          if constexpr (F) {
+            const double B1 = F64A::in(b1[g], M), A1 = F64A::in(a1[g], M);
+            const double B2 = F64A::in(b2[g], M), A2 = F64A::in(a2[g], M);
+            v0 = F64A::to_u64(F64A::mulv(B1, B2, M), M);
+            v1 = F64A::to_u64(F64A::red(F64A::mulv(A1, B2, M) + F64A::mulv(A2, B1, M), M), M);
+            v = F64A::to_u64(F64A::mulv(A1, A2, M), M);
+          } else {
+            U128 s1 = mul_wide(a1[g], b2[g]);
+            add_to(s1, mul_wide(a2[g], b1[g]));
+            v = barrett(mul_wide(a1[g], a2[g]), m);
+            v0 = barrett(mul_wide(b1[g], b2[g]), m);
+            v1 = barrett(s1, m);
+          }
+          rl0[idx] = v0;
+          rl1[idx] = v1;
+          d2[idx] = v;
+          put(k0 + g, v);
+        }
       }
-#pragma unroll
-      for (int g = 0; g < TG; ++g) {
-        const u64 idx = threadIdx.x + (k0 + g) * THREADS;
-        U128 s1 = mul_wide(a1[g], b2[g]);
-        add_to(s1, mul_wide(a2[g], b1[g]));
-        const u64 v = barrett(mul_wide(a1[g], a2[g]), m);
-        rl0[idx] = barrett(mul_wide(b1[g], b2[g]), m);
-        rl1[idx] = barrett(s1, m);
-        d2[idx] = v;
-        put(k0 + g, v);
-      }
-    }
+    };
+    if (f64_mod(m.q)) products(std::true_type{});
+    else products(std::false_type{});
   } else {  // d0 (which 0) or d1 (which 1) of limb level-1, for the rescale
     const u64 h = which == 0 ? 0 : tot;
 #pragma unroll
@@ -338,7 +359,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c,
   const int n2 = c.log_n - LOGS;
   const u32 tpc = (1u << n2) / PL::SUBS;
   const u32 pos = uniform(local % tpc), rest = local / tpc;
-  const u32 limb = uniform(rest % v.nl), z = uniform(rest / v.nl);
+  const u32 z = uniform(rest % v.np), limb = uniform(rest / v.np);  // both polys of a limb adjacent
   const u32 mi = ldc(v.limb_mod + limb);
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
@@ -388,7 +409,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
   const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
   const u32 pos = uniform(local % tpl), rest = local / tpl;
-  const u32 limb = uniform(rest % v.nl), z = uniform(rest / v.nl);
+  const u32 z = uniform(rest % v.np), limb = uniform(rest / v.np);  // both polys of a limb adjacent
   const u32 mi = ldc(v.limb_mod + limb);
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
@@ -582,7 +603,7 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
 
 // ---------------------------------------------------------------- NTT blocks + combine
 // rl_u[i] = rl_u[i] + (ks_u[i] - NTT(z_u[i])) * [P^-1]_{q_i}  (rl holds d_u).
-// Items (u, i, block tile), tile fastest.
+// Items (i, u, block tile), tile fastest.
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
@@ -598,7 +619,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
   const u32 pos = uniform(local % tpl), ui = local / tpl;
-  const u32 i = uniform(ui % pd.level), u = uniform(ui / pd.level);
+  const u32 u = uniform(ui & 1), i = uniform(ui >> 1);  // b and a of limb i adjacent (shared twiddles)
   const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
@@ -720,7 +741,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
 
 // ---------------------------------------------------------------- NTT blocks + rescale combine
 // out_u[i] = (rl_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}; s lives in z.
-// Items (u, i < level-1, block tile), tile fastest.
+// Items (i < level-1, u, block tile), tile fastest.
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
@@ -738,7 +759,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
   const u32 tpl = (1u << n1) / PL::SUBS;
   const u32 nl = pd.level - 1;
   const u32 pos = uniform(local % tpl), ui = local / tpl;
-  const u32 i = uniform(ui % nl), u = uniform(ui / nl);
+  const u32 u = uniform(ui & 1), i = uniform(ui >> 1);  // b and a of limb i adjacent (shared twiddles)
   const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();

@@ -223,16 +223,17 @@ void ntt_launch(const he_ctx* c, bool fwd, const u64* src, u64* dst, u64 src_str
 dim3 ew_grid(u64 total) { return dim3((unsigned)ceil_div(total, EW_THREADS)); }
 
 // ---------------------------------------------------------------- tables
-// Twiddle table entry of w mod m in the arithmetic the kernels use for m.
-Tw2 tw_entry(u64 w, u64 m) {
+// Twiddle table of modulus m (N entries of 16 bytes at t) in the form the
+// kernels read for m: Shoup pairs, or for m < 2^50 the doubles W_k in the
+// first half.
+void tw_fill(Tw2* t, const std::vector<u64>& w, u64 m, u64 N) {
   if (f64_mod(m)) {
-    const double wd = (double)w, wq = wd / (double)m;  // both exact / correctly rounded
-    Tw2 t;
-    memcpy(&t.w, &wd, 8);
-    memcpy(&t.ws, &wq, 8);
-    return t;
+    std::vector<double> d(2 * N, 0.0);
+    for (u64 k = 0; k < N; ++k) d[k] = (double)w[k];  // exact: w < 2^50
+    memcpy(t, d.data(), N * sizeof(Tw2));
+    return;
   }
-  return Tw2{w, shoup63(w, m)};
+  for (u64 k = 0; k < N; ++k) t[k] = Tw2{w[k], shoup63(w[k], m)};
 }
 
 ModInfo make_modinfo(u64 q, u64 N) {
@@ -374,11 +375,14 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     std::vector<u64> pw(N), ipw(N);
     pw[0] = ipw[0] = 1;
     for (u64 k = 1; k < N; ++k) { pw[k] = mulmod(pw[k - 1], psi, m); ipw[k] = mulmod(ipw[k - 1], psii, m); }
+    std::vector<u64> bw(N), ibw(N);
     for (u64 k = 0; k < N; ++k) {
       const unsigned e = bitrev((unsigned)k, log_n);
-      tw[i * N + k] = tw_entry(pw[e], m);
-      itw[i * N + k] = tw_entry(ipw[e], m);
+      bw[k] = pw[e];
+      ibw[k] = ipw[e];
     }
+    tw_fill(tw.data() + i * N, bw, m, N);
+    tw_fill(itw.data() + i * N, ibw, m, N);
   }
   const size_t o_tw = B.add(tw), o_itw = B.add(itw);
   const size_t o_iota = B.add(all_idx);

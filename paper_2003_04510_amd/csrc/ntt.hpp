@@ -31,10 +31,11 @@
 
 namespace he {
 
-// Twiddle tables hold one 16-byte entry per index.  Its meaning depends on
-// the modulus (see IntA / F64A): for q >= 2^50 the pair {W, floor(W 2^63/q)}
-// (2^63-scaled Shoup companion, see shoup63_lazy); for q < 2^50 the bit
-// patterns of the doubles {W, fl(W/q)}.
+// Twiddle tables take 16 bytes per index and modulus.  Their content
+// depends on the modulus (see IntA / F64A): for q >= 2^50 entry k is the
+// pair {W_k, floor(W_k 2^63/q)} (2^63-scaled Shoup companion, see
+// shoup63_lazy); for q < 2^50 the first half of the modulus's table holds
+// the doubles W_k (8 bytes per index) and the second half is unused.
 struct Tw2 {
   u64 w, ws;
 };
@@ -56,7 +57,9 @@ struct IntA {
   struct Scale {
     u64 w, ws;  // Shoup pair (2^64-scaled companion)
   };
+  using Tw = Tw2;
   __device__ static __forceinline__ Mod mod(u64 q, double) { return Mod{q, q << 1, 0 - q, 0 - (q << 1)}; }
+  __device__ static __forceinline__ Tw twid(const Tw2* __restrict__ tw, u64 k, const Mod&) { return tw[k]; }
   __device__ static __forceinline__ V in(u64 x, const Mod&) { return x; }
   // Harvey forward butterfly: x, y in [0, 4q) -> x + w y, x - w y in [0, 4q).
   __device__ static __forceinline__ void fwd(V& x, V& y, const Tw2 t, const Mod& M) {
@@ -85,19 +88,21 @@ struct IntA {
 };
 
 // ---------------------------------------------------------------- FP64 arithmetic
-// For q < 2^50, values are doubles holding integers, kept centred: every
-// butterfly input satisfies |v| < 1.2 q.  A product y w mod q is formed
-// exactly from FMAs:
-//   k  = round(y fl(w/q))            (|y fl(w/q)| < 2^51; the FMA with
+// For q < 2^50, values are doubles holding integers, kept centred.  A
+// product y w mod q (w < q a twiddle or constant) is formed exactly from
+// FMAs, with wq an approximation of w/q of relative error <= 2^-52
+// (fl(w fl(1/q)) for table twiddles, fl(w/q) for constants):
+//   k  = round(y wq)                 (|y wq| < 2^51; the FMA with
 //                                     1.5 2^52 rounds it to an integer)
 //   hi = fl(y w),  lo = y w - hi     (exact: two-product by FMA)
 //   t  = (hi - k q) + lo             (both steps exact: integers < 2^53)
-// so t = y w - k q exactly, with |t| <= (1/2 + |y| 2^-53) q < 0.65 q.
-// A reduction x - round(x fl(1/q)) q leaves |x| <= 0.51 q.  Forward:
-// x' = red(x) + t, y' = red(x) - t (|.| < 1.2 q).  Inverse: x' = red(x + y),
-// y' = (x - y) w with |x|, |y| < 0.7 q, so |x - y| < 1.4 q and the same
-// bounds hold.  The build disables FP contraction, so each step is exactly
-// one rounding as written.
+// so t = y w - k q exactly, with |t| <= (1/2 + |y| 2^-52) q.  A reduction
+// x - round(x fl(1/q)) q leaves |x| <= q/2 (+ a 2^-50 relative margin).
+// Forward: x' = red(x) + t, y' = red(x) - t; with |x|, |y| <= 1.35 q,
+// |t| <= (1/2 + 1.35/4) q and |x'|, |y'| < 1.34 q, so the bound holds at
+// every stage.  Inverse: x' = red(x + y), y' = (x - y) w; with |x|, |y| < q,
+// |x - y| < 2q (so |(x - y) wq| < 2^51) and |y'| < (1/2 + 2/4) q = q.  The
+// build disables FP contraction, so each step is one rounding as written.
 struct F64A {
   using V = double;
   struct Mod {
@@ -106,10 +111,17 @@ struct F64A {
   struct Scale {
     double w, wq;  // w and fl(w/q)
   };
+  struct Tw {
+    double w, wq;
+  };
   static constexpr double RND = 6755399441055744.0;  // 1.5 * 2^52
   static constexpr double TWO52 = 4503599627370496.0;
   static constexpr u64 TWO52_BITS = 0x4330000000000000ull;
   __device__ static __forceinline__ Mod mod(u64 q, double qinv) { return Mod{(double)q, qinv}; }
+  __device__ static __forceinline__ Tw twid(const Tw2* __restrict__ tw, u64 k, const Mod& M) {
+    const double w = reinterpret_cast<const double*>(tw)[k];
+    return Tw{w, __dmul_rn(w, M.qinv)};
+  }
   // x < 2^52 to double (exact)
   __device__ static __forceinline__ V in(u64 x, const Mod&) {
     return __longlong_as_double((long long)(x | TWO52_BITS)) - TWO52;
@@ -125,18 +137,28 @@ struct F64A {
     const double r = __fma_rn(-k, M.q, hi);
     return __dadd_rn(r, lo);
   }
-  __device__ static __forceinline__ void fwd(V& x, V& y, const Tw2 t, const Mod& M) {
+  // a b mod q for 0 <= a, b < q, as an integer of magnitude <= 3q/4:
+  // k = round(fl(a b) fl(1/q)) is within 3/4 of a b / q (a b / q < 2^50),
+  // and (fl(a b) - k q) + (a b - fl(a b)) is exact as above.
+  __device__ static __forceinline__ double mulv(double a, double b, const Mod& M) {
+    const double hi = __dmul_rn(a, b);
+    const double lo = __fma_rn(a, b, -hi);
+    const double k = __fma_rn(hi, M.qinv, RND) - RND;
+    return __dadd_rn(__fma_rn(-k, M.q, hi), lo);
+  }
+  __device__ static __forceinline__ void fwd(V& x, V& y, const Tw t, const Mod& M) {
     const double X = red(x, M);
-    const double T = mulw(y, __longlong_as_double((long long)t.w), __longlong_as_double((long long)t.ws), M);
+    const double T = mulw(y, t.w, t.wq, M);
     x = X + T;
     y = X - T;
   }
-  __device__ static __forceinline__ void inv(V& x, V& y, const Tw2 t, const Mod& M) {
+  __device__ static __forceinline__ void inv(V& x, V& y, const Tw t, const Mod& M) {
     const double X = x, Y = y;
     x = red(X + Y, M);
-    y = mulw(X - Y, __longlong_as_double((long long)t.w), __longlong_as_double((long long)t.ws), M);
+    y = mulw(X - Y, t.w, t.wq, M);
   }
-  // |c| <= 0.7 q, c integral -> canonical u64
+  // |c| <= q, c integral, c mod q in [0, q) -> canonical u64 (c = q cannot
+  // occur: outputs come from red() or mulw(), both below q in magnitude)
   __device__ static __forceinline__ u64 to_u64(double c, const Mod& M) {
     const double v = c < 0.0 ? c + M.q : c;
     return (u64)__double_as_longlong(v + TWO52) - TWO52_BITS;
@@ -211,7 +233,7 @@ __device__ __forceinline__ void round_math(typename A::V (&x)[1 << LOGR], int tt
 #pragma unroll
         for (int i = 0; i < G; ++i) {
           if (i & half) continue;
-          A::fwd(v[i], v[i + half], tw[mloc * base + (blk << k) + (u64)(i >> (rr - k))], M);
+          A::fwd(v[i], v[i + half], A::twid(tw, mloc * base + (blk << k) + (u64)(i >> (rr - k)), M), M);
         }
       }
     } else {
@@ -222,7 +244,7 @@ __device__ __forceinline__ void round_math(typename A::V (&x)[1 << LOGR], int tt
 #pragma unroll
         for (int i = 0; i < G; ++i) {
           if (i & half) continue;
-          A::inv(v[i], v[i + half], tw[mloc * base + (blk << k) + (u64)(i >> (rr - k))], M);
+          A::inv(v[i], v[i + half], A::twid(tw, mloc * base + (blk << k) + (u64)(i >> (rr - k)), M), M);
         }
       }
     }
