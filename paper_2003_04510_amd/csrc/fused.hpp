@@ -9,9 +9,11 @@
 //   k_list_blocks      NTT / INTT "blocks" pass over a limb list of a pair
 //   k_conv             fast base conversion (mod up / mod down)
 //   k_ip               evk inner product (Fig. 2 region 2)
-//   k_ntt_combine      NTT "blocks" pass + mod-down combine
 //   k_lift_ntt_cols    rescale lift of the dropped limb + NTT "cols" pass
-//   k_ntt_rescale      NTT "blocks" pass + rescale combine
+//   k_ntt_combine      NTT "blocks" passes of z and s + mod-down combine
+//                      + rescale combine
+//   k_ntt_rescale      NTT "blocks" pass + rescale combine (stand-alone
+//                      rescale only)
 //
 // Work items.  A launch covers the work items of every pair of a batch: the
 // items of pair p are [offs[p], offs[p+1]) (per-stage prefix sums built on
@@ -78,18 +80,20 @@ struct PlanDev {
 };
 
 // One HE Mul of a launch: operands, outputs, workspace, plan.
-//   ct1, ct2 [2][level][N]; rl [2][level][N] (relinearized, also d0/d1 scratch);
+//   ct1, ct2 [2][level][N]; rl [2][level][N] (holds d0, d1 of the tensor
+//   product; receives the relinearized ciphertext when wrl);
 //   out [2][level-1][N] or null; r: coefficient form of the dropped limb
 //   [2][N] (stand-alone rescale only, else null);
 //   workspace: d2 [level], y [level+2], dt [dt_limbs], ks [2][level+K+1],
-//   z [2][level], zc [2][level] (limbs of N words).
+//   z [2][level], zc [2][level] (limbs of N words; zc_u[i], i < level-1,
+//   receives the rescale's s_u[i] once the mod-down conversion is consumed).
 struct PairDesc {
   const u64 *ct1, *ct2;
   u64 *rl, *out;
   const u64* r;
   u64 *d2, *y, *dt, *ks, *z, *zc;
   const PlanDev* plan;
-  u32 level, rs;  // rs: rescale requested
+  u32 level, rs, wrl, pad;  // rs: rescale requested; wrl: write the relinearized ciphertext to rl
 };
 
 // Per-launch constants.
@@ -141,10 +145,10 @@ enum Stage : int {
   ST_KS_ICOLS,     // INTT cols of the special limbs (+ limb level-1)
   ST_MD_CONV,      // mod-down conversion
   ST_Z_NCOLS,      // NTT cols of z
-  ST_COMBINE,      // NTT blocks of z + combine
-  ST_LIFT,         // rescale lift + NTT cols
-  ST_RESCALE,      // NTT blocks + rescale combine
-  ST_COUNT
+  ST_LIFT,         // rescale lift + NTT cols (s into zc)
+  ST_COMBINE,      // NTT blocks of z and s + combine + rescale combine
+  ST_COUNT,
+  ST_RESCALE = ST_COUNT  // NTT blocks + rescale combine, stand-alone rescale only
 };
 
 // Tiles per limb of a cols / blocks pass at ring degree 2^log_n.
@@ -173,8 +177,8 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
     case ST_KS_ICOLS: return 2 * (K + ex) * tc;
     case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_c;
     case ST_Z_NCOLS: return 2 * level * tc;
-    case ST_COMBINE: return 2 * level * tb;
     case ST_LIFT: return rs ? 2 * (level - 1) * tc : 0;
+    case ST_COMBINE: return 2 * level * tb;
     case ST_RESCALE: return rs ? 2 * (level - 1) * tb : 0;
   }
   return 0;
@@ -601,8 +605,12 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
   }
 }
 
-// ---------------------------------------------------------------- NTT blocks + combine
-// rl_u[i] = rl_u[i] + (ks_u[i] - NTT(z_u[i])) * [P^-1]_{q_i}  (rl holds d_u).
+// ---------------------------------------------------------------- NTT blocks + combine + rescale
+// v_u[i] = d_u[i] + (ks_u[i] - NTT(z_u[i])) * [P^-1]_{q_i}  (rl holds d_u),
+// the relinearized ciphertext, written to rl when requested (wrl); when
+// rescaling, for i < level-1 also
+//   out_u[i] = (v_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}   (s_u in zc),
+// so v never makes a trip through HBM unless it is an output.
 // Items (i, u, block tile), tile fastest.
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common c, Batch b) {
@@ -620,16 +628,30 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   const u32 tpl = (1u << n1) / PL::SUBS;
   const u32 pos = uniform(local % tpl), ui = local / tpl;
   const u32 u = uniform(ui & 1), i = uniform(ui >> 1);  // b and a of limb i adjacent (shared twiddles)
+  const bool resc = pd.rs && i + 1 < pd.level;
+  if (!resc && !pd.wrl) return;  // the dropped limb with no relinearized output
+  const PlanDev* P = pd.plan;
   const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
+  const u64 limb_off = ((u64)(u * pd.level + i) << c.log_n) + toff;
   u64 xi[Gm::R];
-  const auto p = gbl(pd.z + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS));
+  const auto zp = gbl(pd.z + limb_off + ((u64)sub << LOGS));
 #pragma unroll
-  for (int k = 0; k < Gm::R; ++k) xi[k] = p[RF::elem(tt, k / RF::G, k % RF::G)];
+  for (int k = 0; k < Gm::R; ++k) xi[k] = zp[RF::elem(tt, k / RF::G, k % RF::G)];
   const u64 pw = ldc(c.pinv + 2 * i), pws = ldc(c.pinv + 2 * i + 1);
   const auto ksu = gbl(pd.ks + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff);
-  const auto rlu = gbl(pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff);
+  const auto rlu = gbl(pd.rl + limb_off);
+  const auto sp = gbl(pd.zc + limb_off + ((u64)sub << LOGS));
+  const auto ou = gbl(pd.out + ((u64)(u * (pd.level - 1) + i) << c.log_n) + toff);
+  u64 qw = 0, qws = 0;
+  if (resc) {
+    const u64* ql = ldc(&P->qlinv);
+    qw = ldc(ql + 2 * i);
+    qws = ldc(ql + 2 * i + 1);
+  }
+  const Tw2* twl = c.tw + ((u64)i << c.log_n);
+  const u64 base = (1ull << n1) + blk0 + sub;
   with_arith(m.q, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
@@ -637,9 +659,22 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
     typename A::V x[Gm::R];
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
-    sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
-                                                  (1ull << n1) + blk0 + sub, M, [](int, typename A::V) {});
+    sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, twl, base, M, [](int, typename A::V) {});
     lds_barrier();
+    u64 Z[Gm::R];  // NTT(z) in the coalesced epilogue order
+#pragma unroll
+    for (int k = 0; k < Gm::R; ++k) {
+      const int idx = threadIdx.x + k * THREADS;
+      Z[k] = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
+    }
+    if (resc) {
+      lds_barrier();  // every Z is read before the tile is reused
+#pragma unroll
+      for (int k = 0; k < Gm::R; ++k) x[k] = A::in(sp[RF::elem(tt, k / RF::G, k % RF::G)], M);
+      sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, twl, base, M,
+                                                    [](int, typename A::V) {});
+      lds_barrier();
+    }
     constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
 #pragma unroll
     for (int k0 = 0; k0 < Gm::R; k0 += TG) {
@@ -653,9 +688,13 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 #pragma unroll
       for (int g = 0; g < TG; ++g) {
         const int idx = threadIdx.x + (k0 + g) * THREADS;
-        const u64 Z = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
-        const u64 md = shoup_lazy(kv[g] + m.q - Z, pw, pws, m.q);
-        rlu[idx] = csub(csub(dv[g] + md, m.q << 1), m.q);
+        const u64 md = shoup_lazy(kv[g] + m.q - Z[k0 + g], pw, pws, m.q);
+        const u64 v = csub(csub(dv[g] + md, m.q << 1), m.q);
+        if (pd.wrl) rlu[idx] = v;
+        if (resc) {
+          const u64 S = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
+          ou[idx] = csub(shoup_lazy(v + m.q - S, qw, qws, m.q), m.q);
+        }
       }
     }
   });
@@ -726,7 +765,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
     if (2 * r >= ql) v = submod(v, qlm, m.q);
     x[k] = v;
   }
-  const auto out = gbl(pd.z + ((u64)(u * nl + i) << c.log_n) + col);
+  const auto out = gbl(pd.zc + ((u64)(u * pd.level + i) << c.log_n) + col);
   with_arith(m.q, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
@@ -740,7 +779,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
 }
 
 // ---------------------------------------------------------------- NTT blocks + rescale combine
-// out_u[i] = (rl_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}; s lives in z.
+// out_u[i] = (rl_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}; s lives in zc.
 // Items (i < level-1, u, block tile), tile fastest.
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common c, Batch b) {
@@ -764,7 +803,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   u64 xi[Gm::R];
-  const auto p = gbl(pd.z + ((u64)(u * nl + i) << c.log_n) + toff + ((u64)sub << LOGS));
+  const auto p = gbl(pd.zc + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS));
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) xi[k] = p[RF::elem(tt, k / RF::G, k % RF::G)];
   const u64* ql = ldc(&P->qlinv);

@@ -675,10 +675,10 @@ bool tiles_supported(u32 log_n, TileCfg t) {
 }
 
 const char* stage_name(int s) {
-  static const char* names[ST_COUNT] = {"tensor_intt", "y_intt_cols", "modup_convert", "modup_ntt_cols",
-                                        "modup_ntt_blocks", "inner_product", "special_intt_blocks",
-                                        "special_intt_cols", "moddown_convert", "moddown_ntt_cols", "ntt_combine",
-                                        "lift_ntt_cols", "ntt_rescale"};
+  static const char* names[ST_COUNT + 1] = {"tensor_intt", "y_intt_cols", "modup_convert", "modup_ntt_cols",
+                                            "modup_ntt_blocks", "inner_product", "special_intt_blocks",
+                                            "special_intt_cols", "moddown_convert", "moddown_ntt_cols",
+                                            "lift_ntt_cols", "ntt_combine_rescale", "ntt_rescale"};
   return names[s];
 }
 
@@ -686,7 +686,7 @@ const char* stage_name(int s) {
 // butterflies for NTT passes (+N per limb for the inverse cols scaling),
 // 64x64 multiply-accumulates for conversion and inner product, modular
 // products for the element-wise parts; bytes are limbs read + written x 8N.
-void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double& bytes) {
+void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double& bytes, bool wrl = true) {
   const LevelPlan& P = c->lv[level];
   const double N = (double)c->N, hN = N / 2, K = c->K, l = level, ex = rs ? 1 : 0;
   const int n1 = (int)c->log_n / 2, n2 = (int)c->log_n - n1;
@@ -704,7 +704,12 @@ void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double
     case ST_KS_ICOLS: ops = 2 * (K + ex) * (hN * n1 + N); bytes = 4 * (K + ex) * N * 8; break;
     case ST_MD_CONV: ops = 2 * K * l * N; bytes = 2 * (K + l) * N * 8; break;
     case ST_Z_NCOLS: ops = 2 * l * hN * n1; bytes = 4 * l * N * 8; break;
-    case ST_COMBINE: ops = 2 * l * hN * n2 + 2 * l * N; bytes = 2 * l * 4 * N * 8; break;
+    case ST_COMBINE: {  // z, ks, d in; s in and out out when rescaling; rl out when requested
+      const double lo = (rs && !wrl) ? l - 1 : l;  // limbs combined
+      ops = 2 * lo * hN * n2 + 2 * lo * N + (rs ? 2 * (l - 1) * (hN * n2 + N) : 0);
+      bytes = (2 * lo * 3 + (wrl ? 2 * l : 0) + (rs ? 2 * (l - 1) * 2 : 0)) * N * 8;
+      break;
+    }
     case ST_LIFT: ops = rs ? 2 * (l - 1) * hN * n1 : 0; bytes = rs ? (2 * (l - 1) + 6) * N * 8 : 0; break;
     case ST_RESCALE: ops = rs ? 2 * (l - 1) * hN * n2 : 0; bytes = rs ? 2 * (l - 1) * 3 * N * 8 : 0; break;
     default: ops = bytes = 0;
@@ -781,6 +786,7 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
   PairDesc pd{};
   pd.ct1 = ct1; pd.ct2 = ct2; pd.out = out; pd.r = nullptr; pd.plan = P.plan; pd.level = level;
   pd.rs = out ? 1 : 0;
+  pd.wrl = relin ? 1 : 0;
   const u64 used = pair_layout(c, level, (u64*)ws, pd);
   pd.rl = relin ? relin : (u64*)ws + used;
   const Common cm = make_common(c, evk);
@@ -790,7 +796,7 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
     b.npairs = 1;
     b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, pd.rs != 0);
     double ops = 0, bytes = 0;
-    if (c->timing) stage_work(c, s, level, pd.rs != 0, ops, bytes);
+    if (c->timing) stage_work(c, s, level, pd.rs != 0, ops, bytes, pd.wrl != 0);
     launch_stage(c, s, cm, b, ops, bytes, st);
   }
   HIP_TRY(hipGetLastError());
@@ -812,7 +818,7 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
   const LevelPlan& P = c->lv[level];
   PairDesc pd{};
   pd.rl = const_cast<u64*>(d_in);  // read only by the rescale stages
-  pd.out = d_out; pd.r = R; pd.z = R + 2 * N; pd.plan = P.plan; pd.level = level; pd.rs = 1;
+  pd.out = d_out; pd.r = R; pd.zc = R + 2 * N; pd.plan = P.plan; pd.level = level; pd.rs = 1;
   const Common cm = make_common(c, nullptr);
   for (int s : {(int)ST_LIFT, (int)ST_RESCALE}) {
     Batch b{};
@@ -847,7 +853,7 @@ struct he_batch {
   std::vector<u32> hoffs;              // host copy of the offsets [ST_COUNT][n + 1]
   u32 nitems[ST_COUNT] = {};
   std::vector<u32> levels;
-  std::vector<uint8_t> rs;
+  std::vector<uint8_t> rs, wrl;
   TileCfg tiles{};
   u32 chunks = 1;
   std::vector<u32> cut{};              // chunk boundaries in pairs [chunks + 1]
@@ -932,7 +938,7 @@ static he_status batch_build(he_ctx* c, const he_batch_item* items, uint32_t n, 
     const he_batch_item& it = items[i];
     PairDesc& pd = pds[i];
     pd.ct1 = it.ct1; pd.ct2 = it.ct2; pd.out = it.out; pd.r = nullptr;
-    pd.plan = c->lv[it.level].plan; pd.level = it.level; pd.rs = it.out ? 1 : 0;
+    pd.plan = c->lv[it.level].plan; pd.level = it.level; pd.rs = it.out ? 1 : 0; pd.wrl = it.relin ? 1 : 0;
     w += pair_layout(c, it.level, w, pd);
     if (it.relin) {
       pd.rl = it.relin;
@@ -942,6 +948,7 @@ static he_status batch_build(he_ctx* c, const he_batch_item* items, uint32_t n, 
     }
     bt->levels.push_back(it.level);
     bt->rs.push_back(pd.rs);
+    bt->wrl.push_back(pd.wrl);
   }
   const size_t pbytes = sizeof(PairDesc) * n, obytes = sizeof(u32) * (size_t)ST_COUNT * (n + 1);
   bt->host.resize(pbytes + obytes);
@@ -1055,7 +1062,7 @@ static void batch_chain(he_ctx* c, he_batch* bt, const Common& cm, u32 p0, u32 p
     if (c->timing)
       for (u32 i = p0; i < p1; ++i) {
         double o = 0, by = 0;
-        stage_work(c, s, bt->levels[i], bt->rs[i] != 0, o, by);
+        stage_work(c, s, bt->levels[i], bt->rs[i] != 0, o, by, bt->wrl[i] != 0);
         ops += o;
         bytes += by;
       }

@@ -54,6 +54,13 @@ def _he_mul_case(w, level, seed=1):
         assert np.array_equal(lib.to_host(out), want_out)
         # he_rescale alone
         assert np.array_equal(lib.to_host(lib.rescale(level, relin)), want_out)
+        # rescaled output only (the relinearized ciphertext never written)
+        _, out_only = lib.he_mul(level, d1, d2, de, relin=False, rescale=True)
+        assert np.array_equal(lib.to_host(out_only), want_out)
+        # relinearized output only
+        relin_only, none = lib.he_mul(level, d1, d2, de, relin=True, rescale=False)
+        assert none is None
+        assert np.array_equal(lib.to_host(relin_only), want_relin)
 
 
 @pytest.mark.parametrize("level", [3, 2, 1])
