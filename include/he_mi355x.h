@@ -190,6 +190,9 @@ he_status he_batch_autotune(he_ctx* ctx, he_batch* batch, const uint64_t* d_evk,
  * one HE Mul with rescale (level >= 2) on operands ct1, ct2 [2][level][N]
  * into out [2][level-1][N] (device buffers owned by the caller, untouched
  * until the request completes); the arrival time is taken at submission.
+ * The server runs on streams of its own that do not wait for any caller
+ * stream: ct1 and ct2 must hold their final values when submitted (for
+ * example, the caller synchronized the stream that wrote them).
  * he_server_progress never blocks: it retires batches whose work finished
  * and, per ring, admits queued requests in arrival order while their
  * workspace fits the arena (HBM footprint) and at most max_batch per batch,

@@ -85,8 +85,10 @@ struct PlanDev {
 //   out [2][level-1][N] or null; r: coefficient form of the dropped limb
 //   [2][N] (stand-alone rescale only, else null);
 //   workspace: d2 [level], y [level+2], dt [dt_limbs], ks [2][level+K+1],
-//   z [2][level], zc [2][level] (limbs of N words; zc_u[i], i < level-1,
-//   receives the rescale's s_u[i] once the mod-down conversion is consumed).
+//   z [2][level], zc [2][level] (limbs of N words).  d2 and y are adjacent;
+//   once the inner product has consumed them, s_u[i] of the rescale
+//   (i < level-1) is written at limb u*level + i from d2 on, which stays
+//   below y[level] and y[level+1] (still read by the lift).
 struct PairDesc {
   const u64 *ct1, *ct2;
   u64 *rl, *out;
@@ -145,7 +147,7 @@ enum Stage : int {
   ST_KS_ICOLS,     // INTT cols of the special limbs (+ limb level-1)
   ST_MD_CONV,      // mod-down conversion
   ST_Z_NCOLS,      // NTT cols of z
-  ST_LIFT,         // rescale lift + NTT cols (s into zc)
+  ST_LIFT,         // rescale lift + NTT cols (s over d2 / y)
   ST_COMBINE,      // NTT blocks of z and s + combine + rescale combine
   ST_COUNT,
   ST_RESCALE = ST_COUNT  // NTT blocks + rescale combine, stand-alone rescale only
@@ -609,7 +611,7 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
 // v_u[i] = d_u[i] + (ks_u[i] - NTT(z_u[i])) * [P^-1]_{q_i}  (rl holds d_u),
 // the relinearized ciphertext, written to rl when requested (wrl); when
 // rescaling, for i < level-1 also
-//   out_u[i] = (v_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}   (s_u in zc),
+//   out_u[i] = (v_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}   (s_u over d2),
 // so v never makes a trip through HBM unless it is an output.
 // Items (i, u, block tile), tile fastest.
 template <int LOGS, int EPW>
@@ -642,7 +644,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   const u64 pw = ldc(c.pinv + 2 * i), pws = ldc(c.pinv + 2 * i + 1);
   const auto ksu = gbl(pd.ks + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff);
   const auto rlu = gbl(pd.rl + limb_off);
-  const auto sp = gbl(pd.zc + limb_off + ((u64)sub << LOGS));
+  const auto sp = gbl(pd.d2 + limb_off + ((u64)sub << LOGS));
   const auto ou = gbl(pd.out + ((u64)(u * (pd.level - 1) + i) << c.log_n) + toff);
   u64 qw = 0, qws = 0;
   if (resc) {
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
     if (2 * r >= ql) v = submod(v, qlm, m.q);
     x[k] = v;
   }
-  const auto out = gbl(pd.zc + ((u64)(u * pd.level + i) << c.log_n) + col);
+  const auto out = gbl(pd.d2 + ((u64)(u * pd.level + i) << c.log_n) + col);
   with_arith(m.q, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
@@ -779,7 +781,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
 }
 
 // ---------------------------------------------------------------- NTT blocks + rescale combine
-// out_u[i] = (rl_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}; s lives in zc.
+// out_u[i] = (rl_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}; s lives over d2.
 // Items (i < level-1, u, block tile), tile fastest.
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common c, Batch b) {
@@ -803,7 +805,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   u64 xi[Gm::R];
-  const auto p = gbl(pd.zc + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS));
+  const auto p = gbl(pd.d2 + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS));
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) xi[k] = p[RF::elem(tt, k / RF::G, k % RF::G)];
   const u64* ql = ldc(&P->qlinv);

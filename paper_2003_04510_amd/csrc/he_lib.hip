@@ -330,7 +330,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   if (L < 1 || L > 64 || K < 1 || K > 32 || dnum < 1 || dnum > L || dnum > 8)
     return fail(HE_EINVAL, "need 1 <= dnum <= min(L, 8), L <= 64, 1 <= K <= 32");
   const u64 N = 1ull << log_n;
-  std::unique_ptr<he_ctx> c(new he_ctx);
+  std::unique_ptr<he_ctx, void (*)(he_ctx*)> c(new he_ctx, he_ctx_destroy);  // frees device memory on errors
   c->log_n = log_n; c->L = L; c->K = K; c->dnum = dnum; c->N = N;
   c->alpha = (L + dnum - 1) / dnum;
   c->device = device;
@@ -699,7 +699,7 @@ void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double
     case ST_MU_CONV: ops = macs * N; bytes = (l + P.dt_limbs) * N * 8; break;
     case ST_DT_NCOLS: ops = P.dt_limbs * hN * n1; bytes = 2.0 * P.dt_limbs * N * 8; break;
     case ST_DT_NBLOCKS: ops = P.dt_limbs * hN * n2; bytes = 2.0 * P.dt_limbs * N * 8; break;
-    case ST_IP: ops = 2.0 * P.beta * ne * N; bytes = (3.0 * P.beta + 2) * ne * N * 8; break;
+    case ST_IP: ops = 2.0 * P.beta * ne * N; bytes = (3.0 * P.beta + 2) * ne * N * 8 + 2 * ex * N * 8; break;
     case ST_KS_IBLOCKS: ops = 2 * (K + ex) * hN * n2; bytes = 4 * (K + ex) * N * 8; break;
     case ST_KS_ICOLS: ops = 2 * (K + ex) * (hN * n1 + N); bytes = 4 * (K + ex) * N * 8; break;
     case ST_MD_CONV: ops = 2 * K * l * N; bytes = 2 * (K + l) * N * 8; break;
@@ -790,15 +790,16 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
   const u64 used = pair_layout(c, level, (u64*)ws, pd);
   pd.rl = relin ? relin : (u64*)ws + used;
   const Common cm = make_common(c, evk);
-  for (int s = 0; s < ST_COUNT; ++s) {
+  auto run = [&](int s, hipStream_t on) {
     Batch b{};
     b.one = pd;
     b.npairs = 1;
     b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, pd.rs != 0);
     double ops = 0, bytes = 0;
     if (c->timing) stage_work(c, s, level, pd.rs != 0, ops, bytes, pd.wrl != 0);
-    launch_stage(c, s, cm, b, ops, bytes, st);
-  }
+    launch_stage(c, s, cm, b, ops, bytes, on);
+  };
+  for (int s = 0; s < ST_COUNT; ++s) run(s, st);
   HIP_TRY(hipGetLastError());
   return HE_OK;
 }
@@ -818,7 +819,7 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
   const LevelPlan& P = c->lv[level];
   PairDesc pd{};
   pd.rl = const_cast<u64*>(d_in);  // read only by the rescale stages
-  pd.out = d_out; pd.r = R; pd.zc = R + 2 * N; pd.plan = P.plan; pd.level = level; pd.rs = 1;
+  pd.out = d_out; pd.r = R; pd.d2 = R + 2 * N; pd.plan = P.plan; pd.level = level; pd.rs = 1;
   const Common cm = make_common(c, nullptr);
   for (int s : {(int)ST_LIFT, (int)ST_RESCALE}) {
     Batch b{};

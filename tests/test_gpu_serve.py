@@ -15,6 +15,8 @@ pytestmark = pytest.mark.gpu
 
 
 def test_served_results_equal_alone():
+    import torch
+
     import paper_2003_04510_amd as P
     rng = np.random.default_rng(9)
     rings = []
@@ -36,6 +38,7 @@ def test_served_results_equal_alone():
         b = ops[int(rng.integers(0, 4))][:, :lv, :].contiguous()
         out = lib.empty(2, lv - 1, orc.N)
         reqs[i] = (r, lv, a, b, out)
+        torch.cuda.synchronize()  # the server's streams do not wait for torch's
         srv.submit(rid[r], i, lv, a, b, out)
         if i % 7 == 0:
             srv.progress()
