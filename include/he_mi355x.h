@@ -155,8 +155,9 @@ void he_batch_destroy(he_batch* batch);
 
 /* Batch schedule (no paper passage: an implementation choice of how the
  * batch's work is laid on the device).  cols_tile / blocks_tile: elements
- * per workgroup of the NTT "cols" / "blocks" passes (defaults 4096 / 2048;
- * at N = 2^16 also 2048 / 1024).  chunks (1..8, at most the pair count):
+ * per workgroup of the NTT "cols" / "blocks" passes (defaults 4096 / 2048,
+ * at N = 2^16 4096 / 1024; there any of cols 2048 / 4096 with blocks
+ * 1024 / 2048).  chunks (1..8, at most the pair count):
  * the pairs are split into that many contiguous groups of about equal total
  * level; their stage sequences alternate between the batch's stream and a
  * side stream the batch owns, so stages of different groups overlap; a

@@ -10,6 +10,7 @@
 //   k_conv             fast base conversion (mod up / mod down)
 //   k_ip               evk inner product (Fig. 2 region 2)
 //   k_lift_ntt_cols    rescale lift of the dropped limb + NTT "cols" pass
+//   k_zcols_lift       the NTT "cols" pass of z and the lift in one launch
 //   k_ntt_combine      NTT "blocks" passes of z and s + mod-down combine
 //                      + rescale combine
 //   k_ntt_rescale      NTT "blocks" pass + rescale combine (stand-alone
@@ -146,11 +147,12 @@ enum Stage : int {
   ST_KS_IBLOCKS,   // INTT blocks of the special limbs (+ limb level-1)
   ST_KS_ICOLS,     // INTT cols of the special limbs (+ limb level-1)
   ST_MD_CONV,      // mod-down conversion
-  ST_Z_NCOLS,      // NTT cols of z
-  ST_LIFT,         // rescale lift + NTT cols (s over d2 / y)
+  ST_Z_NCOLS,      // NTT cols of z, and the rescale lift + NTT cols of s (over d2 / y)
   ST_COMBINE,      // NTT blocks of z and s + combine + rescale combine
   ST_COUNT,
-  ST_RESCALE = ST_COUNT  // NTT blocks + rescale combine, stand-alone rescale only
+  // stand-alone rescale only
+  ST_LIFT = ST_COUNT,  // rescale lift + NTT cols
+  ST_RESCALE           // NTT blocks + rescale combine
 };
 
 // Tiles per limb of a cols / blocks pass at ring degree 2^log_n.
@@ -178,7 +180,7 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
     case ST_KS_IBLOCKS: return 2 * (K + ex) * tb;
     case ST_KS_ICOLS: return 2 * (K + ex) * tc;
     case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_c;
-    case ST_Z_NCOLS: return 2 * level * tc;
+    case ST_Z_NCOLS: return 2 * level * tc + (rs ? 2 * (level - 1) * tc : 0);
     case ST_LIFT: return rs ? 2 * (level - 1) * tc : 0;
     case ST_COMBINE: return 2 * level * tb;
     case ST_RESCALE: return rs ? 2 * (level - 1) * tb : 0;
@@ -350,17 +352,12 @@ __device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& p
 }
 
 template <bool FWD, int LOGS, int EPW, int ST>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c, Batch b) {
+__device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& pd, u32 local, u64* lds) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
   constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
   using RF = RoundShape<LOGS, LOGR, FIRST>;
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
-  const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= b.nitems) return;
-  u32 local;
-  const PairDesc pd = resolve(b, uniform(w), local);
   const ListView v = list_view<ST>(c, pd);
   const int n2 = c.log_n - LOGS;
   const u32 tpc = (1u << n2) / PL::SUBS;
@@ -393,6 +390,16 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c,
           out[(u64)e << n2] = FWD ? A::template out<true>(val, M) : A::out_scaled(val, sc, M);
         });
   });
+}
+
+template <bool FWD, int LOGS, int EPW, int ST>
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c, Batch b) {
+  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
+  const u32 w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  list_cols_item<FWD, LOGS, EPW, ST>(c, pd, local, lds);
 }
 
 // Blocks pass; the side whose register layout is thread-contiguous
@@ -710,16 +717,11 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 // z_u[l-1] = zc_u[level - 1].  Then s = centered(r) mod q_i.
 // Items (u, column tile, i < level-1), i fastest.
 template <int LOGS, int EPW>
-__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Common c, Batch b) {
+__device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u32 local, u64* lds) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
   using RF = RoundShape<LOGS, LOGR, 0>;
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
-  const u32 w = xcd_item(blockIdx.x, gridDim.x);
-  if (w >= b.nitems) return;
-  u32 local;
-  const PairDesc pd = resolve(b, uniform(w), local);
   const PlanDev* P = pd.plan;
   const int n2 = c.log_n - LOGS;
   const u32 tpc = (1u << n2) / PL::SUBS;
@@ -778,6 +780,32 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
         xa, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n), 1, M,
         [&](int e, typename A::V v) { out[(u64)e << n2] = A::template out<true>(v, M); });
   });
+}
+
+template <int LOGS, int EPW>
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Common c, Batch b) {
+  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
+  const u32 w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  lift_item<LOGS, EPW>(c, pd, local, lds);
+}
+
+// NTT cols pass of z (mod-down) and, when rescaling, the lift + NTT cols
+// pass of s, in one launch: items [0, 2 level tiles) are z's, the rest s's.
+// The two touch disjoint buffers (z cols: zc -> z; lift: zc_u[level-1], y,
+// ks -> s over d2).
+template <int LOGS, int EPW>
+__global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c, Batch b) {
+  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
+  const u32 w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const u32 nz = uniform(2 * pd.level * cols_tiles(c.log_n, EPW));
+  if (local < nz) list_cols_item<true, LOGS, EPW, ST_Z_NCOLS>(c, pd, local, lds);
+  else lift_item<LOGS, EPW>(c, pd, local - nz, lds);
 }
 
 // ---------------------------------------------------------------- NTT blocks + rescale combine
