@@ -68,6 +68,7 @@ struct PlanDev {
   const ConvTarget* md_tg;    // [level]
   const u32* md_c;
   const u32* dt_mod;   // modulus of each mod-up limb [dt_limbs]
+  const u32* dt_perm;  // mod-up limbs ordered by modulus (limbs sharing a twiddle table adjacent)
   const u32* emod;     // modulus of extended-basis limb e [level + K]
   const u32* y_mod;    // INTT list d2 (+ d0, d1 of limb level-1) [level + 2]
   const u64* y_scale;  // Shoup pairs: N^-1 [(Qt_j/q_i)^-1]_{q_i}, N^-1
@@ -324,6 +325,7 @@ struct ListView {
   u64 zs, zd;  // polynomial strides
   const u32* limb_mod;
   const u64* scale;  // inverse cols pass: per-limb Shoup pairs (null: N^-1)
+  const u32* perm;   // item order of the limbs (null: in order)
   u32 nl, np;
 };
 
@@ -338,7 +340,7 @@ __device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& p
     v.limb_mod = ldc(&P->y_mod); v.scale = ldc(&P->y_scale);
   } else if constexpr (ST == ST_DT_NCOLS || ST == ST_DT_NBLOCKS) {
     v.src = pd.dt; v.dst = pd.dt; v.nl = ldc(&P->dt_limbs); v.np = 1;
-    v.limb_mod = ldc(&P->dt_mod); v.scale = nullptr;
+    v.limb_mod = ldc(&P->dt_mod); v.scale = nullptr; v.perm = ldc(&P->dt_perm);
   } else if constexpr (ST == ST_KS_IBLOCKS || ST == ST_KS_ICOLS) {
     const u64 ne = pd.level + c.K;
     v.src = pd.ks + ((u64)pd.level << c.log_n); v.dst = pd.ks + ((u64)pd.level << c.log_n);
@@ -362,7 +364,8 @@ __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& 
   const int n2 = c.log_n - LOGS;
   const u32 tpc = (1u << n2) / PL::SUBS;
   const u32 pos = uniform(local % tpc), rest = local / tpc;
-  const u32 z = uniform(rest % v.np), limb = uniform(rest / v.np);  // both polys of a limb adjacent
+  const u32 z = uniform(rest % v.np), slot = uniform(rest / v.np);  // both polys of a limb adjacent
+  const u32 limb = v.perm ? ldc(v.perm + slot) : slot;
   const u32 mi = ldc(v.limb_mod + limb);
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
@@ -422,7 +425,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
   const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
   const u32 pos = uniform(local % tpl), rest = local / tpl;
-  const u32 z = uniform(rest % v.np), limb = uniform(rest / v.np);  // both polys of a limb adjacent
+  const u32 z = uniform(rest % v.np), slot = uniform(rest / v.np);  // both polys of a limb adjacent
+  const u32 limb = v.perm ? ldc(v.perm + slot) : slot;
   const u32 mi = ldc(v.limb_mod + limb);
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();

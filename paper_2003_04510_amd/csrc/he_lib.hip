@@ -77,7 +77,7 @@ struct LevelPlan {
   const ConvJobDev* mu_jobs = nullptr;  // [beta]
   const ConvJobDev* md_jobs = nullptr;  // [1]
   u32 lo[8] = {}, cnt[8] = {}, dt_first[8] = {};
-  size_t o_modup_scale = 0, o_dt_mod = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
+  size_t o_modup_scale = 0, o_dt_mod = 0, o_dt_perm = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
   // resolved device pointers
   const u64* modup_scale = nullptr;
   const u32* dt_mod = nullptr;
@@ -441,6 +441,11 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
       dt_first += (u32)tg.size();
     }
     P.dt_limbs = dt_first;
+    // NTT passes visit the mod-up limbs grouped by modulus, so limbs that
+    // share a twiddle table run next to each other (same XCD, L2 hits)
+    std::vector<u32> dt_perm(dt_mod.size());
+    for (u32 k = 0; k < dt_perm.size(); ++k) dt_perm[k] = k;
+    std::stable_sort(dt_perm.begin(), dt_perm.end(), [&](u32 a, u32 b) { return dt_mod[a] < dt_mod[b]; });
     // ModDown job: sources = K special limbs (after scaling), targets q_0..q_{lvl-1}
     ConvJob md{};
     md.src_off = lvl; md.ns = K; md.dst_off = 0; md.nt = lvl; md.c_off = 0; md.m_off = 0;
@@ -494,7 +499,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
       P.o_mu_tg = B.add(mtg); P.o_mu_c = B.add(mc); P.o_md_tg = B.add(dtg); P.o_md_c = B.add(dc);
       P.o_y_mod = B.add(ymod); P.o_y_scale = B.add(ysc); P.o_s_mod = B.add(smod); P.o_s_scale = B.add(ssc);
     }
-    P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_emod = B.add(emod);
+    P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_dt_perm = B.add(dt_perm); P.o_emod = B.add(emod);
     P.o_qlinv = B.add(qlinv); P.o_qlmod = B.add(qlmod);
     {
       PlanDev placeholder{};
@@ -514,7 +519,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     pd.mu_c = (const u32*)(d + P.o_mu_c);
     pd.md_jobs = (const ConvJobDev*)(d + P.o_md_jobs); pd.md_tg = (const ConvTarget*)(d + P.o_md_tg);
     pd.md_c = (const u32*)(d + P.o_md_c);
-    pd.dt_mod = (const u32*)(d + P.o_dt_mod); pd.emod = (const u32*)(d + P.o_emod);
+    pd.dt_mod = (const u32*)(d + P.o_dt_mod); pd.dt_perm = (const u32*)(d + P.o_dt_perm); pd.emod = (const u32*)(d + P.o_emod);
     pd.y_mod = (const u32*)(d + P.o_y_mod); pd.y_scale = (const u64*)(d + P.o_y_scale);
     pd.s_mod = (const u32*)(d + P.o_s_mod); pd.s_scale = (const u64*)(d + P.o_s_scale);
     pd.qlinv = (const u64*)(d + P.o_qlinv); pd.qlmod = (const u64*)(d + P.o_qlmod);
