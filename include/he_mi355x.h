@@ -66,8 +66,10 @@ he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uin
  * in bit-reversed order, with Shoup companions, Algorithms 2-3) and all
  * base-conversion constants on device `device`.  The context owns those
  * tables (freed by he_ctx_destroy).  Constraints: 12 <= log_n <= 17,
- * 1 <= dnum <= L <= 64, 1 <= K <= 32, K special primes whose product exceeds
- * every digit's product.  */
+ * 1 <= dnum <= min(L, 4) (HE_EUNSUPPORTED above 4: the key-switch inner
+ * product runs one digit per wavefront of a 4-wave workgroup), L <= 64,
+ * 1 <= K <= 32, K special primes whose product exceeds every digit's
+ * product.  */
 he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
                         const uint64_t* p, int device, he_ctx** out);
 void he_ctx_destroy(he_ctx* ctx);
@@ -162,7 +164,9 @@ void he_batch_destroy(he_batch* batch);
  * level; their stage sequences alternate between the batch's stream and a
  * side stream the batch owns, so stages of different groups overlap; a
  * captured graph keeps that structure.  Results are identical under every
- * schedule.
+ * schedule.  ip_fused (0 or 1): run the mod-up NTT blocks pass, the evk inner
+ * product and the special limbs' INTT blocks pass as one fused pass (less
+ * HBM traffic, longer dependency chains per workgroup) instead of three.
  *
  * he_batch_set_sched: validates (HE_EUNSUPPORTED for tiles not available at
  * this ring degree, HE_EINVAL for a bad chunk count), re-uploads the item
@@ -170,14 +174,15 @@ void he_batch_destroy(he_batch* batch);
  * he_batch_get_sched: the current schedule.
  * he_batch_autotune: runs the batch (overwriting its outputs with the same
  * values) as a graph `reps` times under each candidate schedule -- every
- * available tile pair with one chunk, then the best tiles with 2 and 4
- * chunks -- times each with HIP events on `stream`, and installs the
+ * available tile pair with one chunk, then the best tiles with the fused
+ * inner product, then the best of those with 2 and 4 chunks -- times each with HIP events on `stream`, and installs the
  * fastest; *best and *best_ms (may be NULL) receive it and its time per
  * replay.  Synchronizes `stream`. */
 typedef struct he_batch_sched {
   uint32_t cols_tile;
   uint32_t blocks_tile;
   uint32_t chunks;
+  uint32_t ip_fused;
 } he_batch_sched;
 he_status he_batch_set_sched(he_batch* batch, const he_batch_sched* sched, he_stream stream);
 he_status he_batch_get_sched(const he_batch* batch, he_batch_sched* sched);

@@ -31,7 +31,8 @@ class BatchItem(ctypes.Structure):
 
 
 class BatchSched(ctypes.Structure):
-    _fields_ = [("cols_tile", ctypes.c_uint32), ("blocks_tile", ctypes.c_uint32), ("chunks", ctypes.c_uint32)]
+    _fields_ = [("cols_tile", ctypes.c_uint32), ("blocks_tile", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
+                ("ip_fused", ctypes.c_uint32)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -323,15 +324,15 @@ class Batch:
         _check(load_library().he_mul_batch(self.ctx._h, self._h, vp(evk.data_ptr()), int(use_graph),
                                            self.ctx._stream()), "he_mul_batch")
 
-    def set_sched(self, cols_tile: int, blocks_tile: int, chunks: int):
-        sc = BatchSched(cols_tile, blocks_tile, chunks)
+    def set_sched(self, cols_tile: int, blocks_tile: int, chunks: int, ip_fused: int = 0):
+        sc = BatchSched(cols_tile, blocks_tile, chunks, ip_fused)
         _check(load_library().he_batch_set_sched(self._h, ctypes.byref(sc), self.ctx._stream()),
                "he_batch_set_sched")
 
     def sched(self):
         sc = BatchSched()
         _check(load_library().he_batch_get_sched(self._h, ctypes.byref(sc)), "he_batch_get_sched")
-        return {"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks}
+        return {"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks, "ip_fused": sc.ip_fused}
 
     def autotune(self, evk, reps: int = 3):
         """Time every candidate schedule (graph replays) and keep the
@@ -339,7 +340,8 @@ class Batch:
         sc, ms = BatchSched(), ctypes.c_double()
         _check(load_library().he_batch_autotune(self.ctx._h, self._h, vp(evk.data_ptr()), reps, self.ctx._stream(),
                                                 ctypes.byref(sc), ctypes.byref(ms)), "he_batch_autotune")
-        return {"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks}, ms.value
+        return ({"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks,
+                 "ip_fused": sc.ip_fused}, ms.value)
 
     def close(self):
         if getattr(self, "_h", None):

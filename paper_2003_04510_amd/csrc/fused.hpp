@@ -9,6 +9,9 @@
 //   k_list_blocks      NTT / INTT "blocks" pass over a limb list of a pair
 //   k_conv             fast base conversion (mod up / mod down)
 //   k_ip               evk inner product (Fig. 2 region 2)
+//   k_blocks_ip        NTT "blocks" passes of the mod-up limbs + evk inner
+//                      product + INTT "blocks" pass of the special limbs
+//                      (the fused alternative of the three above)
 //   k_lift_ntt_cols    rescale lift of the dropped limb + NTT "cols" pass
 //   k_zcols_lift       the NTT "cols" pass of z and the lift in one launch
 //   k_ntt_combine      NTT "blocks" passes of z and s + mod-down combine
@@ -35,8 +38,11 @@ constexpr u64 M30 = (1ull << 30) - 1;
 // "cols" passes 4096 elements (16 adjacent columns at N = 2^16), "blocks"
 // passes 2048; batches at N = 2^16 may select other tiles (TileCfg).
 constexpr int EPW_C = 4096, EPW_B = 2048;
+// fused_ip selects k_blocks_ip (mod-up NTT blocks + inner product +
+// special INTT blocks in one pass, less HBM traffic) over the three
+// separate launches (shorter dependency chains per workgroup).
 struct TileCfg {
-  u32 epw_c = EPW_C, epw_b = EPW_B;
+  u32 epw_c = EPW_C, epw_b = EPW_B, fused_ip = 0;
 };
 constexpr int CONV_CPT = 2, CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
 constexpr int IP_CPT = 2, IP_THREADS = 256;                        // inner product
@@ -68,7 +74,6 @@ struct PlanDev {
   const ConvTarget* md_tg;    // [level]
   const u32* md_c;
   const u32* dt_mod;   // modulus of each mod-up limb [dt_limbs]
-  const u32* dt_perm;  // mod-up limbs ordered by modulus (limbs sharing a twiddle table adjacent)
   const u32* emod;     // modulus of extended-basis limb e [level + K]
   const u32* y_mod;    // INTT list d2 (+ d0, d1 of limb level-1) [level + 2]
   const u64* y_scale;  // Shoup pairs: N^-1 [(Qt_j/q_i)^-1]_{q_i}, N^-1
@@ -143,9 +148,10 @@ enum Stage : int {
   ST_Y_ICOLS,      // INTT cols of y
   ST_MU_CONV,      // mod-up conversion
   ST_DT_NCOLS,     // NTT cols of the mod-up limbs
-  ST_DT_NBLOCKS,   // NTT blocks of the mod-up limbs
-  ST_IP,           // inner product with evk
-  ST_KS_IBLOCKS,   // INTT blocks of the special limbs (+ limb level-1)
+  ST_DT_NBLOCKS,   // NTT blocks of the mod-up limbs                      (separate path)
+  ST_IP,           // inner product with evk                              (separate path)
+  ST_KS_IBLOCKS,   // INTT blocks of the special limbs (+ limb level-1)   (separate path)
+  ST_BLOCKS_IP,    // the three above in one pass                         (fused path)
   ST_KS_ICOLS,     // INTT cols of the special limbs (+ limb level-1)
   ST_MD_CONV,      // mod-down conversion
   ST_Z_NCOLS,      // NTT cols of z, and the rescale lift + NTT cols of s (over d2 / y)
@@ -164,21 +170,31 @@ __host__ __device__ constexpr u32 blocks_tiles(u32 log_n, u32 epw = EPW_B) {
   return (1u << (log_n / 2)) / (epw >> (log_n - log_n / 2));
 }
 
+// The fused mod-up blocks + inner-product pass (k_blocks_ip) runs one digit
+// per wavefront of an IP_WAVES-wave workgroup (so dnum <= IP_WAVES) on tiles
+// of 64 / T sub-transforms per wave (T threads per sub-transform).
+constexpr int IP_WAVES = 4;
+__host__ __device__ constexpr u32 ipw_elems(u32 log_n) {
+  return 64u * (1u << ((log_n - log_n / 2) >= 9 ? 5 : ((log_n - log_n / 2) <= 6 ? 3 : 4)));
+}
+__host__ __device__ constexpr u32 ipw_tiles(u32 log_n) { return (1u << log_n) / ipw_elems(log_n); }
+
 // Work items of one pair in a stage.
 inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_limbs, bool rs,
                        TileCfg tc_cfg = TileCfg{}) {
   const u32 tc = cols_tiles(log_n, tc_cfg.epw_c), tb = blocks_tiles(log_n, tc_cfg.epw_b);
-  const u32 chunks_c = (1u << log_n) / (CONV_THREADS * CONV_CPT);
   const u32 chunks_i = (1u << log_n) / (IP_THREADS * IP_CPT);
+  const u32 chunks_c = (1u << log_n) / (CONV_THREADS * CONV_CPT);
   const u32 ex = rs ? 1 : 0;
   switch (st) {
     case ST_TENSOR: return (level + 2 * ex) * tb;
     case ST_Y_ICOLS: return (level + 2 * ex) * tc;
     case ST_MU_CONV: return beta * CONV_GROUPS * chunks_c;
     case ST_DT_NCOLS: return dt_limbs * tc;
-    case ST_DT_NBLOCKS: return dt_limbs * tb;
-    case ST_IP: return (level + K) * chunks_i;
-    case ST_KS_IBLOCKS: return 2 * (K + ex) * tb;
+    case ST_DT_NBLOCKS: return tc_cfg.fused_ip ? 0 : dt_limbs * tb;
+    case ST_IP: return tc_cfg.fused_ip ? 0 : (level + K) * chunks_i;
+    case ST_KS_IBLOCKS: return tc_cfg.fused_ip ? 0 : 2 * (K + ex) * tb;
+    case ST_BLOCKS_IP: return tc_cfg.fused_ip ? (level + K + ex) * ipw_tiles(log_n) : 0;
     case ST_KS_ICOLS: return 2 * (K + ex) * tc;
     case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_c;
     case ST_Z_NCOLS: return 2 * level * tc + (rs ? 2 * (level - 1) * tc : 0);
@@ -325,7 +341,6 @@ struct ListView {
   u64 zs, zd;  // polynomial strides
   const u32* limb_mod;
   const u64* scale;  // inverse cols pass: per-limb Shoup pairs (null: N^-1)
-  const u32* perm;   // item order of the limbs (null: in order)
   u32 nl, np;
 };
 
@@ -340,7 +355,7 @@ __device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& p
     v.limb_mod = ldc(&P->y_mod); v.scale = ldc(&P->y_scale);
   } else if constexpr (ST == ST_DT_NCOLS || ST == ST_DT_NBLOCKS) {
     v.src = pd.dt; v.dst = pd.dt; v.nl = ldc(&P->dt_limbs); v.np = 1;
-    v.limb_mod = ldc(&P->dt_mod); v.scale = nullptr; v.perm = ldc(&P->dt_perm);
+    v.limb_mod = ldc(&P->dt_mod); v.scale = nullptr;
   } else if constexpr (ST == ST_KS_IBLOCKS || ST == ST_KS_ICOLS) {
     const u64 ne = pd.level + c.K;
     v.src = pd.ks + ((u64)pd.level << c.log_n); v.dst = pd.ks + ((u64)pd.level << c.log_n);
@@ -364,8 +379,7 @@ __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& 
   const int n2 = c.log_n - LOGS;
   const u32 tpc = (1u << n2) / PL::SUBS;
   const u32 pos = uniform(local % tpc), rest = local / tpc;
-  const u32 z = uniform(rest % v.np), slot = uniform(rest / v.np);  // both polys of a limb adjacent
-  const u32 limb = v.perm ? ldc(v.perm + slot) : slot;
+  const u32 z = uniform(rest % v.np), limb = uniform(rest / v.np);  // both polys of a limb adjacent
   const u32 mi = ldc(v.limb_mod + limb);
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
@@ -425,8 +439,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
   const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
   const u32 pos = uniform(local % tpl), rest = local / tpl;
-  const u32 z = uniform(rest % v.np), slot = uniform(rest / v.np);  // both polys of a limb adjacent
-  const u32 limb = v.perm ? ldc(v.perm + slot) : slot;
+  const u32 z = uniform(rest % v.np), limb = uniform(rest / v.np);  // both polys of a limb adjacent
   const u32 mi = ldc(v.limb_mod + limb);
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
@@ -616,6 +629,155 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
       xb[kz + k] = va;
     }
   }
+}
+
+// ---------------------------------------------------------------- mod-up NTT blocks + inner product
+// One workgroup per (limb e of the extended basis, tile of IPW_BLOCKS
+// blocks); wave j of its IP_WAVES waves owns digit j: it runs the NTT
+// blocks pass of the mod-up limb of digit j with target e on the tile (or
+// takes d2[e] itself, already in NTT form, when e lies in digit j) into its
+// own LDS tile, synchronizing with wave-level LDS ordering only.  After one
+// workgroup barrier every thread sums the inner-product terms
+//   ks_u[e] = sum_j dt_j[e] * evk_j.u[e]   (u = b, a)
+// for its elements, so the NTT-form mod-up limbs never return to HBM and
+// the digits of one target share their twiddles.  q limbs e < level are
+// written in NTT form; special limbs, and when rescaling limb level-1 once
+// more (into slot level+K), go through the inverse NTT blocks pass (waves
+// 0 and 1, one polynomial each), leaving them the inverse cols pass.
+// Items (e, tile), tile fastest; e < level + K (+1).
+
+template <int LOGS>
+__global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) {
+  constexpr int LOGR = Radix<LOGS>::LOGR;
+  using Gm = Geo<LOGS, LOGR>;
+  constexpr int SUBS = 64 / Gm::T;      // sub-transforms per wave
+  constexpr int EW = SUBS * Gm::S;       // elements per tile
+  constexpr int TILE = SUBS * Gm::SUB;   // LDS words per wave tile
+  constexpr int THREADS = 64 * IP_WAVES;
+  constexpr int PER = EW / THREADS;      // elements per thread in the sum
+  using RF = RoundShape<LOGS, LOGR, 0>;
+  constexpr int IFIRST = Gm::NR - 1;
+  static_assert(EW % THREADS == 0, "tile");
+  __shared__ u64 lds[IP_WAVES * TILE];
+  const u32 w = xcd_item(blockIdx.x, gridDim.x);
+  if (w >= b.nitems) return;
+  u32 local;
+  const PairDesc pd = resolve(b, uniform(w), local);
+  const PlanDev* P = pd.plan;
+  const int n1 = c.log_n - LOGS;
+  const u32 tpl = (1u << n1) / SUBS;
+  const u32 pos = uniform(local % tpl), el = uniform(local / tpl);
+  const bool copy = el == pd.level + c.K;  // ks_u[level-1] again, inverse-transformed into slot level+K
+  const u32 e = copy ? pd.level - 1 : el;
+  const bool coef = copy || e >= pd.level;  // leaves after the inverse blocks pass
+  const u32 mi = ldc(ldc(&P->emod) + e);
+  const ModInfo m = ldc(c.mods + mi);
+  const u64 nm = c.L + c.K;
+  const u32 beta = ldc(&P->beta);
+  const u64 blk0 = (u64)pos * SUBS, toff = blk0 << LOGS;
+  const u32 wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int sub = lane / Gm::T, tt = lane % Gm::T;
+  const u64 base = (1ull << n1) + blk0 + sub;
+  const auto lpos = [](int idx) { return (idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1)); };
+  const u64 kz = (u64)(pd.level + c.K + 1) << c.log_n;
+  with_arith(m.q, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(m.q, m.qinv);
+    typename A::V* const tiles = reinterpret_cast<typename A::V*>(lds);
+    typename A::V* const mine = tiles + wave * TILE;
+    // phase 1: wave j puts digit j's term of target e, NTT form, into its tile
+    if (wave < beta) {
+      const u32 j = wave;
+      const u32 lo = ldc(&P->lo[j]), cnt = ldc(&P->cnt[j]);
+      if (e < pd.level && e >= lo && e < lo + cnt) {
+        const auto x = gbl(pd.d2 + ((u64)e << c.log_n) + toff);
+#pragma unroll
+        for (int k = 0; k < EW / 64; ++k) {
+          const int idx = lane + k * 64;
+          mine[lpos(idx)] = A::in(x[idx], M);
+        }
+      } else {
+        const u32 o = e < lo ? e : e - cnt;
+        const auto src = gbl(pd.dt + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n) + toff + ((u64)sub << LOGS));
+        typename A::V x[Gm::R];
+#pragma unroll
+        for (int k = 0; k < Gm::R; ++k) x[k] = A::in(src[RF::elem(tt, k / RF::G, k % RF::G)], M);
+        sub_transform_regs<A, true, LOGS, LOGR, true, true>(x, mine + sub * Gm::SUB, tt,
+                                                            c.tw + ((u64)mi << c.log_n), base, M,
+                                                            [](int, typename A::V) {});
+      }
+    }
+    // phase 2 operands: the evk values of this thread's elements for every
+    // digit, issued before the barrier so they arrive while waves wait
+    // (digits past beta clamp to the last one; their terms are skipped)
+    u64 vb[IP_WAVES][PER], va[IP_WAVES][PER];
+#pragma unroll
+    for (int j = 0; j < IP_WAVES; ++j) {
+      const u32 jc = min((u32)j, beta - 1);
+      const auto eb = gbl(c.evk + ((((u64)jc * 2) * nm + mi) << c.log_n) + toff);
+      const auto ea = eb + (nm << c.log_n);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = threadIdx.x + k * THREADS;
+        vb[j][k] = eb[idx];
+        va[j][k] = ea[idx];
+      }
+    }
+    lds_barrier();
+    // phase 2: the sums, PER elements per thread
+    u64 sb[PER], sa[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sb[k] = sa[k] = 0;
+#pragma unroll
+    for (int j = 0; j < IP_WAVES; ++j) {
+      if ((u32)j >= beta) break;
+      const typename A::V* const tj = tiles + j * TILE;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = threadIdx.x + k * THREADS;
+        const u64 xv = A::template out<true>(tj[lpos(idx)], M);
+        u64 pb, pa;
+        if constexpr (std::is_same<A, F64A>::value) {
+          const double X = F64A::in(xv, M);
+          pb = F64A::to_u64(F64A::mulv(X, F64A::in(vb[j][k], M), M), M);
+          pa = F64A::to_u64(F64A::mulv(X, F64A::in(va[j][k], M), M), M);
+        } else {
+          pb = barrett(mul_wide(xv, vb[j][k]), m);
+          pa = barrett(mul_wide(xv, va[j][k]), m);
+        }
+        sb[k] = addmod(sb[k], pb, m.q);
+        sa[k] = addmod(sa[k], pa, m.q);
+      }
+    }
+    if (!coef) {
+      const auto ob = gbl(pd.ks + ((u64)e << c.log_n) + toff);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = threadIdx.x + k * THREADS;
+        ob[idx] = sb[k];
+        ob[kz + idx] = sa[k];
+      }
+      return;
+    }
+    // phase 3: inverse blocks pass of the sums; tile 0 <- b, tile 1 <- a
+    lds_barrier();  // every tile read above
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int q = lpos(threadIdx.x + k * THREADS);
+      tiles[q] = A::in(sb[k], M);
+      tiles[TILE + q] = A::in(sa[k], M);
+    }
+    lds_barrier();
+    if (wave < 2) {
+      typename A::V x[Gm::R];
+      lds_get<LOGS, LOGR, IFIRST>(mine + sub * Gm::SUB, x, tt);
+      const u64 slot = copy ? pd.level + c.K : e;
+      const auto out = gbl(pd.ks + (wave ? kz : 0) + (slot << c.log_n) + toff + ((u64)sub << LOGS));
+      sub_transform_regs<A, false, LOGS, LOGR, false, true>(
+          x, mine + sub * Gm::SUB, tt, c.itw + ((u64)mi << c.log_n), base, M,
+          [&](int e2, typename A::V v) { out[e2] = A::template out<false>(v, M); });
+    }
+  });
 }
 
 // ---------------------------------------------------------------- NTT blocks + combine + rescale

@@ -77,7 +77,7 @@ struct LevelPlan {
   const ConvJobDev* mu_jobs = nullptr;  // [beta]
   const ConvJobDev* md_jobs = nullptr;  // [1]
   u32 lo[8] = {}, cnt[8] = {}, dt_first[8] = {};
-  size_t o_modup_scale = 0, o_dt_mod = 0, o_dt_perm = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
+  size_t o_modup_scale = 0, o_dt_mod = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
   // resolved device pointers
   const u64* modup_scale = nullptr;
   const u32* dt_mod = nullptr;
@@ -329,6 +329,8 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   if (log_n < 12 || log_n > 17) return fail(HE_EUNSUPPORTED, "log_n must be in [12, 17]");
   if (L < 1 || L > 64 || K < 1 || K > 32 || dnum < 1 || dnum > L || dnum > 8)
     return fail(HE_EINVAL, "need 1 <= dnum <= min(L, 8), L <= 64, 1 <= K <= 32");
+  if (dnum > (u32)IP_WAVES)
+    return fail(HE_EUNSUPPORTED, "dnum %u: the inner product handles at most %d digits", dnum, IP_WAVES);
   const u64 N = 1ull << log_n;
   std::unique_ptr<he_ctx, void (*)(he_ctx*)> c(new he_ctx, he_ctx_destroy);  // frees device memory on errors
   c->log_n = log_n; c->L = L; c->K = K; c->dnum = dnum; c->N = N;
@@ -441,11 +443,6 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
       dt_first += (u32)tg.size();
     }
     P.dt_limbs = dt_first;
-    // NTT passes visit the mod-up limbs grouped by modulus, so limbs that
-    // share a twiddle table run next to each other (same XCD, L2 hits)
-    std::vector<u32> dt_perm(dt_mod.size());
-    for (u32 k = 0; k < dt_perm.size(); ++k) dt_perm[k] = k;
-    std::stable_sort(dt_perm.begin(), dt_perm.end(), [&](u32 a, u32 b) { return dt_mod[a] < dt_mod[b]; });
     // ModDown job: sources = K special limbs (after scaling), targets q_0..q_{lvl-1}
     ConvJob md{};
     md.src_off = lvl; md.ns = K; md.dst_off = 0; md.nt = lvl; md.c_off = 0; md.m_off = 0;
@@ -499,7 +496,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
       P.o_mu_tg = B.add(mtg); P.o_mu_c = B.add(mc); P.o_md_tg = B.add(dtg); P.o_md_c = B.add(dc);
       P.o_y_mod = B.add(ymod); P.o_y_scale = B.add(ysc); P.o_s_mod = B.add(smod); P.o_s_scale = B.add(ssc);
     }
-    P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_dt_perm = B.add(dt_perm); P.o_emod = B.add(emod);
+    P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_emod = B.add(emod);
     P.o_qlinv = B.add(qlinv); P.o_qlmod = B.add(qlmod);
     {
       PlanDev placeholder{};
@@ -519,7 +516,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     pd.mu_c = (const u32*)(d + P.o_mu_c);
     pd.md_jobs = (const ConvJobDev*)(d + P.o_md_jobs); pd.md_tg = (const ConvTarget*)(d + P.o_md_tg);
     pd.md_c = (const u32*)(d + P.o_md_c);
-    pd.dt_mod = (const u32*)(d + P.o_dt_mod); pd.dt_perm = (const u32*)(d + P.o_dt_perm); pd.emod = (const u32*)(d + P.o_emod);
+    pd.dt_mod = (const u32*)(d + P.o_dt_mod); pd.emod = (const u32*)(d + P.o_emod);
     pd.y_mod = (const u32*)(d + P.o_y_mod); pd.y_scale = (const u64*)(d + P.o_y_scale);
     pd.s_mod = (const u32*)(d + P.o_s_mod); pd.s_scale = (const u64*)(d + P.o_s_scale);
     pd.qlinv = (const u64*)(d + P.o_qlinv); pd.qlmod = (const u64*)(d + P.o_qlmod);
@@ -634,6 +631,7 @@ void launch_lcols(const Common& c, const Batch& b, hipStream_t st) {
   hipLaunchKernelGGL((k_list_cols<FWD, LOGS, EPW, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, c,
                      b);
 }
+
 template <bool FWD, int LOGS, int EPW, int ST>
 void launch_lblocks(const Common& c, const Batch& b, hipStream_t st) {
   hipLaunchKernelGGL((k_list_blocks<FWD, LOGS, EPW, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st,
@@ -663,6 +661,7 @@ void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) 
     case ST_DT_NBLOCKS: launch_lblocks<true, N2, EB, ST_DT_NBLOCKS>(c, b, st); break;
     case ST_IP: hipLaunchKernelGGL(k_ip, g, dim3(IP_THREADS), 0, st, c, b); break;
     case ST_KS_IBLOCKS: launch_lblocks<false, N2, EB, ST_KS_IBLOCKS>(c, b, st); break;
+    case ST_BLOCKS_IP: hipLaunchKernelGGL((k_blocks_ip<N2>), g, dim3(64 * IP_WAVES), 0, st, c, b); break;
     case ST_KS_ICOLS: launch_lcols<false, N1, EC, ST_KS_ICOLS>(c, b, st); break;
     case ST_MD_CONV: launch_conv<true>(conv_bucket(c.K), c, b, st); break;
     case ST_Z_NCOLS: hipLaunchKernelGGL((k_zcols_lift<N1, EC>), g, dim3(pass_threads(N1, EC)), 0, st, c, b); break;
@@ -675,6 +674,7 @@ void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) 
 // Tile choices a batch may select: the defaults at every ring degree, and
 // at N = 2^16 also 2048-element cols tiles and 1024-element blocks tiles.
 bool tiles_supported(u32 log_n, TileCfg t) {
+  if (t.fused_ip > 1) return false;
   if (t.epw_c == EPW_C && t.epw_b == EPW_B) return true;
   return log_n == 16 && (t.epw_c == 2048 || t.epw_c == 4096) && (t.epw_b == 1024 || t.epw_b == 2048);
 }
@@ -691,8 +691,9 @@ TileCfg default_tiles(u32 log_n) {
 const char* stage_name(int s) {
   static const char* names[ST_COUNT + 2] = {"tensor_intt", "y_intt_cols", "modup_convert", "modup_ntt_cols",
                                             "modup_ntt_blocks", "inner_product", "special_intt_blocks",
-                                            "special_intt_cols", "moddown_convert", "moddown_lift_ntt_cols",
-                                            "ntt_combine_rescale", "lift_ntt_cols", "ntt_rescale"};
+                                            "modup_blocks_inner_product", "special_intt_cols", "moddown_convert",
+                                            "moddown_lift_ntt_cols", "ntt_combine_rescale", "lift_ntt_cols",
+                                            "ntt_rescale"};
   return names[s];
 }
 
@@ -715,6 +716,10 @@ void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double
     case ST_DT_NBLOCKS: ops = P.dt_limbs * hN * n2; bytes = 2.0 * P.dt_limbs * N * 8; break;
     case ST_IP: ops = 2.0 * P.beta * ne * N; bytes = (3.0 * P.beta + 2) * ne * N * 8 + 2 * ex * N * 8; break;
     case ST_KS_IBLOCKS: ops = 2 * (K + ex) * hN * n2; bytes = 4 * (K + ex) * N * 8; break;
+    case ST_BLOCKS_IP:  // mod-up limbs (cols-pass form) and d2 in, evk in, ks out
+      ops = P.dt_limbs * hN * n2 + 2.0 * P.beta * ne * N + 2 * (K + ex) * hN * n2;
+      bytes = (P.dt_limbs + l + 2.0 * P.beta * ne + 2 * (ne + ex)) * N * 8;
+      break;
     case ST_KS_ICOLS: ops = 2 * (K + ex) * (hN * n1 + N); bytes = 4 * (K + ex) * N * 8; break;
     case ST_MD_CONV: ops = 2 * K * l * N; bytes = 2 * (K + l) * N * 8; break;
     case ST_Z_NCOLS:  // z cols, plus the lift's cols pass when rescaling
@@ -1032,6 +1037,7 @@ he_status he_batch_set_sched(he_batch* bt, const he_batch_sched* sc, he_stream s
   TileCfg t;
   t.epw_c = sc->cols_tile;
   t.epw_b = sc->blocks_tile;
+  t.fused_ip = sc->ip_fused;
   if (!tiles_supported(c->log_n, t))
     return fail(HE_EUNSUPPORTED, "he_batch_set_sched: tiles %u/%u not available at N = 2^%u", t.epw_c, t.epw_b,
                 c->log_n);
@@ -1063,6 +1069,7 @@ he_status he_batch_get_sched(const he_batch* bt, he_batch_sched* sc) {
   sc->cols_tile = bt->tiles.epw_c;
   sc->blocks_tile = bt->tiles.epw_b;
   sc->chunks = bt->chunks;
+  sc->ip_fused = bt->tiles.fused_ip;
   return HE_OK;
 }
 
@@ -1169,11 +1176,11 @@ he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32
   };
   std::vector<he_batch_sched> tiles;
   const TileCfg d = default_tiles(c->log_n);
-  tiles.push_back({d.epw_c, d.epw_b, 1});
+  tiles.push_back({d.epw_c, d.epw_b, 1, 0});
   if (c->log_n == 16)
     for (uint32_t ec : {4096u, 2048u})
       for (uint32_t eb : {2048u, 1024u})
-        if (!(ec == d.epw_c && eb == d.epw_b)) tiles.push_back({ec, eb, 1});
+        if (!(ec == d.epw_c && eb == d.epw_b)) tiles.push_back({ec, eb, 1, 0});
   he_batch_sched b = tiles[0];
   double bms = 1e30;
   he_status r = HE_OK;
@@ -1181,6 +1188,12 @@ he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32
     double ms = 0;
     if ((r = run(sc, ms)) != HE_OK) break;
     if (ms < bms) { bms = ms; b = sc; }
+  }
+  if (r == HE_OK) {  // the fused mod-up blocks + inner product pass
+    he_batch_sched sc = b;
+    sc.ip_fused = 1;
+    double ms = 0;
+    if ((r = run(sc, ms)) == HE_OK && ms < bms) { bms = ms; b = sc; }
   }
   for (uint32_t ch : {2u, 4u}) {
     if (r != HE_OK || ch > bt->n) break;

@@ -186,6 +186,19 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
+// Ordering of LDS accesses among the lanes of one wavefront (a transform
+// whose threads all sit in one wave): the LDS unit executes one wave's
+// accesses in issue order, so only the compiler must not reorder them.
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) lds_wave_sync();
+  else lds_barrier();
+}
 
 template <int LOGS, int LOGR>
 struct Geo {
@@ -268,8 +281,9 @@ __device__ __forceinline__ void lds_get(const V* tile, V (&x)[1 << LOGR], int tt
     for (int i = 0; i < RS::G; ++i) x[u * RS::G + i] = tile[Geo<LOGS, LOGR>::pad(RS::elem(tt, u, i))];
 }
 
-// Middle rounds 1 .. NR-2 (forward order) through LDS.
-template <class A, bool FWD, int LOGS, int LOGR, int K>
+// Middle rounds 1 .. NR-2 (forward order) through LDS.  WAVE: the
+// transform's threads are one wavefront (wave-level LDS ordering suffices).
+template <class A, bool FWD, int LOGS, int LOGR, int K, bool WAVE = false>
 __device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
                                            const Tw2* __restrict__ tw, u64 base, const typename A::Mod& M) {
   constexpr int NR = Geo<LOGS, LOGR>::NR;
@@ -277,12 +291,12 @@ __device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typena
     constexpr int RD = FWD ? K : NR - 1 - K;
     constexpr int PREV = FWD ? RD - 1 : RD + 1;
     lds_put<LOGS, LOGR, PREV>(tile, x, tt);
-    lds_barrier();
+    lds_sync<WAVE>();
     lds_get<LOGS, LOGR, RD>(tile, x, tt);
     round_math<A, FWD, LOGS, LOGR, RD>(x, tt, tw, base, M);
     // no barrier needed before the next lds_put: within one round every LDS
     // position belongs to exactly one thread
-    mid_rounds<A, FWD, LOGS, LOGR, K + 1>(x, tile, tt, tw, base, M);
+    mid_rounds<A, FWD, LOGS, LOGR, K + 1, WAVE>(x, tile, tt, tw, base, M);
   }
 }
 
@@ -293,7 +307,7 @@ __device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typena
 // sub-transform's LDS area (Geo::SUB words).  A caller that runs several
 // sub-transforms on the same tile back to back must place a barrier between
 // them.
-template <class A, bool FWD, int LOGS, int LOGR, bool OUT_LDS, class Store>
+template <class A, bool FWD, int LOGS, int LOGR, bool OUT_LDS, bool WAVE = false, class Store>
 __device__ __forceinline__ void sub_transform_regs(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
                                                    const Tw2* __restrict__ tw, u64 base, const typename A::Mod& M,
                                                    Store&& store) {
@@ -303,10 +317,10 @@ __device__ __forceinline__ void sub_transform_regs(typename A::V (&x)[1 << LOGR]
   constexpr int LAST = FWD ? NR - 1 : 0;
   round_math<A, FWD, LOGS, LOGR, FIRST>(x, tt, tw, base, M);
   if constexpr (NR > 1) {
-    mid_rounds<A, FWD, LOGS, LOGR, 1>(x, tile, tt, tw, base, M);
+    mid_rounds<A, FWD, LOGS, LOGR, 1, WAVE>(x, tile, tt, tw, base, M);
     constexpr int PREV = FWD ? LAST - 1 : LAST + 1;
     lds_put<LOGS, LOGR, PREV>(tile, x, tt);
-    lds_barrier();
+    lds_sync<WAVE>();
     lds_get<LOGS, LOGR, LAST>(tile, x, tt);
     round_math<A, FWD, LOGS, LOGR, LAST>(x, tt, tw, base, M);
   }

@@ -98,8 +98,8 @@ def _batch_n16(levels, seed):
     return lib, evk, dev, items
 
 
-@pytest.mark.parametrize("sched", [(4096, 2048, 1), (2048, 2048, 2), (4096, 1024, 4), (2048, 1024, 3),
-                                   (4096, 2048, 8)])
+@pytest.mark.parametrize("sched", [(4096, 2048, 1, 0), (2048, 2048, 2, 0), (4096, 1024, 4, 1), (2048, 1024, 3, 1),
+                                   (4096, 2048, 8, 0), (4096, 1024, 1, 1)])
 def test_batch_schedules_bit_exact(sched):
     """Every tile choice and chunk split gives the plain he_mul results,
     eagerly and on repeated graph replays."""
@@ -108,7 +108,7 @@ def test_batch_schedules_bit_exact(sched):
     log("batch sched", sched, levels)
     bt = lib.batch(items)
     bt.set_sched(*sched)
-    assert bt.sched() == {"cols_tile": sched[0], "blocks_tile": sched[1], "chunks": sched[2]}
+    assert bt.sched() == {"cols_tile": sched[0], "blocks_tile": sched[1], "chunks": sched[2], "ip_fused": sched[3]}
     for k, use_graph in enumerate((False, True, True, True)):
         _run_check(lib, bt, items, dev, evk, use_graph, (sched, k))
     bt.close()
@@ -123,6 +123,7 @@ def test_batch_autotune_keeps_results():
     assert ms > 0
     assert sc == bt.sched()
     assert sc["cols_tile"] in (2048, 4096) and sc["blocks_tile"] in (1024, 2048) and sc["chunks"] in (1, 2, 4)
+    assert sc["ip_fused"] in (0, 1)
     for k, use_graph in enumerate((True, False, True)):
         _run_check(lib, bt, items, dev, evk, use_graph, ("tuned", k))
     bt.close()
@@ -133,13 +134,21 @@ def test_batch_sched_errors():
     lib, orc = contexts("n12_L3")
     evk = lib.to_device(random_evk(orc, 8))
     dev = [(lv, lib.to_device(a), lib.to_device(b)) for lv, a, b in _pairs(orc, [3, 2], 700)]
-    bt = lib.batch([(lv, a, b, None, lib.empty(2, lv - 1, orc.N)) for lv, a, b in dev])
+    items = [(lv, a, b, None, lib.empty(2, lv - 1, orc.N)) for lv, a, b in dev]
+    bt = lib.batch(items)
     with pytest.raises(P.HeError, match="EUNSUPPORTED|not available"):
         bt.set_sched(2048, 1024, 1)   # only the default tiles exist at N = 2^12
     with pytest.raises(P.HeError):
         bt.set_sched(4096, 2048, 0)
     with pytest.raises(P.HeError):
         bt.set_sched(4096, 2048, 3)   # more chunks than pairs
-    bt.set_sched(4096, 2048, 2)
-    bt.run(evk, use_graph=True)
+    with pytest.raises(P.HeError):
+        bt.set_sched(4096, 2048, 1, 2)  # ip_fused is 0 or 1
+    bt.set_sched(4096, 2048, 2, 1)   # the fused pass at N = 2^12
+    for _ in range(2):
+        bt.run(evk, use_graph=True)
+    import torch
+    torch.cuda.synchronize()
+    for (lv, a, b), (_, _, _, _, out) in zip(dev, items):
+        assert np.array_equal(lib.to_host(out), lib.to_host(lib.he_mul(lv, a, b, evk, relin=False)[1]))
     bt.close()
