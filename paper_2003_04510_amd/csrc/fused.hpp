@@ -901,11 +901,12 @@ __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u
   const int sub = PL::sub(), tt = PL::tt();
   const u64 N = 1ull << c.log_n;
   const u64 col = (u64)pos * PL::SUBS + sub;
+  // stand-alone rescale: r given, y / ks / zc absent (no pointer formed from them)
   const bool given = pd.r != nullptr;
-  const auto rr = gbl(pd.r + (given ? (u64)u * N + col : 0));
-  const auto dd = gbl(pd.y + ((u64)(pd.level + u) << c.log_n) + col);
-  const auto kk = gbl(pd.ks + ((u64)u * (pd.level + c.K + 1) + pd.level + c.K) * N + col);
-  const auto zz = gbl(pd.zc + ((u64)u * pd.level + pd.level - 1) * N + col);
+  const auto rr = gbl(given ? pd.r + (u64)u * N + col : nullptr);
+  const auto dd = gbl(given ? nullptr : pd.y + ((u64)(pd.level + u) << c.log_n) + col);
+  const auto kk = gbl(given ? nullptr : pd.ks + ((u64)u * (pd.level + c.K + 1) + pd.level + c.K) * N + col);
+  const auto zz = gbl(given ? nullptr : pd.zc + ((u64)u * pd.level + pd.level - 1) * N + col);
   // r = pd.r, or INTT(d) plus the correction; loads are grouped so that no
   // element waits for its own loads alone.
   u64 x[Gm::R];

@@ -152,3 +152,21 @@ def test_batch_sched_errors():
     for (lv, a, b), (_, _, _, _, out) in zip(dev, items):
         assert np.array_equal(lib.to_host(out), lib.to_host(lib.he_mul(lv, a, b, evk, relin=False)[1]))
     bt.close()
+
+
+@pytest.mark.parametrize("wname,levels", [("n17_L45", [45, 17, 3]), ("n15_L12", [12, 5, 9, 2])])
+def test_fused_ip_other_rings(wname, levels):
+    """The fused mod-up blocks + inner-product pass at N = 2^17 (512-point
+    blocks, radix 2^5) and N = 2^15 gives the plain he_mul results."""
+    lib, orc = contexts(wname)
+    evk = lib.to_device(random_evk(orc, 9))
+    dev = [(lv, lib.to_device(a), lib.to_device(b)) for lv, a, b in _pairs(orc, levels, 800)]
+    items = [(lv, a, b, lib.empty(2, lv, orc.N) if i == 0 else None, lib.empty(2, lv - 1, orc.N))
+             for i, (lv, a, b) in enumerate(dev)]
+    log("fused ip", wname, levels)
+    bt = lib.batch(items)
+    sc = bt.sched()
+    bt.set_sched(sc["cols_tile"], sc["blocks_tile"], 1, 1)
+    for k, use_graph in enumerate((False, True, True)):
+        _run_check(lib, bt, items, dev, evk, use_graph, (wname, k))
+    bt.close()
