@@ -549,8 +549,23 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       }
     }
     const auto o = gbl(dst + ((u64)(J.dst_off + t) << c.log_n) + n0);
+    u64 v[CONV_CPT];
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) o[k] = conv_finish(sll[k], slh[k], shl[k], shh[k], m);
+    for (int k = 0; k < CONV_CPT; ++k) o[k] = v[k] = conv_finish(sll[k], slh[k], shl[k], shh[k], m);
+    if constexpr (MD) {
+      // the rescale's dropped limb in coefficient form, once, by linearity:
+      //   r_u = INTT(d_u[l-1]) + (INTT(ks_u[l-1]) - z_u[l-1]) [P^-1]_{q_{l-1}}
+      // with INTT(d_u[l-1]) = y[level + u] (replaced by r_u) and
+      // INTT(ks_u[l-1]) = ks_u[level + K]
+      if (pd.rs && t == pd.level - 1) {
+        const u64 pw = ldc(&P->pinv_l), pws = ldc(&P->pinv_ls);
+        const auto yy = gbl(pd.y + ((u64)(pd.level + jz) << c.log_n) + n0);
+        const auto kk = gbl(src + ((u64)(pd.level + c.K) << c.log_n) + n0);
+#pragma unroll
+        for (int k = 0; k < CONV_CPT; ++k)
+          yy[k] = csub(yy[k] + csub(shoup_lazy(kk[k] + m.q - v[k], pw, pws, m.q), m.q), m.q);
+      }
+    }
   }
 }
 
@@ -876,11 +891,9 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 }
 
 // ---------------------------------------------------------------- rescale lift + NTT cols
-// The dropped limb in coefficient form is pd.r (stand-alone rescale) or is
-// assembled by linearity of the INTT:
-//   r_u = INTT(d_u[l-1]) + (INTT(ks_u[l-1]) - z_u[l-1]) * [P^-1]_{q_{l-1}},
-// with INTT(d_u[l-1]) = y[level + u], INTT(ks_u[l-1]) = ks_u[level + K],
-// z_u[l-1] = zc_u[level - 1].  Then s = centered(r) mod q_i.
+// The dropped limb in coefficient form r_u is pd.r (stand-alone rescale) or
+// y[level + u] (assembled by the mod-down conversion, see k_conv).  Then
+// s = centered(r) mod q_i.
 // Items (u, column tile, i < level-1), i fastest.
 template <int LOGS, int EPW>
 __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u32 local, u64* lds) {
@@ -897,38 +910,15 @@ __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u
   const ModInfo m = ldc(c.mods + i);
   const u64 ql = ldc(&c.mods[nl].q);
   const u64 qlm = ldc(ldc(&P->qlmod) + i);
-  const u64 pw = ldc(&P->pinv_l), pws = ldc(&P->pinv_ls);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 N = 1ull << c.log_n;
   const u64 col = (u64)pos * PL::SUBS + sub;
-  // stand-alone rescale: r given, y / ks / zc absent (no pointer formed from them)
-  const bool given = pd.r != nullptr;
-  const auto rr = gbl(given ? pd.r + (u64)u * N + col : nullptr);
-  const auto dd = gbl(given ? nullptr : pd.y + ((u64)(pd.level + u) << c.log_n) + col);
-  const auto kk = gbl(given ? nullptr : pd.ks + ((u64)u * (pd.level + c.K + 1) + pd.level + c.K) * N + col);
-  const auto zz = gbl(given ? nullptr : pd.zc + ((u64)u * pd.level + pd.level - 1) * N + col);
-  // r = pd.r, or INTT(d) plus the correction; loads are grouped so that no
-  // element waits for its own loads alone.
+  // r_u: pd.r (stand-alone rescale) or y[level + u], where the mod-down
+  // conversion left it
+  const auto rr = gbl(pd.r ? pd.r + (u64)u * N + col : pd.y + ((u64)(pd.level + u) << c.log_n) + col);
   u64 x[Gm::R];
-  const auto first = given ? rr : dd;
 #pragma unroll
-  for (int k = 0; k < Gm::R; ++k) x[k] = first[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
-  if (!given) {
-    constexpr int TG = Gm::R < 8 ? Gm::R : 8;
-#pragma unroll
-    for (int k0 = 0; k0 < Gm::R; k0 += TG) {
-      u64 kv[TG], zv[TG];
-#pragma unroll
-      for (int g = 0; g < TG; ++g) {
-        const u64 e = (u64)RF::elem(tt, (k0 + g) / RF::G, (k0 + g) % RF::G) << n2;
-        kv[g] = kk[e];
-        zv[g] = zz[e];
-      }
-#pragma unroll
-      for (int g = 0; g < TG; ++g)
-        x[k0 + g] = csub(x[k0 + g] + csub(shoup_lazy(kv[g] + ql - zv[g], pw, pws, ql), ql), ql);
-    }
-  }
+  for (int k = 0; k < Gm::R; ++k) x[k] = rr[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) {
     const u64 r = x[k];
