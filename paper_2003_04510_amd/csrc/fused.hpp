@@ -180,7 +180,7 @@ __host__ __device__ constexpr u32 ipw_elems(u32 log_n) {
 __host__ __device__ constexpr u32 ipw_tiles(u32 log_n) { return (1u << log_n) / ipw_elems(log_n); }
 
 // Work items of one pair in a stage.
-inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_limbs, bool rs,
+inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_limbs, bool rs, bool wrl,
                        TileCfg tc_cfg = TileCfg{}) {
   const u32 tc = cols_tiles(log_n, tc_cfg.epw_c), tb = blocks_tiles(log_n, tc_cfg.epw_b);
   const u32 chunks_i = (1u << log_n) / (IP_THREADS * IP_CPT);
@@ -197,7 +197,7 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
     case ST_BLOCKS_IP: return tc_cfg.fused_ip ? (level + K + ex) * ipw_tiles(log_n) : 0;
     case ST_KS_ICOLS: return 2 * (K + ex) * tc;
     case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_c;
-    case ST_Z_NCOLS: return 2 * level * tc + (rs ? 2 * (level - 1) * tc : 0);
+    case ST_Z_NCOLS: return rs ? (wrl ? 2 * level * tc + 2 * (level - 1) * tc : 2 * (level - 1) * tc) : 2 * level * tc;
     case ST_LIFT: return rs ? 2 * (level - 1) * tc : 0;
     case ST_COMBINE: return 2 * level * tb;
     case ST_RESCALE: return rs ? 2 * (level - 1) * tb : 0;
@@ -491,7 +491,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
 // 30x30-bit products (no carries for up to 15 sources) and reducing once.
 // Mod up: sources y, outputs dt (jobs = digits).  Mod down: sources the
 // special limbs of ks (coefficient form), outputs zc, one job per polynomial.
-// Items (job or polynomial, target group, coefficient chunk).
+// Mod-down constants carry P^-1 ([P/p_k]_t [P^-1]_t), so zc holds z P^-1.
+// Items (job or polynomial, coefficient chunk, target group), group fastest.
 // NSMAX bounds the number of sources (the digit size for mod up, K for mod
 // down): all NSMAX source loads are issued unconditionally (index clamped to
 // the job's ns, constants of unused sources zero), so each thread waits for
@@ -504,8 +505,10 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const PairDesc pd = resolve(b, uniform(w), local);
   const PlanDev* P = pd.plan;
   const u32 nch = (1u << c.log_n) / (CONV_THREADS * CONV_CPT);
-  const u32 chunk = uniform(local % nch), rest = local / nch;
-  const u32 grp = uniform(rest % CONV_GROUPS), jz = uniform(rest / CONV_GROUPS);
+  // the target groups of a chunk are adjacent items (same XCD, same time),
+  // so their repeated source loads hit L2
+  const u32 grp = uniform(local % CONV_GROUPS), rest = local / CONV_GROUPS;
+  const u32 chunk = uniform(rest % nch), jz = uniform(rest / nch);
   const ConvJobDev J = ldc((MD ? ldc(&P->md_jobs) : ldc(&P->mu_jobs)) + (MD ? 0 : jz));
   const ConvTarget* tg = MD ? ldc(&P->md_tg) : ldc(&P->mu_tg);
   const u32* consts = MD ? ldc(&P->md_c) : ldc(&P->mu_c);
@@ -513,8 +516,13 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u64 ne1 = pd.level + c.K + 1;
   const u64* src = MD ? pd.ks + (u64)jz * ne1 * N : pd.y;
   u64* dst = MD ? pd.zc + (u64)jz * pd.level * N : pd.dt;
-  const u32 per = (J.nt + CONV_GROUPS - 1) / CONV_GROUPS;
-  const u32 t0 = grp * per, t1 = min(J.nt, t0 + per);
+  // merged rescale (mod down, rescaling, relinearized value not an output):
+  // targets q_0 .. q_{l-2} receive z'_t + [r]_t, see below
+  const bool merged = MD && pd.rs && !pd.wrl;
+  const u32 nt = merged ? J.nt - 1 : J.nt;
+  const u32 per = (nt + CONV_GROUPS - 1) / CONV_GROUPS;
+  const u32 t0 = grp * per, t1 = min(nt, t0 + per);
+  if (t0 >= t1) return;
   const u64 n0 = ((u64)chunk * CONV_THREADS + threadIdx.x) * CONV_CPT;
   const auto s0 = gbl(src + ((u64)J.src_off << c.log_n) + n0);
   u32 y0[NSMAX][CONV_CPT], y1[NSMAX][CONV_CPT];
@@ -528,7 +536,8 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       y1[s][k] = (u32)(y >> 30);
     }
   }
-  for (u32 t = t0; t < t1; ++t) {
+  // sum_s y_s c_s mod t for target index t of the job, canonical
+  const auto convert = [&](u32 t, u64 (&v)[CONV_CPT]) {
     const ConvTarget T = ldc(tg + J.tg_off + t);
     const ModInfo m = ldc(c.mods + T.mi);
     const u32* C = consts + T.c_off;
@@ -548,22 +557,66 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
         shh[k] += (u64)y1[s][k] * c1;
       }
     }
-    const auto o = gbl(dst + ((u64)(J.dst_off + t) << c.log_n) + n0);
+#pragma unroll
+    for (int k = 0; k < CONV_CPT; ++k) v[k] = conv_finish(sll[k], slh[k], shl[k], shh[k], m);
+  };
+  // The rescale's dropped limb in coefficient form, by linearity: with the
+  // mod-down constants carrying P^-1 (z' = z P^-1),
+  //   r_u = INTT(d_u[l-1]) + INTT(ks_u[l-1]) [P^-1]_{q_{l-1}} - z'_u[l-1]
+  // where INTT(d_u[l-1]) = y[level + u] and INTT(ks_u[l-1]) = ks_u[level + K].
+  const auto dropped = [&](const u64 (&zl)[CONV_CPT], u64 (&r)[CONV_CPT]) {
+    const u64 ql = ldc(&c.mods[pd.level - 1].q);
+    const u64 pw = ldc(&P->pinv_l), pws = ldc(&P->pinv_ls);
+    const auto yy = gbl(pd.y + ((u64)(pd.level + jz) << c.log_n) + n0);
+    const auto kk = gbl(src + ((u64)(pd.level + c.K) << c.log_n) + n0);
+#pragma unroll
+    for (int k = 0; k < CONV_CPT; ++k) {
+      const u64 a = csub(yy[k] + csub(shoup_lazy(kk[k], pw, pws, ql), ql), ql);
+      r[k] = submod(a, zl[k], ql);
+    }
+  };
+  if (merged) {
+    // Every group forms r (one more target), then each output is
+    // z'_t + [r]_t with r lifted centred; the NTT of that sum is
+    // NTT(z) P^-1 + NTT(s), so one transform serves mod down and rescale.
+    u64 r[CONV_CPT];
+    {
+      u64 zl[CONV_CPT];
+      convert(pd.level - 1, zl);
+      dropped(zl, r);
+    }
+    const u64 ql = ldc(&c.mods[pd.level - 1].q);
+    const u64* qlm = ldc(&P->qlmod);
+    for (u32 t = t0; t < t1; ++t) {
+      u64 v[CONV_CPT];
+      convert(t, v);
+      const ModInfo m = ldc(c.mods + t);
+      const u64 qm = ldc(qlm + t);
+      const auto o = gbl(dst + ((u64)t << c.log_n) + n0);
+#pragma unroll
+      for (int k = 0; k < CONV_CPT; ++k) {
+        u64 s = csub(r[k] - mulhi(r[k], m.one_s) * m.q, m.q);  // r mod q_t
+        if (2 * r[k] >= ql) s = submod(s, qm, m.q);           // centred
+        o[k] = csub(v[k] + s, m.q);
+      }
+    }
+    return;
+  }
+  for (u32 t = t0; t < t1; ++t) {
     u64 v[CONV_CPT];
+    convert(t, v);
+    const auto o = gbl(dst + ((u64)(J.dst_off + t) << c.log_n) + n0);
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) o[k] = v[k] = conv_finish(sll[k], slh[k], shl[k], shh[k], m);
+    for (int k = 0; k < CONV_CPT; ++k) o[k] = v[k];
     if constexpr (MD) {
-      // the rescale's dropped limb in coefficient form, once, by linearity:
-      //   r_u = INTT(d_u[l-1]) + (INTT(ks_u[l-1]) - z_u[l-1]) [P^-1]_{q_{l-1}}
-      // with INTT(d_u[l-1]) = y[level + u] (replaced by r_u) and
-      // INTT(ks_u[l-1]) = ks_u[level + K]
+      // rescaling with the relinearized value as an output: r_u replaces
+      // y[level + u] for the lift
       if (pd.rs && t == pd.level - 1) {
-        const u64 pw = ldc(&P->pinv_l), pws = ldc(&P->pinv_ls);
+        u64 r[CONV_CPT];
+        dropped(v, r);
         const auto yy = gbl(pd.y + ((u64)(pd.level + jz) << c.log_n) + n0);
-        const auto kk = gbl(src + ((u64)(pd.level + c.K) << c.log_n) + n0);
 #pragma unroll
-        for (int k = 0; k < CONV_CPT; ++k)
-          yy[k] = csub(yy[k] + csub(shoup_lazy(kk[k] + m.q - v[k], pw, pws, m.q), m.q), m.q);
+        for (int k = 0; k < CONV_CPT; ++k) yy[k] = r[k];
       }
     }
   }
@@ -796,11 +849,14 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
 }
 
 // ---------------------------------------------------------------- NTT blocks + combine + rescale
-// v_u[i] = d_u[i] + (ks_u[i] - NTT(z_u[i])) * [P^-1]_{q_i}  (rl holds d_u),
-// the relinearized ciphertext, written to rl when requested (wrl); when
-// rescaling, for i < level-1 also
-//   out_u[i] = (v_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}   (s_u over d2),
-// so v never makes a trip through HBM unless it is an output.
+// v_u[i] = d_u[i] + ks_u[i] [P^-1]_{q_i} - NTT(z'_u[i])  (rl holds d_u,
+// z' = z P^-1), the relinearized ciphertext, written to rl when requested
+// (wrl).  When rescaling, for i < level-1 also
+//   out_u[i] = (v_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}:
+// with rl an output, s_u (over d2) takes a second transform here; without
+// it, the mod-down conversion already added s to z', so z holds the NTT
+// input of z' + s and out_u[i] = v_u[i] * [q_{l-1}^-1]_{q_i}.  v never
+// makes a trip through HBM unless it is an output.
 // Items (i, u, block tile), tile fastest.
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common c, Batch b) {
@@ -857,7 +913,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
       const int idx = threadIdx.x + k * THREADS;
       Z[k] = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
     }
-    if (resc) {
+    const bool two = resc && pd.wrl;  // s not merged into z
+    if (two) {
       lds_barrier();  // every Z is read before the tile is reused
 #pragma unroll
       for (int k = 0; k < Gm::R; ++k) x[k] = A::in(sp[RF::elem(tt, k / RF::G, k % RF::G)], M);
@@ -878,11 +935,11 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 #pragma unroll
       for (int g = 0; g < TG; ++g) {
         const int idx = threadIdx.x + (k0 + g) * THREADS;
-        const u64 md = shoup_lazy(kv[g] + m.q - Z[k0 + g], pw, pws, m.q);
-        const u64 v = csub(csub(dv[g] + md, m.q << 1), m.q);
+        const u64 md = shoup_lazy(kv[g], pw, pws, m.q);  // [0, 2q)
+        const u64 v = csub(csub(dv[g] + md + m.q - Z[k0 + g], m.q << 1), m.q);
         if (pd.wrl) rlu[idx] = v;
         if (resc) {
-          const u64 S = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
+          const u64 S = two ? A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M) : 0;
           ou[idx] = csub(shoup_lazy(v + m.q - S, qw, qws, m.q), m.q);
         }
       }
@@ -949,10 +1006,11 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
   lift_item<LOGS, EPW>(c, pd, local, lds);
 }
 
-// NTT cols pass of z (mod-down) and, when rescaling, the lift + NTT cols
-// pass of s, in one launch: items [0, 2 level tiles) are z's, the rest s's.
-// The two touch disjoint buffers (z cols: zc -> z; lift: zc_u[level-1], y,
-// ks -> s over d2).
+// NTT cols pass of z' (mod-down) and, when rescaling with rl an output, the
+// lift + NTT cols pass of s, in one launch: items [0, 2 level tiles) are
+// z's, the rest s's.  The two touch disjoint buffers (z cols: zc -> z; lift:
+// y -> s over d2).  Rescaling without rl as an output, s is already in z'
+// and only limbs i < level-1 are transformed.
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c, Batch b) {
   __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
@@ -960,7 +1018,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c
   if (w >= b.nitems) return;
   u32 local;
   const PairDesc pd = resolve(b, uniform(w), local);
-  const u32 nz = uniform(2 * pd.level * cols_tiles(c.log_n, EPW));
+  const u32 nz = uniform(2 * (pd.rs && !pd.wrl ? pd.level - 1 : pd.level) * cols_tiles(c.log_n, EPW));
   if (local < nz) list_cols_item<true, LOGS, EPW, ST_Z_NCOLS>(c, pd, local, lds);
   else lift_item<LOGS, EPW>(c, pd, local - nz, lds);
 }

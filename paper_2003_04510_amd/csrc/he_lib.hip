@@ -448,7 +448,8 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     md.src_off = lvl; md.ns = K; md.dst_off = 0; md.nt = lvl; md.c_off = 0; md.m_off = 0;
     std::vector<u64> mdc((size_t)K * lvl);
     for (u32 k = 0; k < K; ++k)
-      for (u32 i = 0; i < lvl; ++i) mdc[(size_t)k * lvl + i] = prod_mod(c->mod, pidx, L + k, q[i]);
+      for (u32 i = 0; i < lvl; ++i)  // [P/p_k]_{q_i} [P^-1]_{q_i}: the conversion yields z P^-1
+        mdc[(size_t)k * lvl + i] = mulmod(prod_mod(c->mod, pidx, L + k, q[i]), pinv[2 * i], q[i]);
     // rescale constants
     std::vector<u64> qlinv(2 * (lvl > 1 ? lvl - 1 : 1), 0), qlmod(lvl > 1 ? lvl - 1 : 1, 0);
     for (u32 i = 0; i + 1 < lvl; ++i) {
@@ -721,15 +722,22 @@ void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double
       bytes = (P.dt_limbs + l + 2.0 * P.beta * ne + 2 * (ne + ex)) * N * 8;
       break;
     case ST_KS_ICOLS: ops = 2 * (K + ex) * (hN * n1 + N); bytes = 4 * (K + ex) * N * 8; break;
-    case ST_MD_CONV: ops = 2 * K * l * N; bytes = 2 * (K + l) * N * 8; break;
-    case ST_Z_NCOLS:  // z cols, plus the lift's cols pass when rescaling
-      ops = 2 * l * hN * n1 + (rs ? 2 * (l - 1) * hN * n1 : 0);
-      bytes = (4 * l + (rs ? 2 * (l - 1) + 6 : 0)) * N * 8;
+    case ST_MD_CONV: {  // special limbs in, z' out; rescaling: y, ks[level+K] in, r out or merged
+      const double lo = (rs && !wrl) ? l - 1 : l;
+      ops = 2 * K * l * N;
+      bytes = (2 * K + 2 * lo + (rs ? (wrl ? 6 : 4) : 0)) * N * 8;
       break;
-    case ST_COMBINE: {  // z, ks, d in; s in and out out when rescaling; rl out when requested
+    }
+    case ST_Z_NCOLS: {  // z' cols (z' + s when merged), plus the lift's cols pass when not merged
+      const double lo = (rs && !wrl) ? l - 1 : l, ls = (rs && wrl) ? l - 1 : 0;
+      ops = 2 * (lo + ls) * hN * n1;
+      bytes = (4 * lo + (ls ? 2 * ls + 2 : 0)) * N * 8;
+      break;
+    }
+    case ST_COMBINE: {  // z, ks, d in; out out when rescaling (s in when not merged); rl out when requested
       const double lo = (rs && !wrl) ? l - 1 : l;  // limbs combined
-      ops = 2 * lo * hN * n2 + 2 * lo * N + (rs ? 2 * (l - 1) * (hN * n2 + N) : 0);
-      bytes = (2 * lo * 3 + (wrl ? 2 * l : 0) + (rs ? 2 * (l - 1) * 2 : 0)) * N * 8;
+      ops = 2 * lo * hN * n2 + 2 * lo * N + (rs ? 2 * (l - 1) * ((wrl ? hN * n2 : 0) + N) : 0);
+      bytes = (2 * lo * 3 + (wrl ? 2 * l : 0) + (rs ? 2 * (l - 1) * (wrl ? 2 : 1) : 0)) * N * 8;
       break;
     }
     case ST_LIFT: ops = rs ? 2 * (l - 1) * hN * n1 : 0; bytes = rs ? (2 * (l - 1) + 6) * N * 8 : 0; break;
@@ -816,7 +824,7 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
     Batch b{};
     b.one = pd;
     b.npairs = 1;
-    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, pd.rs != 0, default_tiles(c->log_n));
+    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, pd.rs != 0, pd.wrl != 0, default_tiles(c->log_n));
     double ops = 0, bytes = 0;
     if (c->timing) stage_work(c, s, level, pd.rs != 0, ops, bytes, pd.wrl != 0);
     launch_stage(c, s, cm, b, ops, bytes, on, default_tiles(c->log_n));
@@ -847,7 +855,7 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
     Batch b{};
     b.one = pd;
     b.npairs = 1;
-    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, true, default_tiles(c->log_n));
+    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, true, false, default_tiles(c->log_n));
     double ops = 0, bytes = 0;
     if (c->timing) stage_work(c, s, level, true, ops, bytes);
     launch_stage(c, s, cm, b, ops, bytes, st, default_tiles(c->log_n));
@@ -908,7 +916,7 @@ static he_status batch_offsets(const he_ctx* c, he_batch* bt) {
     for (u32 i = 0; i < n; ++i) {
       bt->hoffs[(size_t)s * (n + 1) + i] = (u32)acc;
       const LevelPlan& P = c->lv[bt->levels[i]];
-      acc += stage_items(s, c->log_n, bt->levels[i], c->K, P.beta, P.dt_limbs, bt->rs[i] != 0, bt->tiles);
+      acc += stage_items(s, c->log_n, bt->levels[i], c->K, P.beta, P.dt_limbs, bt->rs[i] != 0, bt->wrl[i] != 0, bt->tiles);
     }
     if (acc > 0xffffff00ull) return fail(HE_EUNSUPPORTED, "he_batch: batch too large");
     bt->hoffs[(size_t)s * (n + 1) + n] = (u32)acc;
