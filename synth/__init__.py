@@ -156,3 +156,38 @@ def enc_draws(w: Workload, seed: int) -> EncDraws:
 def batch_levels(n_pairs: int = 256, lo: int = 4, hi: int = 24, seed: int = 42) -> np.ndarray:
     """Per-pair levels for the batched workload, uniform over lo..hi inclusive."""
     return rng(seed).integers(lo, hi + 1, size=n_pairs)
+
+
+# ---------------------------------------------------------------- big-integer (non-RNS) workload
+# The paper's own HE Mul: N = 2^16, log Q = 1200 (= 40 levels of log p = 30)
+# (Sec. II-A, Table III).
+BIG_LOG_N, BIG_LOG_Q, BIG_LOG_P = 16, 1200, 30
+
+
+def big_words(bits: int) -> int:
+    """64-bit words holding a `bits`-bit non-negative integer."""
+    return -(-bits // 64)
+
+
+def uniform_bigint(seed: int, bits: int, n: int, stream: int = 0, words: int = 0) -> np.ndarray:
+    """n uniform integers in [0, 2^bits) as little-endian words [words][n] uint64
+    (words >= big_words(bits); higher words zero)."""
+    W = max(words, big_words(bits))
+    g = rng(seed, 100 + stream)
+    out = np.zeros((W, n), dtype=np.uint64)
+    full, rem = divmod(bits, 64)
+    for k in range(full):
+        out[k] = g.integers(0, 2**64, size=n, dtype=np.uint64)
+    if rem:
+        out[full] = g.integers(0, 2**rem, size=n, dtype=np.uint64)
+    return out
+
+
+def big_ciphertext(seed: int, logq: int, n: int, words: int = 0) -> np.ndarray:
+    """A ciphertext-shaped [2][words][n] array of uniform coefficients below 2^logq."""
+    return np.stack([uniform_bigint(seed, logq, n, 0, words), uniform_bigint(seed, logq, n, 1, words)])
+
+
+def big_evk(seed: int, logQ: int, n: int) -> np.ndarray:
+    """An evaluation-key-shaped [2][words][n] array of uniform coefficients below Q^2."""
+    return np.stack([uniform_bigint(seed, 2 * logQ, n, 2), uniform_bigint(seed, 2 * logQ, n, 3)])
