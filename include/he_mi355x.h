@@ -259,6 +259,59 @@ typedef struct he_kernel_stat {
 he_status he_timing_enable(he_ctx* ctx, int enable, const char* only);
 he_status he_timing_read(he_ctx* ctx, he_kernel_stat* out, uint32_t max, uint32_t* n);
 
+/* ---------------------------------------------------------------------------
+ * The paper's own (non-RNS) HE Mul: HEAAN with power-of-two moduli
+ * (Sec. II-III, Fig. 2).  A ciphertext at level q = 2^logq is (bx, ax), two
+ * polynomials of N big-integer coefficients in [0, q); the evaluation key is
+ * (evk.bx, evk.ax) modulo Q^2 (Q = 2^logQ).  HE Mul runs five polynomial
+ * products through RNS: region 1 (ax1+bx1)(ax2+bx2), ax1 ax2, bx1 bx2 modulo
+ * q over np1 primes; region 2 ax1 ax2 times evk.bx and evk.ax over np2
+ * primes, shifted right by log Q with rounding (round half up); then
+ *   ax3 = ks_ax + axbx - axax - bxbx,  bx3 = ks_bx + bxbx   (mod q)
+ * and optionally the rescale round(c3 / 2^logp) (Sec. II-A).  Each product
+ * is CRT (Sec. IV-A, matrix form), NTT, element-wise product, inverse NTT
+ * and iCRT (Algorithm 6, matrix form).
+ *
+ * Layout: a big-integer polynomial is [W][N] little-endian uint64 words,
+ * W = ceil(logQ / 64) (words above logq zero); a ciphertext is [2][W][N]
+ * (bx, ax).  The evaluation key is [2][W2][N], W2 = ceil(2 logQ / 64).
+ * All pointers named d_* are device memory the caller owns. */
+typedef struct he_big_ctx he_big_ctx;
+
+/* Context for ring degree 2^log_n (12..17) and log Q in [64, 1216]: picks
+ * the region primes (60-bit, 1 mod 2N; np1 of them cover 2 log Q + log N + 3
+ * bits, np2 cover 3 log Q + log N + 3 bits) and uploads NTT, CRT and iCRT
+ * tables to `device`.  HE_EUNSUPPORTED outside those ranges. */
+he_status he_big_ctx_create(uint32_t log_n, uint32_t logQ, int device, he_big_ctx** out);
+void he_big_ctx_destroy(he_big_ctx* ctx);
+/* np1, np2, words per coefficient W, and the np2 primes (any may be NULL). */
+he_status he_big_info(const he_big_ctx* ctx, uint32_t* np1, uint32_t* np2, uint32_t* words, uint64_t* primes);
+size_t he_big_ct_bytes(const he_big_ctx* ctx);        /* 2*W*N*8 */
+size_t he_big_evk_bytes(const he_big_ctx* ctx);       /* 2*W2*N*8 */
+size_t he_big_evk_ntt_bytes(const he_big_ctx* ctx);   /* 2*np2*N*8 */
+size_t he_big_workspace_bytes(const he_big_ctx* ctx); /* for he_big_mul */
+
+/* One-time key preparation (the key's CRT and NTT, Fig. 2 region 2):
+ * d_evk [2][W2][N] (coefficients below Q^2) -> d_evk_ntt [2][np2][N], the NTT
+ * form over the np2 primes.  Enqueued on `stream`. */
+he_status he_big_evk_prepare(he_big_ctx* ctx, const uint64_t* d_evk, uint64_t* d_evk_ntt, he_stream stream);
+
+/* HE Mul at level q = 2^logq (1 <= logq <= log Q): d_ct1, d_ct2 [2][W][N]
+ * with coefficients below 2^logq; d_evk_ntt from he_big_evk_prepare.  Writes
+ * c3 to d_out [2][W][N], or, when logp > 0, the rescaled c3 at level
+ * 2^(logq - logp) (logp < logq, logp <= 63).  d_out must not overlap the
+ * inputs (HE_EINVAL).  ws: he_big_workspace_bytes bytes (HE_ENOMEM if
+ * smaller).  Enqueued on `stream`; asynchronous. */
+he_status he_big_mul(he_big_ctx* ctx, uint32_t logq, const uint64_t* d_ct1, const uint64_t* d_ct2,
+                     const uint64_t* d_evk_ntt, uint64_t* d_out, uint32_t logp, void* ws, size_t ws_bytes,
+                     he_stream stream);
+
+/* Per-kernel timing of the big-integer path (as he_timing_*): kinds
+ * big_crt, ntt_cols / ntt_blocks (NTT), intt_blocks / intt_cols (iNTT),
+ * big_icrt, big_pointwise and big_finish (element-wise work). */
+he_status he_big_timing_enable(he_big_ctx* ctx, int enable);
+he_status he_big_timing_read(he_big_ctx* ctx, he_kernel_stat* out, uint32_t max, uint32_t* n);
+
 const char* he_status_str(he_status s);
 const char* he_last_error(void);
 

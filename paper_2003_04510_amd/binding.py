@@ -93,13 +93,25 @@ def load_library():
     L.he_server_stats.argtypes = [vp] + [ctypes.POINTER(ctypes.c_uint64)] * 4
     L.he_server_destroy.argtypes = [vp]
     L.he_server_destroy.restype = None
+    L.he_big_ctx_create.argtypes = [u32, u32, ctypes.c_int, ctypes.POINTER(vp)]
+    L.he_big_ctx_destroy.argtypes = [vp]
+    L.he_big_ctx_destroy.restype = None
+    L.he_big_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32), u64p]
+    for f in ("he_big_ct_bytes", "he_big_evk_bytes", "he_big_evk_ntt_bytes", "he_big_workspace_bytes"):
+        getattr(L, f).argtypes = [vp]
+        getattr(L, f).restype = ctypes.c_size_t
+    L.he_big_evk_prepare.argtypes = [vp, vp, vp, vp]
+    L.he_big_mul.argtypes = [vp, u32, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
+    L.he_big_timing_enable.argtypes = [vp, ctypes.c_int]
+    L.he_big_timing_read.argtypes = [vp, ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
     L.he_status_str.argtypes = [st]
     L.he_status_str.restype = ctypes.c_char_p
     L.he_last_error.restype = ctypes.c_char_p
     for f in ("he_gen_primes", "he_ctx_create", "he_keygen", "he_encrypt", "he_decrypt", "he_mul",
               "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read", "he_batch_create",
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
-              "he_server_poll", "he_server_stats"):
+              "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
+              "he_big_mul", "he_big_timing_enable", "he_big_timing_read"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -404,3 +416,86 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class BigContext:
+    """The paper's non-RNS HE Mul (power-of-two moduli, big-integer
+    coefficients as [W][N] uint64 words) on GPU `device`."""
+
+    def __init__(self, log_n: int, logQ: int, device: int = 0):
+        import torch
+        self.torch = torch
+        L = load_library()
+        self.log_n, self.N, self.logQ, self.device = log_n, 1 << log_n, logQ, device
+        h = vp()
+        _check(L.he_big_ctx_create(log_n, logQ, device, ctypes.byref(h)), "he_big_ctx_create")
+        self._h = h
+        np1, np2, W = u32(0), u32(0), u32(0)
+        _check(L.he_big_info(h, ctypes.byref(np1), ctypes.byref(np2), ctypes.byref(W), None), "he_big_info")
+        self.np1, self.np2, self.W = np1.value, np2.value, W.value
+        self.W2 = (2 * logQ + 63) // 64
+        pr = np.zeros(self.np2, dtype=np.uint64)
+        _check(L.he_big_info(h, None, None, None, pr.ctypes.data_as(u64p)), "he_big_info")
+        self.primes = [int(x) for x in pr]
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().he_big_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dev(self):
+        return self.torch.device("cuda", self.device)
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.dev).cuda_stream)
+
+    def empty(self, *shape):
+        return self.torch.empty(shape, dtype=self.torch.int64, device=self.dev)
+
+    def to_device(self, arr: np.ndarray):
+        a = np.ascontiguousarray(arr, dtype=np.uint64).view(np.int64)
+        return self.torch.from_numpy(a.copy()).to(self.dev)
+
+    @staticmethod
+    def to_host(t) -> np.ndarray:
+        return t.detach().cpu().numpy().view(np.uint64)
+
+    def workspace(self):
+        need = int(load_library().he_big_workspace_bytes(self._h)) // 8
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = self.empty(need)
+        return self._ws
+
+    def evk_prepare(self, evk):
+        """evk [2][W2][N] words (below Q^2) -> NTT form [2][np2][N]."""
+        out = self.empty(2, self.np2, self.N)
+        _check(load_library().he_big_evk_prepare(self._h, vp(evk.data_ptr()), vp(out.data_ptr()), self._stream()),
+               "he_big_evk_prepare")
+        return out
+
+    def he_mul(self, logq: int, ct1, ct2, evk_ntt, logp: int = 0, out=None, ws=None):
+        """HE Mul at level 2^logq; rescaled by 2^logp when logp > 0.  -> [2][W][N]."""
+        out = self.empty(2, self.W, self.N) if out is None else out
+        ws = self.workspace() if ws is None else ws
+        _check(load_library().he_big_mul(self._h, logq, vp(ct1.data_ptr()), vp(ct2.data_ptr()),
+                                         vp(evk_ntt.data_ptr()), vp(out.data_ptr()), logp, vp(ws.data_ptr()),
+                                         ws.numel() * 8, self._stream()), "he_big_mul")
+        return out
+
+    def timing(self, enable: bool):
+        _check(load_library().he_big_timing_enable(self._h, int(enable)), "he_big_timing_enable")
+
+    def timing_read(self) -> dict:
+        arr = (KernelStat * 64)()
+        n = u32(0)
+        _check(load_library().he_big_timing_read(self._h, arr, 64, ctypes.byref(n)), "he_big_timing_read")
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].ops, arr[i].bytes)
+                for i in range(min(n.value, 64))}

@@ -1360,3 +1360,4 @@ he_status he_decrypt(he_ctx* c, uint32_t level, const uint64_t* d_ct, const int6
 }
 
 }  // extern "C"
+#include "big_host.hpp"

@@ -55,3 +55,16 @@ def test_status_strings_and_argument_errors():
     assert lib.he_ctx_create(12, 3, 1, 3, bad, p, 0, ctypes.byref(h)) == -1  # duplicate
     with pytest.raises(Exception):
         P.binding.gen_primes(12, 70, 1)
+
+
+def test_big_context_argument_errors():
+    """The non-RNS path rejects unsupported parameters before any device call."""
+    import paper_2003_04510_amd as P
+    lib = P.load_library()
+    h = ctypes.c_void_p()
+    assert lib.he_big_ctx_create(16, 1200, 0, None) == -1        # null out
+    assert lib.he_big_ctx_create(11, 1200, 0, ctypes.byref(h)) == -5  # log_n below 12
+    assert lib.he_big_ctx_create(16, 1217, 0, ctypes.byref(h)) == -5  # log Q above 1216
+    assert lib.he_big_ctx_create(16, 63, 0, ctypes.byref(h)) == -5    # log Q below 64
+    assert lib.he_big_ct_bytes(None) == 0 and lib.he_big_workspace_bytes(None) == 0
+    assert lib.he_big_mul(None, 10, None, None, None, None, 0, None, 0, None) == -1
