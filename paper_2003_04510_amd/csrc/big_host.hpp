@@ -8,16 +8,20 @@
 // the CRT / iCRT tables.
 struct he_big_ctx {
   he_ctx* ntt = nullptr;
-  u32 log_n = 0, logQ = 0, np1 = 0, np2 = 0, W = 0, W2 = 0, C1 = 0, C2 = 0, ndmax = 0;
+  u32 log_n = 0, logQ = 0, np1 = 0, np2 = 0, W = 0, W2 = 0, C1 = 0, C2 = 0, Pc1 = 0, Pc2 = 0;
+  u32 kb_ct = 0, kb_evk = 0;       // CRT k-blocks (32 bytes) of a ciphertext / key coefficient
   u64 N = 0;
   int device = 0;
   std::vector<u64> primes;
   uint8_t* blob = nullptr;
-  const u32* crt_c = nullptr;    // [np2][ndmax][2]
-  const u64* iscale1 = nullptr;  // [np1][2]: N^-1 [(M1/p_i)^-1]_{p_i}, Shoup pairs
-  const u64* iscale2 = nullptr;  // [np2][2]
-  const double* pinv = nullptr;  // [np2]
-  const u32 *T1 = nullptr, *negM1 = nullptr, *T2 = nullptr, *negM2 = nullptr;
+  const u64* crtB = nullptr;       // [8 (np2 + 1)][4 kb_evk]: CRT matrix (balanced digits)
+  const u64 *adj_ct = nullptr, *adj_evk = nullptr;  // [np2]: offset corrections of the CRT
+  const u64* iscale1 = nullptr;    // [np1][2]: N^-1 [(M1/p_i)^-1]_{p_i}, Shoup pairs
+  const u64* iscale2 = nullptr;    // [np2][2]
+  const double* pinv = nullptr;    // [np2]
+  const u64 *B1 = nullptr, *B2 = nullptr;            // [64][Pc]: iCRT Toeplitz fragments
+  const long long *CW1 = nullptr, *CW2 = nullptr;    // [C]: iCRT offset corrections per word column
+  const u32 *negM1 = nullptr, *negM2 = nullptr;      // [C]: words of -M mod 2^(32 C)
 };
 
 namespace {
@@ -92,18 +96,46 @@ Words words_neg(const Words& a) {  // -a mod 2^(32 |a|)
   }
   return r;
 }
+// Balanced base-256 digits in [-128, 127] of the little-endian bytes
+// `bytes` (the final carry, of weight 256^n, is dropped: callers need the
+// value modulo 256^n or know it to be zero).
+std::vector<int> balanced(const std::vector<uint8_t>& bytes) {
+  std::vector<int> d(bytes.size());
+  int cy = 0;
+  for (size_t i = 0; i < bytes.size(); ++i) {
+    int v = bytes[i] + cy;
+    cy = 0;
+    if (v >= 128) {
+      v -= 256;
+      cy = 1;
+    }
+    d[i] = v;
+  }
+  return d;
+}
+u64 pack8(const int* d) {  // 8 signed digits -> bytes of a word
+  u64 w = 0;
+  for (int j = 0; j < 8; ++j) w |= (u64)(uint8_t)(int8_t)d[j] << (8 * j);
+  return w;
+}
 double log2_sum(const std::vector<u64>& p, u32 n) {
   double s = 0;
   for (u32 i = 0; i < n; ++i) s += std::log2((double)p[i]);
   return s;
 }
 
+constexpr u32 MF_ROWS = big::MF_THREADS / 4;  // coefficients per matrix-core workgroup
+
 void icrt_launch(const big::IcrtArgs& a, u32 njobs, hipStream_t st) {
-  const u32 blocks = (u32)((1ull << a.log_n) / big::ICRT_THREADS);
-  hipLaunchKernelGGL(big::k_big_icrt, dim3(blocks, njobs), dim3(big::ICRT_THREADS), 0, st, a);
+  const u32 blocks = (u32)((1ull << a.log_n) / MF_ROWS);
+  hipLaunchKernelGGL(big::k_big_icrt, dim3(blocks, njobs), dim3(big::MF_THREADS), 0, st, a);
+}
+void crt_launch(const big::CrtArgs& a, u32 njobs, hipStream_t st) {
+  const u32 blocks = (u32)((1ull << a.log_n) / MF_ROWS);
+  hipLaunchKernelGGL(big::k_big_crt, dim3(blocks, njobs), dim3(big::MF_THREADS), 0, st, a);
 }
 
-size_t big_ws_limbs(const he_big_ctx* b) { return 6ull * b->np1 + 3ull * b->W + 2ull * b->np2 + 2ull * b->W; }
+size_t big_ws_limbs(const he_big_ctx* b) { return 4ull * b->np1 + 3ull * b->W + 2ull * b->np2 + 2ull * b->W; }
 
 }  // namespace
 
@@ -122,7 +154,8 @@ he_status he_big_ctx_create(uint32_t log_n, uint32_t logQ, int device, he_big_ct
   // polynomials, region 2 products of a log Q-bit one with the evaluation
   // key (2 log Q bits): |X| < N 2^bits, so M > 2^(bits + log N + 3) keeps
   // the centred value within M/4.
-  const double need1 = 2.0 * logQ + log_n + 3, need2 = 3.0 * logQ + log_n + 3;
+  // (Region 1's Karatsuba sums are not reduced mod q: two more bits.)
+  const double need1 = 2.0 * logQ + log_n + 5, need2 = 3.0 * logQ + log_n + 3;
   std::vector<u64> pr(64);
   if (!gen_primes(log_n, 60, 64, nullptr, 0, pr.data())) return fail(HE_EINVAL, "he_big_ctx_create: primes");
   u32 np1 = 1, np2 = 1;
@@ -133,28 +166,53 @@ he_status he_big_ctx_create(uint32_t log_n, uint32_t logQ, int device, he_big_ct
   b->primes = pr; b->np1 = np1; b->np2 = np2;
   b->C1 = (logQ + 31) / 32 + 1;
   b->C2 = (2 * logQ + 31) / 32 + 1;
+  b->Pc1 = 16 * ((b->C1 + 3) / 4);
+  b->Pc2 = 16 * ((b->C2 + 3) / 4);
+  b->kb_ct = (b->W + 3) / 4;
+  b->kb_evk = (b->W2 + 3) / 4;
+  if (np2 > 64 || b->kb_evk > (u32)big::CRT_KBMAX) return fail(HE_EUNSUPPORTED, "log Q %u too large", logQ);
   he_status r = ntt_ctx_create(log_n, pr, device, &b->ntt);
   if (r != HE_OK) return r;
   const u64 N = b->N;
   Blob B;
-  // CRT: 2^(28 h) mod p_i, digits of a 2 log Q-bit key coefficient
-  b->ndmax = (64 * b->W2 + big::DIG - 1) / big::DIG;
-  std::vector<u32> cc((size_t)np2 * b->ndmax * 2);
-  for (u32 i = 0; i < np2; ++i)
-    for (u32 h = 0; h < b->ndmax; ++h) {
-      const u64 v = powmod(2, (u64)big::DIG * h, pr[i]);
-      cc[((size_t)i * b->ndmax + h) * 2] = (u32)(v & ((1u << 30) - 1));
-      cc[((size_t)i * b->ndmax + h) * 2 + 1] = (u32)(v >> 30);
+  // CRT matrix: column 8i + b, k = byte h: digit b of c_{i,h} = [2^(8h)]_{p_i}
+  // (balanced); 8 (np2 + 1) columns so a last half tile stays in the table.
+  const u32 KW = 4 * b->kb_evk, KP = 8 * KW;
+  std::vector<u64> crtB((size_t)8 * (np2 + 1) * KW, 0);
+  std::vector<u64> adj_ct(np2), adj_evk(np2);
+  for (u32 i = 0; i < np2; ++i) {
+    const u64 p = pr[i];
+    std::vector<std::vector<int>> dig(KP);
+    u64 sum_ct = 0, sum_evk = 0;  // sum_h c_{i,h} mod p over the k-range of each use
+    for (u32 h = 0; h < KP; ++h) {
+      const u64 c = powmod(2, 8ull * h, p);
+      std::vector<uint8_t> by(8);
+      for (int t = 0; t < 8; ++t) by[t] = (uint8_t)(c >> (8 * t));
+      dig[h] = balanced(by);  // c < 2^60: eight digits, no final carry
+      if (h < 32 * b->kb_ct) sum_ct = addmod(sum_ct, c, p);
+      sum_evk = addmod(sum_evk, c, p);
     }
-  const size_t o_cc = B.add(cc);
+    for (u32 bd = 0; bd < 8; ++bd)
+      for (u32 kw = 0; kw < KW; ++kw) {
+        int d8[8];
+        for (int j = 0; j < 8; ++j) d8[j] = dig[8 * kw + j][bd];
+        crtB[((size_t)(8 * i + bd)) * KW + kw] = pack8(d8);
+      }
+    const u64 t80 = powmod(2, 80, p);
+    adj_ct[i] = submod(mulmod(128 % p, sum_ct, p), t80, p);
+    adj_evk[i] = submod(mulmod(128 % p, sum_evk, p), t80, p);
+  }
+  const size_t o_crtB = B.add(crtB), o_adj_ct = B.add(adj_ct), o_adj_evk = B.add(adj_evk);
   std::vector<double> pinv(np2);
   for (u32 i = 0; i < np2; ++i) pinv[i] = 1.0 / (double)pr[i];
   const size_t o_pinv = B.add(pinv);
-  // iCRT tables of a region over the first np primes, C columns
-  auto region = [&](u32 np, u32 C, size_t& o_sc, size_t& o_T, size_t& o_nM) {
+  // iCRT tables of a region over the first np primes, C word columns:
+  // fragments B[i][P] (byte j = digit P - j of (M/p_i) mod 2^(32 C)),
+  // offset corrections per word column, -M mod 2^(32 C), inverse NTT scales.
+  auto region = [&](u32 np, u32 C, u32 Pc, size_t& o_sc, size_t& o_B, size_t& o_cw, size_t& o_nM) {
     std::vector<u64> sc(2 * np);
-    const size_t row = C + 1 + big::ICRT_CT;  // row i: 0, words 0 .. C-1, zero padding
-    std::vector<u32> T((size_t)np * row, 0);
+    std::vector<u64> Bt((size_t)64 * Pc, 0);
+    std::vector<long long> colsum(Pc, 0), cw(C, 0);
     Words M{1};
     for (u32 i = 0; i < np; ++i) words_mul(M, pr[i]);
     for (u32 i = 0; i < np; ++i) {
@@ -169,14 +227,27 @@ he_status he_big_ctx_create(uint32_t log_n, uint32_t logQ, int device, he_big_ct
       sc[2 * i] = v;
       sc[2 * i + 1] = shoup(v, pr[i]);
       const Words t = words_trunc(Mi, C);
-      for (u32 c = 0; c < C; ++c) T[(size_t)i * row + 1 + c] = t[c];
+      std::vector<uint8_t> by(4 * C);
+      for (u32 q = 0; q < 4 * C; ++q) by[q] = (uint8_t)(t[q / 4] >> (8 * (q % 4)));
+      const std::vector<int> d = balanced(by);  // mod 2^(32 C): the final carry drops out
+      for (u32 P = 0; P < Pc; ++P) {
+        int d8[8];
+        for (int j = 0; j < 8; ++j) {
+          const int q = (int)P - j;
+          d8[j] = (q >= 0 && q < (int)(4 * C)) ? d[q] : 0;
+          colsum[P] += d8[j];
+        }
+        Bt[(size_t)i * Pc + P] = pack8(d8);
+      }
     }
+    for (u32 m = 0; m < C; ++m)
+      for (u32 bb = 0; bb < 4; ++bb) cw[m] += 128ll * colsum[4 * m + bb] * (1ll << (8 * bb));
     const Words nM = words_neg(words_trunc(M, C));
-    o_sc = B.add(sc); o_T = B.add(T); o_nM = B.add(nM);
+    o_sc = B.add(sc); o_B = B.add(Bt); o_cw = B.add(cw); o_nM = B.add(nM);
   };
-  size_t o_s1, o_T1, o_n1, o_s2, o_T2, o_n2;
-  region(np1, b->C1, o_s1, o_T1, o_n1);
-  region(np2, b->C2, o_s2, o_T2, o_n2);
+  size_t o_s1, o_B1, o_c1, o_n1, o_s2, o_B2, o_c2, o_n2;
+  region(np1, b->C1, b->Pc1, o_s1, o_B1, o_c1, o_n1);
+  region(np2, b->C2, b->Pc2, o_s2, o_B2, o_c2, o_n2);
   HIP_TRY(hipSetDevice(device));
   HIP_TRY(hipMalloc(&b->blob, B.bytes.size()));
   {
@@ -186,10 +257,14 @@ he_status he_big_ctx_create(uint32_t log_n, uint32_t logQ, int device, he_big_ct
       return fail(HE_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
     }
   }
-  b->crt_c = (const u32*)(b->blob + o_cc);
-  b->pinv = (const double*)(b->blob + o_pinv);
-  b->iscale1 = (const u64*)(b->blob + o_s1); b->T1 = (const u32*)(b->blob + o_T1); b->negM1 = (const u32*)(b->blob + o_n1);
-  b->iscale2 = (const u64*)(b->blob + o_s2); b->T2 = (const u32*)(b->blob + o_T2); b->negM2 = (const u32*)(b->blob + o_n2);
+  uint8_t* d = b->blob;
+  b->crtB = (const u64*)(d + o_crtB);
+  b->adj_ct = (const u64*)(d + o_adj_ct); b->adj_evk = (const u64*)(d + o_adj_evk);
+  b->pinv = (const double*)(d + o_pinv);
+  b->iscale1 = (const u64*)(d + o_s1); b->B1 = (const u64*)(d + o_B1);
+  b->CW1 = (const long long*)(d + o_c1); b->negM1 = (const u32*)(d + o_n1);
+  b->iscale2 = (const u64*)(d + o_s2); b->B2 = (const u64*)(d + o_B2);
+  b->CW2 = (const long long*)(d + o_c2); b->negM2 = (const u32*)(d + o_n2);
   *out = b.release();
   return HE_OK;
 }
@@ -224,12 +299,13 @@ he_status he_big_evk_prepare(he_big_ctx* b, const uint64_t* d_evk, uint64_t* d_e
   hipStream_t st = (hipStream_t)stream;
   const u64 N = b->N;
   big::CrtArgs a{};
-  for (int u = 0; u < 2; ++u) a.job[u] = {d_evk + (u64)u * b->W2 * N, nullptr, d_evk_ntt + (u64)u * b->np2 * N};
-  a.mods = b->ntt->mods; a.cc = b->crt_c; a.np = b->np2; a.W = b->W2; a.bits = 2 * b->logQ;
-  a.nd = (2 * b->logQ + big::DIG - 1) / big::DIG; a.ndmax = b->ndmax; a.log_n = b->log_n;
-  const u32 ngrp = (b->np2 + big::CRT_PG - 1) / big::CRT_PG;
-  hipLaunchKernelGGL((big::k_big_crt<2 * big::WMAX>), dim3((u32)(N / big::CRT_THREADS) * ngrp, 2),
-                     dim3(big::CRT_THREADS), 0, st, a);
+  for (int u = 0; u < 2; ++u) {
+    a.src[u] = d_evk + (u64)u * b->W2 * N;
+    a.dst[u] = d_evk_ntt + (u64)u * b->np2 * N;
+  }
+  a.mods = b->ntt->mods; a.B = b->crtB; a.adj = b->adj_evk; a.np = b->np2; a.W = b->W2;
+  a.kb = b->kb_evk; a.kbmax = b->kb_evk; a.log_n = b->log_n;
+  crt_launch(a, 2, st);
   ntt_launch(b->ntt, true, d_evk_ntt, d_evk_ntt, N, N, b->np2 * N, b->np2 * N, b->ntt->iota, nullptr, b->np2, 2,
              st);
   HIP_TRY(hipGetLastError());
@@ -253,56 +329,42 @@ he_status he_big_mul(he_big_ctx* b, uint32_t logq, const uint64_t* d_ct1, const 
   hipStream_t st = (hipStream_t)stream;
   he_ctx* nc = b->ntt;
   const u32 np1 = b->np1, np2 = b->np2;
-  u64* R1 = (u64*)ws;                  // [6][np1][N]
-  u64* B1 = R1 + 6ull * np1 * N;       // [3][W][N]: axbx, axax, bxbx
+  u64* R1 = (u64*)ws;                  // [4][np1][N]: ax1, ax2, bx1, bx2 -> axbx, axax, bxbx
+  u64* B1 = R1 + 4ull * np1 * N;       // [3][W][N]: axbx, axax, bxbx
   u64* R2 = B1 + 3ull * W * N;         // [2][np2][N]
   u64* KS = R2 + 2ull * np2 * N;       // [2][W][N]: ks_b, ks_a
   const u64 L1 = (u64)np1 * N, L2 = (u64)np2 * N, WN = W * N;
   const u64 *bx1 = d_ct1, *ax1 = d_ct1 + WN, *bx2 = d_ct2, *ax2 = d_ct2 + WN;
-  const u32 nd = (logq + big::DIG - 1) / big::DIG;
   const double cN = (double)N;
-  auto crt = [&](u32 njobs, u32 np, const big::CrtArgs& a) {
-    const u32 ngrp = (np + big::CRT_PG - 1) / big::CRT_PG;
-    timed(nc, "big_crt", cN * njobs * np * nd, cN * njobs * (W + (u64)np) * 8, st, [&] {
-      hipLaunchKernelGGL((big::k_big_crt<big::WMAX>), dim3((u32)(N / big::CRT_THREADS) * ngrp, njobs),
-                         dim3(big::CRT_THREADS), 0, st, a);
-    });
-  };
-  auto pointwise = [&](const big::MulArgs& a) {
-    timed(nc, "big_pointwise", cN * a.np * a.nk, cN * a.np * a.nk * 24, st, [&] {
-      hipLaunchKernelGGL(big::k_big_mul, dim3((u32)((u64)a.np * N / 256)), dim3(256), 0, st, a);
-    });
+  auto crt = [&](u32 njobs, const big::CrtArgs& a) {
+    timed(nc, "big_crt", cN * njobs * a.np * 8 * 32 * a.kb, cN * njobs * (W + (u64)a.np) * 8, st,
+          [&] { crt_launch(a, njobs, st); });
   };
   auto icrt = [&](u32 njobs, const big::IcrtArgs& a) {
-    timed(nc, "big_icrt", cN * njobs * a.np * a.C * 2, cN * njobs * ((u64)a.np + W) * 8, st,
+    timed(nc, "big_icrt", cN * njobs * 32 * a.kb * 16 * ((a.C + 3) / 4), cN * njobs * ((u64)a.np + W) * 8, st,
           [&] { icrt_launch(a, njobs, st); });
   };
-  // region 1: CRT of ax1+bx1, ax2+bx2, ax1, ax2, bx1, bx2
+  // region 1: CRT of ax1, ax2, bx1, bx2
   {
     big::CrtArgs a{};
-    a.job[0] = {ax1, bx1, R1};
-    a.job[1] = {ax2, bx2, R1 + L1};
-    a.job[2] = {ax1, nullptr, R1 + 2 * L1};
-    a.job[3] = {ax2, nullptr, R1 + 3 * L1};
-    a.job[4] = {bx1, nullptr, R1 + 4 * L1};
-    a.job[5] = {bx2, nullptr, R1 + 5 * L1};
-    a.mods = nc->mods; a.cc = b->crt_c; a.np = np1; a.W = (u32)W; a.bits = logq; a.nd = nd; a.ndmax = b->ndmax;
-    a.log_n = b->log_n;
-    crt(6, np1, a);
+    const u64* srcs[4] = {ax1, ax2, bx1, bx2};
+    for (int u = 0; u < 4; ++u) {
+      a.src[u] = srcs[u];
+      a.dst[u] = R1 + u * L1;
+    }
+    a.mods = nc->mods; a.B = b->crtB; a.adj = b->adj_ct; a.np = np1; a.W = (u32)W; a.kb = b->kb_ct;
+    a.kbmax = b->kb_evk; a.log_n = b->log_n;
+    crt(4, a);
   }
-  ntt_launch(nc, true, R1, R1, N, N, L1, L1, nc->iota, nullptr, np1, 6, st);
-  {
-    big::MulArgs a{};
-    a.x[0] = R1; a.y[0] = R1 + L1; a.out[0] = R1;                  // axbx
-    a.x[1] = R1 + 2 * L1; a.y[1] = R1 + 3 * L1; a.out[1] = R1 + L1;  // axax
-    a.x[2] = R1 + 4 * L1; a.y[2] = R1 + 5 * L1; a.out[2] = R1 + 2 * L1;  // bxbx
-    a.mods = nc->mods; a.np = np1; a.nk = 3; a.log_n = b->log_n;
-    pointwise(a);
-  }
+  ntt_launch(nc, true, R1, R1, N, N, L1, L1, nc->iota, nullptr, np1, 4, st);
+  timed(nc, "big_pointwise", cN * np1 * 3, cN * np1 * 7 * 8, st, [&] {
+    hipLaunchKernelGGL(big::k_big_mul_r1, dim3((u32)(L1 / 256)), dim3(256), 0, st, R1, nc->mods, np1, b->log_n);
+  });
   ntt_launch(nc, false, R1, R1, N, N, L1, L1, nc->iota, b->iscale1, np1, 3, st);
   {
     big::IcrtArgs a{};
-    a.src = R1; a.dst = B1; a.pinv = b->pinv; a.T = b->T1; a.negM = b->negM1; a.np = np1; a.Ct = b->C1;
+    a.src = R1; a.dst = B1; a.pinv = b->pinv; a.B = b->B1; a.CW = b->CW1; a.negM = b->negM1;
+    a.np = np1; a.kb = (np1 + 3) / 4; a.Pc = b->Pc1;
     a.shift = 0; a.round = 0; a.outbits = logq; a.W = (u32)W; a.log_n = b->log_n;
     a.C = std::min(b->C1, (logq + 31) / 32 + 1);
     icrt(3, a);
@@ -310,10 +372,11 @@ he_status he_big_mul(he_big_ctx* b, uint32_t logq, const uint64_t* d_ct1, const 
   // region 2: axax times the evaluation key, shifted right by log Q
   {
     big::CrtArgs a{};
-    a.job[0] = {B1 + WN, nullptr, R2};
-    a.mods = nc->mods; a.cc = b->crt_c; a.np = np2; a.W = (u32)W; a.bits = logq; a.nd = nd; a.ndmax = b->ndmax;
-    a.log_n = b->log_n;
-    crt(1, np2, a);
+    a.src[0] = B1 + WN;
+    a.dst[0] = R2;
+    a.mods = nc->mods; a.B = b->crtB; a.adj = b->adj_ct; a.np = np2; a.W = (u32)W; a.kb = b->kb_ct;
+    a.kbmax = b->kb_evk; a.log_n = b->log_n;
+    crt(1, a);
   }
   ntt_launch(nc, true, R2, R2, N, N, 0, 0, nc->iota, nullptr, np2, 1, st);
   {
@@ -322,12 +385,15 @@ he_status he_big_mul(he_big_ctx* b, uint32_t logq, const uint64_t* d_ct1, const 
     a.x[0] = R2; a.y[0] = d_evk_ntt + L2; a.out[0] = R2 + L2;
     a.x[1] = R2; a.y[1] = d_evk_ntt; a.out[1] = R2;
     a.mods = nc->mods; a.np = np2; a.nk = 2; a.log_n = b->log_n;
-    pointwise(a);
+    timed(nc, "big_pointwise", cN * np2 * 2, cN * np2 * 5 * 8, st, [&] {
+      hipLaunchKernelGGL(big::k_big_mul, dim3((u32)(L2 / 256)), dim3(256), 0, st, a);
+    });
   }
   ntt_launch(nc, false, R2, R2, N, N, L2, L2, nc->iota, b->iscale2, np2, 2, st);
   {
     big::IcrtArgs a{};
-    a.src = R2; a.dst = KS; a.pinv = b->pinv; a.T = b->T2; a.negM = b->negM2; a.np = np2; a.Ct = b->C2;
+    a.src = R2; a.dst = KS; a.pinv = b->pinv; a.B = b->B2; a.CW = b->CW2; a.negM = b->negM2;
+    a.np = np2; a.kb = (np2 + 3) / 4; a.Pc = b->Pc2;
     a.shift = b->logQ; a.round = 1; a.outbits = logq; a.W = (u32)W; a.log_n = b->log_n;
     a.C = std::min(b->C2, (b->logQ + logq + 31) / 32 + 1);
     icrt(2, a);

@@ -31,98 +31,111 @@
 namespace he {
 namespace big {
 
-constexpr int CRT_THREADS = 256, CRT_PG = 8;   // primes per work item
-constexpr int DIG = 28;                        // CRT digit width
-constexpr int DIG_BLOCK = 44;                  // digits summed before a reduction (< 64)
-constexpr int ICRT_THREADS = 64;
+constexpr int MF_THREADS = 256;                // 4 wavefronts of 16 rows (coefficients) each
+constexpr int ICRT_THREADS = MF_THREADS;
 constexpr int FIN_THREADS = 256;
 constexpr int WMAX = 19;                       // words of a ciphertext coefficient (log Q <= 1216)
+constexpr int CRT_KBMAX = 10;                  // 32-byte k-blocks of a CRT input (2 log Q bits)
+constexpr int ICRT_KBMAX = 16;                 // k-blocks of the iCRT (4 primes each, np <= 64)
 
-// One CRT job: src (+ src2, summed modulo 2^bits) -> dst [np][N].
-struct CrtJob {
-  const u64* a;
-  const u64* b;
-  u64* dst;
-};
+typedef int v4i __attribute__((ext_vector_type(4)));
 
+// 16x16 int32 tile += A (16 x 32 int8) * B (32 x 16 int8).  Lane l supplies
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16] as byte j of a
+// 64-bit operand and receives D[4 (l / 16) + j][l % 16] in element j.
+__device__ __forceinline__ v4i mfma_i8(long a, long b, v4i c) {
+  return __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, c, 0, 0, 0);
+}
+
+// Offset binary: the bytes u of a word as signed int8 values u - 128.
+__device__ __forceinline__ long offset_bytes(u64 w) { return (long)(w ^ 0x8080808080808080ull); }
+
+// One CRT job: src [W][N] -> dst [np][N].
 struct CrtArgs {
-  CrtJob job[6];
+  const u64* src[4];
+  u64* dst[4];
   const ModInfo* mods;  // [np]
-  const u32* cc;        // [np][ndmax][2]: 30-bit halves of 2^(28h) mod p_i
-  u32 np, W, bits, nd, ndmax, log_n;
+  const u64* B;         // [8 np2][4 kbmax]: column 8i+b, word kw: bytes j = digit b of [2^(8 (8kw+j))]_{p_i}
+  const u64* adj;       // [np2]: ([128 sum_h c_{i,h}] - [2^80]) mod p_i
+  u32 np, W, kb, kbmax, log_n;
 };
 
-// Words of one coefficient, summed with a second operand modulo 2^bits.
-template <int WM>
-__device__ __forceinline__ void load_words(const CrtArgs& a, const CrtJob& J, u64 n, u64 (&w)[WM + 1]) {
+// x mod p_i as a matrix product (the matrix form of CRT): with x = sum_h u_h
+// 2^(8h) (bytes) and c_{i,h} = [2^(8h)]_{p_i} = sum_b t_{i,h,b} 2^(8b)
+// (balanced signed digits), V_i = sum_b 2^(8b) sum_h u_h t_{i,h,b} = sum_h u_h
+// c_{i,h} == x (mod p_i).  The inner sums are an int8 GEMM on the matrix
+// cores: rows = coefficients, k = bytes h, columns = (prime, digit).  The
+// data enter as offset binary (u_h - 128); the correction 128 sum_h c_{i,h}
+// is the per-prime constant adj.  Items: (job, 64 coefficients); each wave
+// owns 16 coefficients and all the job's primes, two primes per column tile.
+__global__ __launch_bounds__(MF_THREADS) void k_big_crt(CrtArgs a) {
+  __shared__ int zs[MF_THREADS / 64][16][17];
+  const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const u64 N = 1ull << a.log_n;
-  const auto pa = gbl(J.a + n);
+  const u32 job = blockIdx.y;
+  const u64 n0 = (u64)blockIdx.x * (MF_THREADS / 4) + wave * 16;
+  const u32 r = lane & 15, g = lane >> 4;
+  // A fragments: word 4 kb + g of coefficient n0 + r
+  long A[CRT_KBMAX];
+  const auto src = gbl(a.src[job] + n0 + r);
 #pragma unroll
-  for (int k = 0; k < WM; ++k) w[k] = (u32)k < a.W ? pa[(u64)k * N] : 0;
-  w[WM] = 0;
-  if (J.b) {
-    const auto pb = gbl(J.b + n);
-    u64 cy = 0;
-#pragma unroll
-    for (int k = 0; k < WM; ++k) {
-      const u64 y = (u32)k < a.W ? pb[(u64)k * N] : 0;
-      const u64 s = w[k] + y;
-      const u64 c1 = s < y ? 1 : 0;
-      w[k] = s + cy;
-      cy = c1 + (w[k] < cy ? 1 : 0);
-    }
+  for (int kb = 0; kb < CRT_KBMAX; ++kb) {
+    const u32 w = 4 * kb + g;
+    A[kb] = (u32)kb < a.kb ? offset_bytes(w < a.W ? src[(u64)w * N] : 0) : 0;
   }
+  const auto dst = gbl(a.dst[job]);
+  const u32 tiles = (a.np + 1) / 2;
+  for (u32 ct = 0; ct < tiles; ++ct) {
+    v4i acc = {0, 0, 0, 0};
+    const u64* Bc = a.B + (u64)(16 * ct + r) * 4 * a.kbmax + g;
 #pragma unroll
-  for (int k = 0; k < WM; ++k) {  // mod 2^bits
-    const int lo = 64 * k;
-    if (lo >= (int)a.bits) w[k] = 0;
-    else if (lo + 64 > (int)a.bits) w[k] &= (1ull << (a.bits - lo)) - 1;
+    for (int kb = 0; kb < CRT_KBMAX; ++kb)
+      if ((u32)kb < a.kb) acc = mfma_i8(A[kb], (long)Bc[4 * kb], acc);
+    // D rows 4g + j, column r = (prime 2 ct + r / 8, digit r % 8)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) zs[wave][4 * g + j][r] = acc[j];
+    lds_wave_sync();
+    // lanes (row = lane % 16, prime 2 ct + lane / 16) for lane < 32
+    const u32 i = 2 * ct + (lane >> 4);
+    if (lane < 32 && i < a.np) {
+      const int* z = &zs[wave][r][8 * (lane >> 4)];
+      // V = sum_b 2^(8b) z_b, |V| < 2^79; U = V + 2^80 > 0
+      long long lo = 0, hi = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) lo += (long long)z[b] << (8 * b);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) hi += (long long)z[4 + b] << (8 * b);
+      // U = lo + hi 2^32 + 2^80 as an unsigned 128-bit value
+      typedef __int128 i128;
+      const i128 v = (i128)lo + ((i128)hi << 32) + ((i128)1 << 80);
+      U128 u;
+      u.lo = (u64)v;
+      u.hi = (u64)(v >> 64);
+      const ModInfo m = ldc(a.mods + i);
+      dst[(u64)i * N + n0 + r] = addmod(reduce128(u, m), ldc(a.adj + i), m.q);
+    }
+    lds_wave_sync();
   }
 }
 
-// Items: (job, coefficient chunk, prime group), prime group fastest so the
-// groups of a chunk read its words while they are in L2.
-template <int WM>
-__global__ __launch_bounds__(CRT_THREADS) void k_big_crt(CrtArgs a) {
-  constexpr int ND = (64 * WM + DIG - 1) / DIG;
-  const u32 ngrp = (a.np + CRT_PG - 1) / CRT_PG;
-  const u32 grp = blockIdx.x % ngrp, chunk = blockIdx.x / ngrp;
-  const CrtJob J = a.job[blockIdx.y];
-  const u64 n = (u64)chunk * CRT_THREADS + threadIdx.x;
-  const u64 N = 1ull << a.log_n;
-  u64 w[WM + 1];
-  load_words<WM>(a, J, n, w);
-  u32 d[ND];
-#pragma unroll
-  for (int h = 0; h < ND; ++h) {
-    const int bit = DIG * h, j = bit >> 6, off = bit & 63;
-    u64 v = w[j] >> off;
-    if (off + DIG > 64) v |= w[j + 1] << (64 - off);
-    d[h] = (u32)v & ((1u << DIG) - 1);
-  }
-  const u32 i0 = grp * CRT_PG, i1 = min(a.np, i0 + CRT_PG);
-  for (u32 i = i0; i < i1; ++i) {
-    const ModInfo m = ldc(a.mods + i);
-    const u32* C = a.cc + (u64)i * a.ndmax * 2;
-    u64 r = 0;
-#pragma unroll
-    for (int h0 = 0; h0 < ND; h0 += DIG_BLOCK) {
-      u64 s0 = 0, s1 = 0;
-#pragma unroll
-      for (int h = h0; h < h0 + DIG_BLOCK && h < ND; ++h) {
-        const bool use = (u32)h < a.nd;
-        const u32 c0 = use ? ldc(C + 2 * h) : 0u, c1 = use ? ldc(C + 2 * h + 1) : 0u;
-        s0 += (u64)d[h] * c0;
-        s1 += (u64)d[h] * c1;
-      }
-      // s0 + s1 2^30 as a 128-bit value
-      U128 v;
-      v.lo = s0 + (s1 << 30);
-      v.hi = (s1 >> 34) + (v.lo < s0 ? 1 : 0);
-      r = addmod(r, reduce128(v, m), m.q);
-    }
-    gbl(J.dst)[(u64)i * N + n] = r;
-  }
+// Region 1's products in NTT form from the four operand transforms
+// t = (ax1, ax2, bx1, bx2) [4][np][N]: slot 0 <- (ax1+bx1)(ax2+bx2),
+// slot 1 <- ax1 ax2, slot 2 <- bx1 bx2 (each element read before written).
+// The Karatsuba sums are taken in RNS, without the reduction mod q: the
+// product differs from HEAAN's by a multiple of q, and the result is taken
+// mod q (the region-1 primes cover the doubled operands).
+__global__ __launch_bounds__(256) void k_big_mul_r1(u64* t, const ModInfo* mods, u32 np, u32 log_n) {
+  const u64 N = 1ull << log_n;
+  const u64 e = (u64)blockIdx.x * 256 + threadIdx.x;
+  const u32 i = (u32)(e >> log_n);
+  if (i >= np) return;
+  const ModInfo m = ldc(mods + uniform(i));
+  const u64 L = (u64)np * N, off = e;
+  const auto p = gbl(t);
+  const u64 a1 = p[off], a2 = p[L + off], b1 = p[2 * L + off], b2 = p[3 * L + off];
+  p[off] = mulmod(addmod(a1, b1, m.q), addmod(a2, b2, m.q), m);
+  p[L + off] = mulmod(a1, a2, m);
+  p[2 * L + off] = mulmod(b1, b2, m);
 }
 
 // out_k[i] = x_k[i] * y_k[i] mod p_i for k < nk, i < np.
@@ -147,91 +160,103 @@ __global__ __launch_bounds__(256) void k_big_mul(MulArgs a) {
   }
 }
 
-constexpr int ICRT_NPMAX = 64, ICRT_CT = 8;  // primes; columns per tile
-
 struct IcrtArgs {
-  const u64* src;       // [njobs][np][N], y_i (canonical)
-  u64* dst;             // [njobs][W][N] words
-  const double* pinv;   // [np] fl(1/p_i)
-  const u32* T;         // [np][Ct + 1 + ICRT_CT]: 0, words 0 .. Ct-1 of (M/p_i) mod 2^(32 Ct), zeros
-  const u32* negM;      // [Ct]: words of -M mod 2^(32 Ct)
-  u32 np, Ct, C, shift, round, outbits, W, log_n;
+  const u64* src;        // [njobs][np][N], y_i (canonical)
+  u64* dst;              // [njobs][W][N] words
+  const double* pinv;    // [np] fl(1/p_i)
+  const u64* B;          // [64][Pc]: byte j = digit P - j of (M/p_i) mod 2^(32 Ct) (balanced, zero outside)
+  const long long* CW;   // [Ct]: offset correction of word column m, sum_b 128 colsum[4m+b] 2^(8b)
+  const u32* negM;       // [Ct]: words of -M mod 2^(32 Ct)
+  u32 np, kb, Pc, C, shift, round, outbits, W, log_n;
 };
 
-__global__ __launch_bounds__(ICRT_THREADS) void k_big_icrt(IcrtArgs a) {
-  __shared__ u32 ys[2][ICRT_NPMAX][ICRT_THREADS];
+// X = sum_i y_i (M/p_i) - k M modulo 2^(32 C) as a matrix product (the
+// matrix form of iCRT, Algorithm 6): with y_i = sum_a y_{i,a} 2^(8a) and
+// (M/p_i) = sum_b t_{i,b} 2^(8b), byte column P of the product is
+// Z_P = sum_{i,a} y_{i,a} t_{i,P-a}, an int8 GEMM on the matrix cores with
+// k = (prime, byte of y) and a Toeplitz B.  The data enter as offset binary
+// (the correction is CW); the byte columns are folded four at a time into
+// 32-bit words and carried serially per coefficient.  The output is the bit
+// field [shift, shift + outbits) of X with optional round-half-up at bit
+// shift - 1.  Items: (job, 64 coefficients), 16 per wave; the B tile of a
+// column tile is staged in LDS for the workgroup.
+__global__ __launch_bounds__(MF_THREADS) void k_big_icrt(IcrtArgs a) {
+  __shared__ u64 bs[64][16];
+  __shared__ int zs[MF_THREADS / 64][16][17];
+  const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const u64 N = 1ull << a.log_n;
-  const u32 tid = threadIdx.x;
-  const u64 n = (u64)blockIdx.x * ICRT_THREADS + tid;
   const u32 job = blockIdx.y;
-  const auto src = gbl(a.src + (u64)job * a.np * N + n);
+  const u64 n0 = (u64)blockIdx.x * (MF_THREADS / 4) + wave * 16;
+  const u32 r = lane & 15, g = lane >> 4;
+  const auto src = gbl(a.src + (u64)job * a.np * N + n0 + r);
+  long A[ICRT_KBMAX];
   double s = 0.0;
-  for (u32 i = 0; i < a.np; ++i) {
-    const u64 y = src[(u64)i * N];
-    ys[0][i][tid] = (u32)y;
-    ys[1][i][tid] = (u32)(y >> 32);
-    s += (double)y * ldc(a.pinv + i);
+#pragma unroll
+  for (int kb = 0; kb < ICRT_KBMAX; ++kb) {
+    const u32 i = 4 * kb + g;
+    const u64 y = ((u32)kb < a.kb && i < a.np) ? src[(u64)i * N] : 0;
+    if (i < a.np) s += (double)y * ldc(a.pinv + i);
+    A[kb] = offset_bytes(y);
   }
+  // sum_i y_i / p_i over the four lane groups of this row
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
   // sum y_i / p_i = k + X / M with |X| / M < 1/4: round to nearest
-  const u32 k = (u32)__double2int_rn(s);
-  const auto out = reinterpret_cast<gptr<u32>>(gbl(a.dst + (u64)job * a.W * N + n));
+  const long long k = __double2int_rn(s);
+  const auto out = reinterpret_cast<gptr<u32>>(gbl(a.dst + (u64)job * a.W * N + n0 + r));
   const u32 cs = a.shift >> 5, sh = a.shift & 31;
   const u32 ocols = (a.outbits + 31) >> 5;
-  const u32 rcol = a.round ? (a.shift - 1) >> 5 : ~0u, rbit = (a.shift - 1) & 31;
-  // output column m of 32 bits -> word m/2, half m%2 (little-endian halves)
+  const u32 rcol = a.round ? (a.shift - 1) >> 5 : ~0u;
+  const long long rval = a.round ? 1ll << ((a.shift - 1) & 31) : 0;
+  const bool owner = lane < 16;  // lane r carries row r
   const auto emit = [&](u32 m, u32 v) {
     if (m >= ocols) return;
     if (m == ocols - 1 && (a.outbits & 31)) v &= (1u << (a.outbits & 31)) - 1;
     out[((u64)(m >> 1) * N) * 2 + (m & 1)] = v;
   };
-  for (u32 m = ocols; m < 2 * a.W; ++m) out[((u64)(m >> 1) * N) * 2 + (m & 1)] = 0;
-  // Columns c0 .. c0+CT-1 of X: S_j = sum_i y_i.lo T_i[c] + y_i.hi T_i[c-1],
-  // 64-bit sums with a count of their carries.  Only this thread's LDS
-  // entries are read, so no barrier is needed.
-  u64 cy = 0;  // carry into the next column (< 2^40)
+  if (owner)
+    for (u32 m = ocols; m < 2 * a.W; ++m) out[((u64)(m >> 1) * N) * 2 + (m & 1)] = 0;
+  long long cy = 0;
   u32 prev = 0;
-  const u32 row = a.Ct + 1 + ICRT_CT;  // a tile's last reads stay inside the row
-  for (u32 c0 = 0; c0 < a.C; c0 += ICRT_CT) {
-    u64 S[ICRT_CT];
-    u32 Sh[ICRT_CT];
+  const u32 tiles = (a.C + 3) / 4;
+  for (u32 ct = 0; ct < tiles; ++ct) {
+    lds_barrier();  // the previous tile's B reads are done
 #pragma unroll
-    for (int j = 0; j < ICRT_CT; ++j) S[j] = 0, Sh[j] = 0;
-    for (u32 i = 0; i < a.np; ++i) {
-      const u32 y0 = ys[0][i][tid], y1 = ys[1][i][tid];
-      const u32* Ti = a.T + (u64)i * row + c0;  // Ti[j] = word c0 + j - 1
-      u32 t[ICRT_CT + 1];
+    for (int e = 0; e < 4; ++e) {
+      const u32 idx = threadIdx.x + e * MF_THREADS;  // 1024 entries: i = idx / 16, column idx % 16
+      bs[idx >> 4][idx & 15] = a.B[(u64)(idx >> 4) * a.Pc + 16 * ct + (idx & 15)];
+    }
+    lds_barrier();
+    v4i acc = {0, 0, 0, 0};
 #pragma unroll
-      for (int j = 0; j <= ICRT_CT; ++j) t[j] = ldc(Ti + j);
+    for (int kb = 0; kb < ICRT_KBMAX; ++kb)
+      if ((u32)kb < a.kb) acc = mfma_i8(A[kb], (long)bs[4 * kb + g][r], acc);
 #pragma unroll
-      for (int j = 0; j < ICRT_CT; ++j) {
-        u64 p = (u64)y0 * t[j + 1];
-        S[j] += p;
-        Sh[j] += S[j] < p ? 1u : 0u;
-        p = (u64)y1 * t[j];
-        S[j] += p;
-        Sh[j] += S[j] < p ? 1u : 0u;
+    for (int j = 0; j < 4; ++j) zs[wave][4 * g + j][r] = acc[j];
+    lds_wave_sync();
+    if (owner) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u32 m = 4 * ct + q;  // 32-bit word column
+        if (m >= a.C) break;
+        const int* z = &zs[wave][r][4 * q];
+        long long w = (long long)z[0] + ((long long)z[1] << 8) + ((long long)z[2] << 16) +
+                      ((long long)z[3] << 24);
+        w += ldc(a.CW + m) + k * (long long)ldc(a.negM + m) + cy;
+        if (m == rcol) w += rval;
+        const u32 col = (u32)w;
+        cy = w >> 32;  // arithmetic: the carry may be negative
+        if (sh == 0) {
+          if (m >= cs) emit(m - cs, col);
+        } else if (m >= cs + 1) {
+          emit(m - cs - 1, (prev >> sh) | (col << (32 - sh)));
+        }
+        prev = col;
       }
     }
-#pragma unroll
-    for (int j = 0; j < ICRT_CT; ++j) {
-      const u32 c = c0 + j;
-      if (c >= a.C) break;
-      u64 p = (u64)k * ldc(a.negM + c);
-      if (c == rcol) p += 1ull << rbit;
-      p += cy;
-      S[j] += p;
-      Sh[j] += S[j] < p ? 1u : 0u;
-      const u32 col = (u32)S[j];
-      cy = (S[j] >> 32) | ((u64)Sh[j] << 32);
-      if (sh == 0) {
-        if (c >= cs) emit(c - cs, col);
-      } else if (c >= cs + 1) {
-        emit(c - cs - 1, (prev >> sh) | (col << (32 - sh)));
-      }
-      prev = col;
-    }
+    lds_wave_sync();
   }
-  if (sh && a.C >= cs + 1) emit(a.C - cs - 1, prev >> sh);
+  if (owner && sh && a.C >= cs + 1) emit(a.C - cs - 1, prev >> sh);
 }
 
 // c3 = (ks_b + bxbx, ks_a + axbx - axax - bxbx) mod 2^logq, then optionally
