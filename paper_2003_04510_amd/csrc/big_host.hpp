@@ -14,7 +14,8 @@ struct he_big_ctx {
   int device = 0;
   std::vector<u64> primes;
   uint8_t* blob = nullptr;
-  const u64* crtB = nullptr;       // [8 (np2 + 1)][4 kb_evk]: CRT matrix (balanced digits)
+  const u64* crtB = nullptr;       // [4 kb_evk][crt_cols]: CRT matrix (balanced digits)
+  u32 crt_cols = 0;                // 32 ceil(np2 / 4): whole four-prime steps
   const u64 *adj_ct = nullptr, *adj_evk = nullptr;  // [np2]: offset corrections of the CRT
   const u64* iscale1 = nullptr;    // [np1][2]: N^-1 [(M1/p_i)^-1]_{p_i}, Shoup pairs
   const u64* iscale2 = nullptr;    // [np2][2]
@@ -176,9 +177,11 @@ he_status he_big_ctx_create(uint32_t log_n, uint32_t logQ, int device, he_big_ct
   const u64 N = b->N;
   Blob B;
   // CRT matrix: column 8i + b, k = byte h: digit b of c_{i,h} = [2^(8h)]_{p_i}
-  // (balanced); 8 (np2 + 1) columns so a last half tile stays in the table.
+  // (balanced), stored word-major [kw][column] so 16 lanes read 128
+  // contiguous bytes; whole steps of four primes (zero columns past np2).
   const u32 KW = 4 * b->kb_evk, KP = 8 * KW;
-  std::vector<u64> crtB((size_t)8 * (np2 + 1) * KW, 0);
+  b->crt_cols = 32 * ((np2 + 3) / 4);
+  std::vector<u64> crtB((size_t)KW * b->crt_cols, 0);
   std::vector<u64> adj_ct(np2), adj_evk(np2);
   for (u32 i = 0; i < np2; ++i) {
     const u64 p = pr[i];
@@ -196,7 +199,7 @@ he_status he_big_ctx_create(uint32_t log_n, uint32_t logQ, int device, he_big_ct
       for (u32 kw = 0; kw < KW; ++kw) {
         int d8[8];
         for (int j = 0; j < 8; ++j) d8[j] = dig[8 * kw + j][bd];
-        crtB[((size_t)(8 * i + bd)) * KW + kw] = pack8(d8);
+        crtB[(size_t)kw * b->crt_cols + 8 * i + bd] = pack8(d8);
       }
     const u64 t80 = powmod(2, 80, p);
     adj_ct[i] = submod(mulmod(128 % p, sum_ct, p), t80, p);
@@ -304,7 +307,7 @@ he_status he_big_evk_prepare(he_big_ctx* b, const uint64_t* d_evk, uint64_t* d_e
     a.dst[u] = d_evk_ntt + (u64)u * b->np2 * N;
   }
   a.mods = b->ntt->mods; a.B = b->crtB; a.adj = b->adj_evk; a.np = b->np2; a.W = b->W2;
-  a.kb = b->kb_evk; a.kbmax = b->kb_evk; a.log_n = b->log_n;
+  a.kb = b->kb_evk; a.ncols = b->crt_cols; a.log_n = b->log_n;
   crt_launch(a, 2, st);
   ntt_launch(b->ntt, true, d_evk_ntt, d_evk_ntt, N, N, b->np2 * N, b->np2 * N, b->ntt->iota, nullptr, b->np2, 2,
              st);
@@ -353,7 +356,7 @@ he_status he_big_mul(he_big_ctx* b, uint32_t logq, const uint64_t* d_ct1, const 
       a.dst[u] = R1 + u * L1;
     }
     a.mods = nc->mods; a.B = b->crtB; a.adj = b->adj_ct; a.np = np1; a.W = (u32)W; a.kb = b->kb_ct;
-    a.kbmax = b->kb_evk; a.log_n = b->log_n;
+    a.ncols = b->crt_cols; a.log_n = b->log_n;
     crt(4, a);
   }
   ntt_launch(nc, true, R1, R1, N, N, L1, L1, nc->iota, nullptr, np1, 4, st);
@@ -375,7 +378,7 @@ he_status he_big_mul(he_big_ctx* b, uint32_t logq, const uint64_t* d_ct1, const 
     a.src[0] = B1 + WN;
     a.dst[0] = R2;
     a.mods = nc->mods; a.B = b->crtB; a.adj = b->adj_ct; a.np = np2; a.W = (u32)W; a.kb = b->kb_ct;
-    a.kbmax = b->kb_evk; a.log_n = b->log_n;
+    a.ncols = b->crt_cols; a.log_n = b->log_n;
     crt(1, a);
   }
   ntt_launch(nc, true, R2, R2, N, N, 0, 0, nc->iota, nullptr, np2, 1, st);

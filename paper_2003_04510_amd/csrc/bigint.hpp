@@ -55,9 +55,9 @@ struct CrtArgs {
   const u64* src[4];
   u64* dst[4];
   const ModInfo* mods;  // [np]
-  const u64* B;         // [8 np2][4 kbmax]: column 8i+b, word kw: bytes j = digit b of [2^(8 (8kw+j))]_{p_i}
+  const u64* B;         // [4 kbmax][ncols]: word kw of column 8i+b: bytes j = digit b of [2^(8 (8kw+j))]_{p_i}
   const u64* adj;       // [np2]: ([128 sum_h c_{i,h}] - [2^80]) mod p_i
-  u32 np, W, kb, kbmax, log_n;
+  u32 np, W, kb, ncols, log_n;
 };
 
 // x mod p_i as a matrix product (the matrix form of CRT): with x = sum_h u_h
@@ -67,9 +67,10 @@ struct CrtArgs {
 // cores: rows = coefficients, k = bytes h, columns = (prime, digit).  The
 // data enter as offset binary (u_h - 128); the correction 128 sum_h c_{i,h}
 // is the per-prime constant adj.  Items: (job, 64 coefficients); each wave
-// owns 16 coefficients and all the job's primes, two primes per column tile.
+// owns 16 coefficients and all the job's primes, four primes (two column
+// tiles) per step so that every lane finishes one (coefficient, prime).
 __global__ __launch_bounds__(MF_THREADS) void k_big_crt(CrtArgs a) {
-  __shared__ int zs[MF_THREADS / 64][16][17];
+  __shared__ int zs[MF_THREADS / 64][16][33];
   const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const u64 N = 1ull << a.log_n;
   const u32 job = blockIdx.y;
@@ -84,35 +85,42 @@ __global__ __launch_bounds__(MF_THREADS) void k_big_crt(CrtArgs a) {
     A[kb] = (u32)kb < a.kb ? offset_bytes(w < a.W ? src[(u64)w * N] : 0) : 0;
   }
   const auto dst = gbl(a.dst[job]);
-  const u32 tiles = (a.np + 1) / 2;
-  for (u32 ct = 0; ct < tiles; ++ct) {
-    v4i acc = {0, 0, 0, 0};
-    const u64* Bc = a.B + (u64)(16 * ct + r) * 4 * a.kbmax + g;
+  const auto Bg = gbl(a.B + (u64)g * a.ncols + r);
+  const u32 steps = (a.np + 3) / 4;
+  for (u32 cp = 0; cp < steps; ++cp) {
+    v4i acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    const u32 c0 = 32 * cp;
 #pragma unroll
     for (int kb = 0; kb < CRT_KBMAX; ++kb)
-      if ((u32)kb < a.kb) acc = mfma_i8(A[kb], (long)Bc[4 * kb], acc);
-    // D rows 4g + j, column r = (prime 2 ct + r / 8, digit r % 8)
+      if ((u32)kb < a.kb) {
+        const u64 off = (u64)(4 * kb) * a.ncols + c0;
+        acc0 = mfma_i8(A[kb], (long)Bg[off], acc0);
+        acc1 = mfma_i8(A[kb], (long)Bg[off + 16], acc1);
+      }
+    // D rows 4g + j; columns c0 + r (acc0) and c0 + 16 + r (acc1)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) zs[wave][4 * g + j][r] = acc[j];
+    for (int j = 0; j < 4; ++j) {
+      zs[wave][4 * g + j][r] = acc0[j];
+      zs[wave][4 * g + j][16 + r] = acc1[j];
+    }
     lds_wave_sync();
-    // lanes (row = lane % 16, prime 2 ct + lane / 16) for lane < 32
-    const u32 i = 2 * ct + (lane >> 4);
-    if (lane < 32 && i < a.np) {
-      const int* z = &zs[wave][r][8 * (lane >> 4)];
+    // lane: coefficient r, prime 4 cp + g (digits at columns 8 g .. 8 g + 7)
+    const u32 i = 4 * cp + g;
+    if (i < a.np) {
+      const int* z = &zs[wave][r][8 * g];
       // V = sum_b 2^(8b) z_b, |V| < 2^79; U = V + 2^80 > 0
       long long lo = 0, hi = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) lo += (long long)z[b] << (8 * b);
 #pragma unroll
       for (int b = 0; b < 4; ++b) hi += (long long)z[4 + b] << (8 * b);
-      // U = lo + hi 2^32 + 2^80 as an unsigned 128-bit value
       typedef __int128 i128;
       const i128 v = (i128)lo + ((i128)hi << 32) + ((i128)1 << 80);
       U128 u;
       u.lo = (u64)v;
       u.hi = (u64)(v >> 64);
-      const ModInfo m = ldc(a.mods + i);
-      dst[(u64)i * N + n0 + r] = addmod(reduce128(u, m), ldc(a.adj + i), m.q);
+      const ModInfo m = a.mods[i];
+      dst[(u64)i * N + n0 + r] = addmod(reduce128(u, m), a.adj[i], m.q);
     }
     lds_wave_sync();
   }
@@ -181,13 +189,31 @@ struct IcrtArgs {
 // shift - 1.  Items: (job, 64 coefficients), 16 per wave; the B tile of a
 // column tile is staged in LDS for the workgroup.
 __global__ __launch_bounds__(MF_THREADS) void k_big_icrt(IcrtArgs a) {
-  __shared__ u64 bs[64][16];
+  __shared__ u64 bs[2][64][16];
   __shared__ int zs[MF_THREADS / 64][16][17];
   const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const u64 N = 1ull << a.log_n;
   const u32 job = blockIdx.y;
   const u64 n0 = (u64)blockIdx.x * (MF_THREADS / 4) + wave * 16;
   const u32 r = lane & 15, g = lane >> 4;
+  const u32 tiles = (a.C + 3) / 4;
+  // B tile ct: 1024 fragments, entry e = i * 16 + column
+  u64 pf[4];
+  const auto fetch = [&](u32 ct) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const u32 idx = threadIdx.x + e * MF_THREADS;
+      pf[e] = a.B[(u64)(idx >> 4) * a.Pc + 16 * ct + (idx & 15)];
+    }
+  };
+  const auto stage = [&](u32 buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const u32 idx = threadIdx.x + e * MF_THREADS;
+      bs[buf][idx >> 4][idx & 15] = pf[e];
+    }
+  };
+  fetch(0);
   const auto src = gbl(a.src + (u64)job * a.np * N + n0 + r);
   long A[ICRT_KBMAX];
   double s = 0.0;
@@ -198,6 +224,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_big_icrt(IcrtArgs a) {
     if (i < a.np) s += (double)y * ldc(a.pinv + i);
     A[kb] = offset_bytes(y);
   }
+  stage(0);
   // sum_i y_i / p_i over the four lane groups of this row
   s += __shfl_xor(s, 16);
   s += __shfl_xor(s, 32);
@@ -218,21 +245,18 @@ __global__ __launch_bounds__(MF_THREADS) void k_big_icrt(IcrtArgs a) {
     for (u32 m = ocols; m < 2 * a.W; ++m) out[((u64)(m >> 1) * N) * 2 + (m & 1)] = 0;
   long long cy = 0;
   u32 prev = 0;
-  const u32 tiles = (a.C + 3) / 4;
+  lds_barrier();
   for (u32 ct = 0; ct < tiles; ++ct) {
-    lds_barrier();  // the previous tile's B reads are done
+    const u32 buf = ct & 1;
+    if (ct + 1 < tiles) fetch(ct + 1);  // in flight during this tile
+    v4i acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const u32 idx = threadIdx.x + e * MF_THREADS;  // 1024 entries: i = idx / 16, column idx % 16
-      bs[idx >> 4][idx & 15] = a.B[(u64)(idx >> 4) * a.Pc + 16 * ct + (idx & 15)];
+    for (int kb = 0; kb < ICRT_KBMAX; kb += 2) {
+      if ((u32)kb < a.kb) acc0 = mfma_i8(A[kb], (long)bs[buf][4 * kb + g][r], acc0);
+      if ((u32)kb + 1 < a.kb) acc1 = mfma_i8(A[kb + 1], (long)bs[buf][4 * kb + 4 + g][r], acc1);
     }
-    lds_barrier();
-    v4i acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int kb = 0; kb < ICRT_KBMAX; ++kb)
-      if ((u32)kb < a.kb) acc = mfma_i8(A[kb], (long)bs[4 * kb + g][r], acc);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) zs[wave][4 * g + j][r] = acc[j];
+    for (int j = 0; j < 4; ++j) zs[wave][4 * g + j][r] = acc0[j] + acc1[j];
     lds_wave_sync();
     if (owner) {
 #pragma unroll
@@ -255,6 +279,9 @@ __global__ __launch_bounds__(MF_THREADS) void k_big_icrt(IcrtArgs a) {
       }
     }
     lds_wave_sync();
+    // buffer buf ^ 1 was last read in tile ct - 1, before the previous barrier
+    if (ct + 1 < tiles) stage(buf ^ 1);
+    lds_barrier();
   }
   if (owner && sh && a.C >= cs + 1) emit(a.C - cs - 1, prev >> sh);
 }
