@@ -100,6 +100,20 @@ he_status he_encrypt(he_ctx* ctx, uint32_t level, const int64_t* m, const int64_
                      const int64_t* e0, const int64_t* e1, const uint64_t* d_pk, uint64_t* d_ct,
                      void* ws, size_t ws_bytes, he_stream stream);
 
+/* Encoding (Sec. III-A): n <= N/2 complex slots d_z [n][2] (re, im
+ * doubles, device) times `scale`, placed at the roots zeta^(5^j) of
+ * X^N + 1 (zeta = exp(i pi / N)) with their conjugates, to the integer
+ * coefficients d_m [N] (int64, device) of the polynomial taking those
+ * values, each rounded to nearest (ties to even); slots j >= n are zero.
+ * ws: 16 N bytes (HE_ENOMEM if smaller).  Enqueued on `stream`. */
+he_status he_encode(he_ctx* ctx, const double* d_z, uint32_t n, double scale, int64_t* d_m, void* ws,
+                    size_t ws_bytes, he_stream stream);
+
+/* HE Add (Sec. III-B): d_out = d_ct1 + d_ct2 limb by limb, all
+ * [2][level][N] (d_out may alias an input).  Enqueued on `stream`. */
+he_status he_add(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint64_t* d_ct2, uint64_t* d_out,
+                 he_stream stream);
+
 /* Decryption to RNS coefficients (Sec. III-A: t = bx - ax*sk): writes
  * d_m [level][N], coefficient form, limb i modulo q_i.  s: host [N]. */
 he_status he_decrypt(he_ctx* ctx, uint32_t level, const uint64_t* d_ct, const int64_t* s,

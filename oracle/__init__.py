@@ -238,6 +238,12 @@ class Context:
                           _u(_c(pk)), _u(ct))
         return ct
 
+    def he_add(self, level, ct1, ct2):
+        """HE Add (Sec. III-B): (c1 + c2) mod q_i limb by limb, [2][level][N]."""
+        q = np.array(self.q[:level], dtype=np.uint64).reshape(1, level, 1)
+        s = np.asarray(ct1, dtype=np.uint64) + np.asarray(ct2, dtype=np.uint64)
+        return np.where(s >= q, s - q, s)
+
     def decrypt_limbs(self, level, ct, s):
         m = np.zeros((level, self.N), dtype=np.uint64)
         lib().orc_decrypt_limbs(self._h, level, _u(_c(ct)), _i(_ci(s)), _u(m))
@@ -293,8 +299,9 @@ def slot_exponents(N: int) -> np.ndarray:
     return e
 
 
-def encode(z: np.ndarray, scale: float, N: int) -> np.ndarray:
-    """Coefficients m with m(zeta^{5^j}) ~ scale*z_j, rounded to nearest: int64 [N].
+def encode(z: np.ndarray, scale: float, N: int, rounded: bool = True) -> np.ndarray:
+    """Coefficients m with m(zeta^{5^j}) ~ scale*z_j, rounded to nearest: int64 [N]
+    (float64 before the rounding when rounded is False).
 
     m_k = (2/N) Re sum_j scale z_j zeta^{-5^j k} written as one length-N FFT
     over the odd powers of zeta (all N of them, conjugates included)."""
@@ -309,7 +316,7 @@ def encode(z: np.ndarray, scale: float, N: int) -> np.ndarray:
     k = np.arange(N)
     x = np.fft.fft(V) / N                       # = m_k zeta^k
     m = np.real(x * np.exp(-1j * np.pi * k / N))
-    return np.rint(m).astype(np.int64)
+    return np.rint(m).astype(np.int64) if rounded else m
 
 
 def decode(coeffs, scale: float, slots=None) -> np.ndarray:

@@ -104,6 +104,8 @@ def load_library():
     L.he_big_mul.argtypes = [vp, u32, vp, vp, vp, vp, u32, vp, ctypes.c_size_t, vp]
     L.he_big_timing_enable.argtypes = [vp, ctypes.c_int]
     L.he_big_timing_read.argtypes = [vp, ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
+    L.he_encode.argtypes = [vp, vp, u32, ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
+    L.he_add.argtypes = [vp, u32, vp, vp, vp, vp]
     L.he_status_str.argtypes = [st]
     L.he_status_str.restype = ctypes.c_char_p
     L.he_last_error.restype = ctypes.c_char_p
@@ -111,7 +113,7 @@ def load_library():
               "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read", "he_batch_create",
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
               "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
-              "he_big_mul", "he_big_timing_enable", "he_big_timing_read"):
+              "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_add"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -256,6 +258,22 @@ class Context:
                                          vp(pk.data_ptr()), vp(ct.data_ptr()), vp(ws.data_ptr()),
                                          ws.numel() * 8, self._stream()), "he_encrypt")
         return ct
+
+    def encode(self, z, scale: float):
+        """Complex slots (numpy, n <= N/2) -> int64 coefficients [N] on the GPU."""
+        zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128)).view(np.float64)
+        zd = self.torch.from_numpy(zz.copy()).to(self.dev)
+        m = self.empty(self.N)
+        ws = self.workspace(1)
+        _check(load_library().he_encode(self._h, vp(zd.data_ptr()), len(zz) // 2, float(scale), vp(m.data_ptr()),
+                                        vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_encode")
+        return m
+
+    def add(self, level, ct1, ct2, out=None):
+        out = self.empty(2, level, self.N) if out is None else out
+        _check(load_library().he_add(self._h, level, vp(ct1.data_ptr()), vp(ct2.data_ptr()), vp(out.data_ptr()),
+                                     self._stream()), "he_add")
+        return out
 
     def decrypt_limbs(self, level, ct, s):
         out = self.empty(level, self.N)

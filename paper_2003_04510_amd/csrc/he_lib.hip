@@ -1361,3 +1361,4 @@ he_status he_decrypt(he_ctx* c, uint32_t level, const uint64_t* d_ct, const int6
 
 }  // extern "C"
 #include "big_host.hpp"
+#include "scheme_host.hpp"

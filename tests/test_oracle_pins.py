@@ -408,3 +408,22 @@ def test_decrypt_of_he_mul_matches_fp64_product_n12():
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     assert rel_pre < 2.0**-20, rel_pre
     assert rel < 2.0**-20, rel
+
+
+def test_he_add_decrypts_to_sum_n12():
+    """HE Add (Sec. III-B) is linear under decryption: the decrypted sum is
+    the sum of the decrypted inputs, exactly, modulo each q_i."""
+    w = synth.CFG_N12
+    ctx = oracle.Context.for_workload(w)
+    level = w.L
+    s, evk, za, zb, (c1, c2) = _fresh_pair(ctx, w, level)
+    c3 = ctx.he_add(level, c1, c2)
+    d1, d2, d3 = (ctx.decrypt_limbs(level, c, s) for c in (c1, c2, c3))
+    for i, q in enumerate(ctx.q[:level]):
+        assert np.array_equal((d1[i].astype(object) + d2[i].astype(object)) % q, d3[i].astype(object))
+    scale = 2.0**w.log_scale
+    assert np.max(np.abs(ctx.decrypt(level, c3, s, scale) - (za + zb))) < 2.0**-19
+    # wrap-around: every residue q-1 plus 1 gives 0
+    ones = np.ones_like(c1)
+    top = np.stack([np.stack([np.full(w.N, q - 1, dtype=np.uint64) for q in ctx.q[:level]])] * 2)
+    assert not ctx.he_add(level, top, ones).any()
