@@ -77,6 +77,9 @@ def lib():
         L.orc_keygen_evk.argtypes = [ctypes.c_void_p, i64p, i64p, u64p, u64p]
         L.orc_encrypt.argtypes = [ctypes.c_void_p, ctypes.c_uint32, i64p, i64p, i64p, i64p, u64p, u64p]
         L.orc_decrypt_limbs.argtypes = [ctypes.c_void_p, ctypes.c_uint32, u64p, i64p, u64p]
+        L.orc_automorphism.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, u64p, u64p]
+        L.orc_keygen_rot.argtypes = [ctypes.c_void_p, i64p, ctypes.c_uint64, i64p, u64p, u64p]
+        L.orc_rotate.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, u64p, u64p, u64p]
         for f in ("orc_counter_ntt", "orc_counter_intt"):
             getattr(L, f).restype = ctypes.c_uint64
         _lib = L
@@ -237,6 +240,26 @@ class Context:
         lib().orc_encrypt(self._h, level, _i(_ci(m_coeffs)), _i(_ci(v)), _i(_ci(e0)), _i(_ci(e1)),
                           _u(_c(pk)), _u(ct))
         return ct
+
+    # -- rotation (automorphism X -> X^g, g = 5^r mod 2N, then key switching)
+    def galois(self, r: int) -> int:
+        """g = 5^r mod 2N: slot j of sigma_g(m) is slot j + r of m."""
+        return pow(5, r % (self.N // 2), 2 * self.N)
+
+    def automorphism(self, level, ct, g):
+        out = np.zeros((2, level, self.N), dtype=np.uint64)
+        lib().orc_automorphism(self._h, level, g, _u(_c(ct)), _u(out))
+        return out
+
+    def keygen_rot(self, s, g, e_rk, a_rk):
+        rk = np.zeros((self.dnum, 2, self.L + self.K, self.N), dtype=np.uint64)
+        lib().orc_keygen_rot(self._h, _i(_ci(s)), g, _i(_ci(e_rk)), _u(_c(a_rk)), _u(rk))
+        return rk
+
+    def rotate(self, level, ct, rk, g):
+        out = np.zeros((2, level, self.N), dtype=np.uint64)
+        lib().orc_rotate(self._h, level, g, _u(_c(ct)), _u(_c(rk)), _u(out))
+        return out
 
     def he_add(self, level, ct1, ct2):
         """HE Add (Sec. III-B): (c1 + c2) mod q_i limb by limb, [2][level][N]."""

@@ -515,3 +515,92 @@ void orc_decrypt_limbs(const orc_ctx* c, uint32_t level, const uint64_t* ct, con
     free(sn);
   }
 }
+
+/* ---------- rotation: automorphism X -> X^g and key switching ---------- */
+/* The automorphism of a polynomial in coefficient form, by its definition:
+ * the term a_k X^k goes to a_k X^(k g mod 2N), negated when k g mod 2N >= N
+ * (X^N = -1).  g odd.  in, out: [N] residues mod m (out != in). */
+static void automorphism_coeff(const uint64_t* in, uint64_t* out, uint64_t N, uint64_t g, uint64_t m) {
+  for (uint64_t k = 0; k < N; ++k) {
+    uint64_t e = (uint64_t)(((u128)k * g) % (2 * N));
+    if (e < N) out[e] = in[k];
+    else out[e - N] = in[k] ? m - in[k] : 0;
+  }
+}
+
+/* sigma_g of a ciphertext [2][level][N] in NTT form: INTT, the automorphism
+ * in coefficient form, NTT. */
+void orc_automorphism(const orc_ctx* c, uint32_t level, uint64_t g, const uint64_t* in, uint64_t* out) {
+  uint64_t N = c->N;
+#pragma omp parallel for schedule(dynamic)
+  for (uint32_t t = 0; t < 2 * level; ++t) {
+    uint32_t i = t % level;
+    uint64_t* tmp = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    memcpy(tmp, in + (uint64_t)t * N, sizeof(uint64_t) * N);
+    orc_intt(c, i, tmp);
+    automorphism_coeff(tmp, out + (uint64_t)t * N, N, g, c->mod[i]);
+    orc_ntt(c, i, out + (uint64_t)t * N);
+    free(tmp);
+  }
+}
+
+/* Rotation key for sigma_g: the evaluation key of the secret -sigma_g(s)
+ * in place of s^2 (b_j = a_j s + e_j - G_j sigma_g(s)), so that key
+ * switching sigma_g(a) gives a pair decrypting, under s, to
+ * -sigma_g(a) sigma_g(s).  Same layout as the evaluation key. */
+void orc_keygen_rot(const orc_ctx* c, const int64_t* s, uint64_t g, const int64_t* e, const uint64_t* a_unif,
+                    uint64_t* rk) {
+  uint64_t N = c->N;
+  uint32_t L = c->L, K = c->K, nm = L + K;
+  int64_t* sg = (int64_t*)malloc(sizeof(int64_t) * N);  /* -sigma_g(s) as a signed polynomial */
+  for (uint64_t k = 0; k < N; ++k) {
+    uint64_t ex = (uint64_t)(((u128)k * g) % (2 * N));
+    if (ex < N) sg[ex] = -s[k];
+    else sg[ex - N] = s[k];
+  }
+#pragma omp parallel for schedule(dynamic)
+  for (uint32_t i = 0; i < nm; ++i) {
+    uint64_t m = c->mod[i];
+    uint64_t Pm = 1 % m;
+    for (uint32_t k = 0; k < K; ++k) Pm = mmul(Pm, c->mod[L + k] % m, m);
+    uint64_t* sn = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    uint64_t* gn = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    uint64_t* en = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    small_to_ntt(c, i, s, sn);
+    small_to_ntt(c, i, sg, gn);
+    for (uint32_t j = 0; j < c->dnum; ++j) {
+      small_to_ntt(c, i, e + (uint64_t)j * N, en);
+      int in_digit = (i < L) && (i / c->alpha == j);
+      for (uint64_t n = 0; n < N; ++n) {
+        uint64_t a = a_unif[((uint64_t)j * nm + i) * N + n];
+        uint64_t b = madd(mmul(a, sn[n], m), en[n], m);
+        if (in_digit) b = madd(b, mmul(Pm, gn[n], m), m);
+        rk[(((uint64_t)j * 2 + 0) * nm + i) * N + n] = b;
+        rk[(((uint64_t)j * 2 + 1) * nm + i) * N + n] = a;
+      }
+    }
+    free(sn); free(gn); free(en);
+  }
+  free(sg);
+}
+
+/* Rotation of a ciphertext [2][level][N] (NTT form): (sigma_g(b), sigma_g(a))
+ * key-switched back to s with rk: out = (sigma_g(b) + KS_b, KS_a), where KS
+ * is ModUp, inner product with rk and ModDown of sigma_g(a) (the triple
+ * (sigma_g(b), 0, sigma_g(a)) through the same steps as HE Mul). */
+void orc_rotate(const orc_ctx* c, uint32_t level, uint64_t g, const uint64_t* ct, const uint64_t* rk,
+                uint64_t* out) {
+  uint64_t N = c->N;
+  uint32_t beta = orc_num_digits(c, level), ne = level + c->K;
+  uint64_t* sct = (uint64_t*)malloc(sizeof(uint64_t) * 2 * level * N);
+  uint64_t* d = (uint64_t*)calloc(3 * (uint64_t)level * N, sizeof(uint64_t));
+  uint64_t* dt = (uint64_t*)malloc(sizeof(uint64_t) * (uint64_t)beta * ne * N);
+  uint64_t* ks = (uint64_t*)malloc(sizeof(uint64_t) * 2 * ne * N);
+  orc_automorphism(c, level, g, ct, sct);
+  memcpy(d, sct, sizeof(uint64_t) * level * N);                               /* d0 = sigma(b) */
+  memcpy(d + 2ull * level * N, sct + (uint64_t)level * N, sizeof(uint64_t) * level * N); /* d2 = sigma(a) */
+  orc_modup(c, level, d + 2ull * level * N, dt);
+  orc_inner_product(c, level, dt, rk, ks);
+  orc_moddown_combine(c, level, ks, d, out);
+  free(sct); free(d); free(dt); free(ks);
+}

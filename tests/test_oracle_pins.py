@@ -427,3 +427,60 @@ def test_he_add_decrypts_to_sum_n12():
     ones = np.ones_like(c1)
     top = np.stack([np.stack([np.full(w.N, q - 1, dtype=np.uint64) for q in ctx.q[:level]])] * 2)
     assert not ctx.he_add(level, top, ones).any()
+
+
+# ---------------------------------------------------------------- rotation (automorphisms)
+def test_automorphism_closed_form_and_composition():
+    """sigma_g(X) = X^g (negated past degree N), sigma_g1 sigma_g2 = sigma_(g1 g2),
+    and sigma_g is a ring map: sigma(a b) = sigma(a) sigma(b)."""
+    w = synth.CFG_TINY
+    ctx = oracle.Context.for_workload(w)
+    N, level = w.N, w.L
+    mono = np.zeros((2, level, N), dtype=np.uint64)
+    for i in range(level):
+        x = np.zeros(N, dtype=np.uint64)
+        x[1] = 1
+        mono[0, i] = mono[1, i] = ctx.ntt(i, x)
+    for g in (3, 5, 2 * N - 1, 25 % (2 * N)):
+        out = ctx.automorphism(level, mono, g)
+        for i in range(level):
+            want = np.zeros(N, dtype=np.uint64)
+            e = g % (2 * N)
+            if e < N:
+                want[e] = 1
+            else:
+                want[e - N] = ctx.q[i] - 1
+            assert np.array_equal(ctx.intt(i, out[0, i]), want), (g, i)
+    a = synth.random_ciphertext(3, ctx.q[:level], N)
+    b = synth.random_ciphertext(4, ctx.q[:level], N)
+    g1, g2 = 5, 2 * N - 5
+    assert np.array_equal(ctx.automorphism(level, ctx.automorphism(level, a, g2), g1),
+                          ctx.automorphism(level, a, (g1 * g2) % (2 * N)))
+    prod = np.stack([np.stack([(a[u, i].astype(object) * b[u, i].astype(object) % ctx.q[i]).astype(np.uint64)
+                               for i in range(level)]) for u in range(2)])
+    sa, sb, sp = (ctx.automorphism(level, x, g1) for x in (a, b, prod))
+    for u in range(2):
+        for i in range(level):
+            assert np.array_equal((sa[u, i].astype(object) * sb[u, i].astype(object) % ctx.q[i]).astype(np.uint64),
+                                  sp[u, i])
+
+
+@pytest.mark.parametrize("r", [1, 7, 1023])
+def test_rotation_decrypts_to_rotated_slots_n12(r):
+    """decrypt(rotate_r(enc(z))) ~ z shifted left by r slots (slot j <- j + r)
+    within the key-switching error; the wrong rotation key misses by O(1)."""
+    w = synth.CFG_N12
+    ctx = oracle.Context.for_workload(w)
+    level = w.L
+    s, evk, za, zb, (c1, c2) = _fresh_pair(ctx, w, level)
+    g = ctx.galois(r)
+    e_rk = synth.gaussian(90 + r, w.N, 16, w.dnum)
+    a_rk = np.stack([synth.uniform_limbs(91 + r, ctx.moduli, w.N, j) for j in range(w.dnum)])
+    rk = ctx.keygen_rot(s, g, e_rk, a_rk)
+    out = ctx.rotate(level, c1, rk, g)
+    scale = 2.0**w.log_scale
+    got = ctx.decrypt(level, out, s, scale)
+    want = np.roll(za, -r)
+    assert np.max(np.abs(got - want)) < 2.0**-20
+    wrong = ctx.rotate(level, c1, ctx.keygen_rot(s, ctx.galois(r + 1), e_rk, a_rk), g)
+    assert np.max(np.abs(ctx.decrypt(level, wrong, s, scale) - want)) > 2.0**-4
