@@ -114,6 +114,23 @@ he_status he_encode(he_ctx* ctx, const double* d_z, uint32_t n, double scale, in
 he_status he_add(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint64_t* d_ct2, uint64_t* d_out,
                  he_stream stream);
 
+/* Rotation by `rot` slots (slot j of the result holds slot j + rot): the
+ * automorphism X -> X^g, g = 5^rot mod 2N, of both polynomials, then the
+ * key switching of HE Mul (ModUp, inner product, ModDown) of sigma_g(a)
+ * back to sk with the rotation key of `rot`.  d_ct, d_out: [2][level][N]
+ * NTT form; d_out must not overlap d_ct (HE_EINVAL).  ws: he_workspace_bytes
+ * (level) bytes.  Enqueued on `stream`. */
+he_status he_rotate(he_ctx* ctx, uint32_t level, const uint64_t* d_ct, const uint64_t* d_rk, int32_t rot,
+                    uint64_t* d_out, void* ws, size_t ws_bytes, he_stream stream);
+
+/* Rotation key of `rot` (layout and gadget of the evaluation key,
+ * [dnum][2][L+K][N]): b_j = a_j sk + e_j - G_j sigma_g(sk), so that key
+ * switching sigma_g(a) returns a pair decrypting to -sigma_g(a) sigma_g(sk).
+ * s: host [N]; e_rk: host [dnum][N]; a_rk: host [dnum][L+K][N] uniform
+ * residues (NTT form).  Synchronizes `stream`. */
+he_status he_keygen_rot(he_ctx* ctx, const int64_t* s, int32_t rot, const int64_t* e_rk, const uint64_t* a_rk,
+                        uint64_t* d_rk, void* ws, size_t ws_bytes, he_stream stream);
+
 /* Decryption to RNS coefficients (Sec. III-A: t = bx - ax*sk): writes
  * d_m [level][N], coefficient form, limb i modulo q_i.  s: host [N]. */
 he_status he_decrypt(he_ctx* ctx, uint32_t level, const uint64_t* d_ct, const int64_t* s,

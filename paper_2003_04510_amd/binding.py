@@ -106,6 +106,8 @@ def load_library():
     L.he_big_timing_read.argtypes = [vp, ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
     L.he_encode.argtypes = [vp, vp, u32, ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
     L.he_add.argtypes = [vp, u32, vp, vp, vp, vp]
+    L.he_rotate.argtypes = [vp, u32, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
+    L.he_keygen_rot.argtypes = [vp, i64p, ctypes.c_int32, i64p, u64p, vp, vp, ctypes.c_size_t, vp]
     L.he_status_str.argtypes = [st]
     L.he_status_str.restype = ctypes.c_char_p
     L.he_last_error.restype = ctypes.c_char_p
@@ -113,7 +115,8 @@ def load_library():
               "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read", "he_batch_create",
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
               "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
-              "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_add"):
+              "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_add", "he_rotate",
+              "he_keygen_rot"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -268,6 +271,25 @@ class Context:
         _check(load_library().he_encode(self._h, vp(zd.data_ptr()), len(zz) // 2, float(scale), vp(m.data_ptr()),
                                         vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_encode")
         return m
+
+    def keygen_rot(self, s, rot: int, e_rk, a_rk):
+        """Rotation key of `rot` slots from supplied draws -> [dnum][2][L+K][N] on the GPU."""
+        rk = self.empty(self.dnum, 2, self.L + self.K, self.N)
+        ws = self.workspace(self.L)
+        s_, sp = _i64(s)
+        e_, ep = _i64(e_rk)
+        a_ = np.ascontiguousarray(a_rk, dtype=np.uint64)
+        _check(load_library().he_keygen_rot(self._h, sp, int(rot), ep, a_.ctypes.data_as(u64p), vp(rk.data_ptr()),
+                                            vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_keygen_rot")
+        return rk
+
+    def rotate(self, level, ct, rk, rot: int, out=None, ws=None):
+        out = self.empty(2, level, self.N) if out is None else out
+        ws = self.workspace(level) if ws is None else ws
+        _check(load_library().he_rotate(self._h, level, vp(ct.data_ptr()), vp(rk.data_ptr()), int(rot),
+                                        vp(out.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8, self._stream()),
+               "he_rotate")
+        return out
 
     def add(self, level, ct1, ct2, out=None):
         out = self.empty(2, level, self.N) if out is None else out

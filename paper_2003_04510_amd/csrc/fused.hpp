@@ -159,7 +159,9 @@ enum Stage : int {
   ST_COUNT,
   // stand-alone rescale only
   ST_LIFT = ST_COUNT,  // rescale lift + NTT cols
-  ST_RESCALE           // NTT blocks + rescale combine
+  ST_RESCALE,          // NTT blocks + rescale combine
+  // rotation only (replaces ST_TENSOR): INTT blocks of sigma_g(a), from d2 into y
+  ST_Y_IBLOCKS
 };
 
 // Tiles per limb of a cols / blocks pass at ring degree 2^log_n.
@@ -201,6 +203,7 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
     case ST_LIFT: return rs ? 2 * (level - 1) * tc : 0;
     case ST_COMBINE: return 2 * level * tb;
     case ST_RESCALE: return rs ? 2 * (level - 1) * tb : 0;
+    case ST_Y_IBLOCKS: return level * tb;
   }
   return 0;
 }
@@ -361,6 +364,9 @@ __device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& p
     v.src = pd.ks + ((u64)pd.level << c.log_n); v.dst = pd.ks + ((u64)pd.level << c.log_n);
     v.zs = v.zd = (ne + 1) * N; v.nl = c.K + ex; v.np = 2;
     v.limb_mod = ldc(&P->s_mod); v.scale = ldc(&P->s_scale);
+  } else if constexpr (ST == ST_Y_IBLOCKS) {
+    v.src = pd.d2; v.dst = pd.y; v.nl = pd.level; v.np = 1;
+    v.limb_mod = c.iota; v.scale = nullptr;
   } else {  // ST_Z_NCOLS
     v.src = pd.zc; v.dst = pd.z; v.zs = v.zd = (u64)pd.level * N; v.nl = pd.level; v.np = 2;
     v.limb_mod = c.iota; v.scale = nullptr;
@@ -1021,6 +1027,28 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c
   const u32 nz = uniform(2 * (pd.rs && !pd.wrl ? pd.level - 1 : pd.level) * cols_tiles(c.log_n, EPW));
   if (local < nz) list_cols_item<true, LOGS, EPW, ST_Z_NCOLS>(c, pd, local, lds);
   else lift_item<LOGS, EPW>(c, pd, local - nz, lds);
+}
+
+// ---------------------------------------------------------------- rotation: automorphism
+// sigma_g (X -> X^g, g odd) of a ciphertext in NTT form, as a permutation of
+// the evaluation points: entry k holds the value at psi^(2 brv(k) + 1), so
+// sigma_g(a)[k] = a[k'] with 2 brv(k') + 1 = (2 brv(k) + 1) g mod 2N.
+// Writes the triple key switching expects: rl = (sigma_g(b), 0), d2 = sigma_g(a).
+// One thread per (limb, coefficient) of [level][N].
+__global__ __launch_bounds__(256) void k_automorphism(const u64* ct, u64* rl, u64* d2, u64 g, u32 level,
+                                                      u32 log_n) {
+  const u64 N = 1ull << log_n, tot = (u64)level * N;
+  const u64 t = (u64)blockIdx.x * 256 + threadIdx.x;
+  if (t >= tot) return;
+  const u64 k = t & (N - 1), base = t - k;
+  const u64 j = __brev((u32)k) >> (32 - log_n);
+  const u64 e = ((2 * j + 1) * g) & (2 * N - 1);
+  const u64 ks = __brev((u32)((e - 1) >> 1)) >> (32 - log_n);
+  const auto in = gbl(ct);
+  const auto r = gbl(rl), d = gbl(d2);
+  r[t] = in[base + ks];
+  r[tot + t] = 0;
+  d[t] = in[tot + base + ks];
 }
 
 // ---------------------------------------------------------------- NTT blocks + rescale combine

@@ -669,6 +669,7 @@ void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) 
     case ST_COMBINE: hipLaunchKernelGGL((k_ntt_combine<N2, EB>), g, dim3(pass_threads(N2, EB)), 0, st, c, b); break;
     case ST_LIFT: hipLaunchKernelGGL((k_lift_ntt_cols<N1, EC>), g, dim3(pass_threads(N1, EC)), 0, st, c, b); break;
     case ST_RESCALE: hipLaunchKernelGGL((k_ntt_rescale<N2, EB>), g, dim3(pass_threads(N2, EB)), 0, st, c, b); break;
+    case ST_Y_IBLOCKS: launch_lblocks<false, N2, EB, ST_Y_IBLOCKS>(c, b, st); break;
   }
 }
 
@@ -690,11 +691,11 @@ TileCfg default_tiles(u32 log_n) {
 }
 
 const char* stage_name(int s) {
-  static const char* names[ST_COUNT + 2] = {"tensor_intt", "y_intt_cols", "modup_convert", "modup_ntt_cols",
+  static const char* names[ST_COUNT + 3] = {"tensor_intt", "y_intt_cols", "modup_convert", "modup_ntt_cols",
                                             "modup_ntt_blocks", "inner_product", "special_intt_blocks",
                                             "modup_blocks_inner_product", "special_intt_cols", "moddown_convert",
                                             "moddown_lift_ntt_cols", "ntt_combine_rescale", "lift_ntt_cols",
-                                            "ntt_rescale"};
+                                            "ntt_rescale", "y_intt_blocks"};
   return names[s];
 }
 
@@ -742,6 +743,7 @@ void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double
     }
     case ST_LIFT: ops = rs ? 2 * (l - 1) * hN * n1 : 0; bytes = rs ? (2 * (l - 1) + 6) * N * 8 : 0; break;
     case ST_RESCALE: ops = rs ? 2 * (l - 1) * hN * n2 : 0; bytes = rs ? 2 * (l - 1) * 3 * N * 8 : 0; break;
+    case ST_Y_IBLOCKS: ops = l * hN * n2; bytes = 2 * l * N * 8; break;
     default: ops = bytes = 0;
   }
 }
