@@ -109,6 +109,16 @@ he_status he_encrypt(he_ctx* ctx, uint32_t level, const int64_t* m, const int64_
 he_status he_encode(he_ctx* ctx, const double* d_z, uint32_t n, double scale, int64_t* d_m, void* ws,
                     size_t ws_bytes, he_stream stream);
 
+/* Decoding (Sec. III-A), the inverse of he_encode: d_m [level][N] residues
+ * of a plaintext in coefficient form (as he_decrypt writes them) -> n <= N/2
+ * complex slots d_z [n][2] (doubles) = m(zeta^(5^j)) / scale, with m the
+ * centred integer polynomial (mixed-radix reconstruction from the residues,
+ * exact, then converted to double).  ws: 16 N + 8 level (level + 1) + 256
+ * bytes.  Enqueued on `stream` (the small reconstruction tables are
+ * uploaded synchronously). */
+he_status he_decode(he_ctx* ctx, uint32_t level, const uint64_t* d_m, double scale, uint32_t n, double* d_z,
+                    void* ws, size_t ws_bytes, he_stream stream);
+
 /* HE Add (Sec. III-B): d_out = d_ct1 + d_ct2 limb by limb, all
  * [2][level][N] (d_out may alias an input).  Enqueued on `stream`. */
 he_status he_add(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint64_t* d_ct2, uint64_t* d_out,

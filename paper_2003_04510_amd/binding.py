@@ -106,6 +106,7 @@ def load_library():
     L.he_big_timing_read.argtypes = [vp, ctypes.POINTER(KernelStat), u32, ctypes.POINTER(u32)]
     L.he_encode.argtypes = [vp, vp, u32, ctypes.c_double, vp, vp, ctypes.c_size_t, vp]
     L.he_add.argtypes = [vp, u32, vp, vp, vp, vp]
+    L.he_decode.argtypes = [vp, u32, vp, ctypes.c_double, u32, vp, vp, ctypes.c_size_t, vp]
     L.he_rotate.argtypes = [vp, u32, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
     L.he_keygen_rot.argtypes = [vp, i64p, ctypes.c_int32, i64p, u64p, vp, vp, ctypes.c_size_t, vp]
     L.he_status_str.argtypes = [st]
@@ -115,7 +116,7 @@ def load_library():
               "he_rescale", "he_ntt", "he_ctx_info", "he_timing_enable", "he_timing_read", "he_batch_create",
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
               "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
-              "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_add", "he_rotate",
+              "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_decode", "he_add", "he_rotate",
               "he_keygen_rot"):
         getattr(L, f).restype = st
     _lib = L
@@ -290,6 +291,15 @@ class Context:
                                         vp(out.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8, self._stream()),
                "he_rotate")
         return out
+
+    def decode(self, level, m_limbs, scale: float, n: int = None):
+        """Coefficient-form residues [level][N] (device) -> n complex slots (numpy)."""
+        n = self.N // 2 if n is None else n
+        z = self.torch.empty(2 * max(n, 1), dtype=self.torch.float64, device=self.dev)
+        ws = self.workspace(level)
+        _check(load_library().he_decode(self._h, level, vp(m_limbs.data_ptr()), float(scale), n, vp(z.data_ptr()),
+                                        vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_decode")
+        return z.cpu().numpy()[:2 * n].view(np.complex128)
 
     def add(self, level, ct1, ct2, out=None):
         out = self.empty(2, level, self.N) if out is None else out

@@ -18,9 +18,52 @@ he_status he_encode(he_ctx* c, const double* d_z, uint32_t n, double scale, int6
   const u32 T = enc::THREADS;
   hipLaunchKernelGGL(enc::k_enc_scatter, dim3((u32)ceil_div(N / 2, T)), dim3(T), 0, st, d_z, n, scale, V, c->log_n);
   for (u32 s = 1; s <= c->log_n; ++s)
-    hipLaunchKernelGGL(enc::k_fft_stage, dim3((u32)ceil_div(N / 2, T)), dim3(T), 0, st, V, s, c->log_n);
+    hipLaunchKernelGGL(enc::k_fft_stage, dim3((u32)ceil_div(N / 2, T)), dim3(T), 0, st, V, s, c->log_n, -1.0);
   hipLaunchKernelGGL(enc::k_enc_finish, dim3((u32)ceil_div(N, T)), dim3(T), 0, st, (const enc::cplx*)V, d_m,
                      c->log_n);
+  HIP_TRY(hipGetLastError());
+  return HE_OK;
+}
+
+he_status he_decode(he_ctx* c, uint32_t level, const uint64_t* d_m, double scale, uint32_t n, double* d_z,
+                    void* ws, size_t ws_bytes, he_stream stream) {
+  if (!c || !d_m || !ws || (n && !d_z)) return fail(HE_EINVAL, "he_decode: null pointer");
+  if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_decode: level %u not in [1, L]", level);
+  if (n > c->N / 2) return fail(HE_EINVAL, "he_decode: %u slots exceed N/2", n);
+  if (!(scale > 0.0)) return fail(HE_EINVAL, "he_decode: scale must be positive");
+  const u64 N = c->N, tabs = (u64)level * level * 8 + (u64)level * 8;
+  if (ws_bytes < 16 * N + tabs + 256) return fail(HE_ENOMEM, "he_decode: workspace too small");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  // mixed-radix tables: [W_j]_{q_i} (j < i), [W_i^-1]_{q_i}, W_i as doubles
+  std::vector<u64> wmod((size_t)level * level, 0);
+  std::vector<double> wd(level);
+  double w = 1.0;
+  for (u32 i = 0; i < level; ++i) {
+    const u64 qi = c->mod[i];
+    u64 W = 1 % qi;
+    for (u32 j = 0; j < i; ++j) {
+      wmod[(size_t)i * level + j] = W;  // [W_j]_{q_i}
+      W = mulmod(W, c->mod[j] % qi, qi);
+    }
+    wmod[(size_t)i * level + i] = invmod(W, qi);
+    wd[i] = w;
+    w *= (double)qi;
+  }
+  enc::cplx* V = (enc::cplx*)ws;
+  u64* tw = (u64*)((uint8_t*)ws + 16 * N);
+  double* td = (double*)(tw + (u64)level * level);
+  he_status r;
+  if ((r = upload_sync(tw, wmod.data(), wmod.size() * 8, st)) != HE_OK) return r;
+  if ((r = upload_sync(td, wd.data(), wd.size() * 8, st)) != HE_OK) return r;
+  enc::DecArgs a{d_m, c->mods, tw, td, V, level, c->log_n};
+  const u32 T = enc::THREADS;
+  hipLaunchKernelGGL(enc::k_dec_crt, dim3((u32)ceil_div(N, T)), dim3(T), 0, st, a);
+  for (u32 s = 1; s <= c->log_n; ++s)
+    hipLaunchKernelGGL(enc::k_fft_stage, dim3((u32)ceil_div(N / 2, T)), dim3(T), 0, st, V, s, c->log_n, 1.0);
+  if (n)
+    hipLaunchKernelGGL(enc::k_dec_gather, dim3((u32)ceil_div(n, T)), dim3(T), 0, st, (const enc::cplx*)V, n, scale,
+                       d_z, c->log_n);
   HIP_TRY(hipGetLastError());
   return HE_OK;
 }

@@ -58,3 +58,27 @@ def test_he_add_bit_exact(wname, level):
     # in place
     lib.add(level, d1, d2, out=d1)
     assert np.array_equal(lib.to_host(d1), want)
+
+
+@pytest.mark.parametrize("wname,level", [("n12_L3", 3), ("n16_L24", 24), ("n16_L24", 2)])
+def test_decode_matches_oracle(wname, level):
+    """GPU decoding of decrypted residues against the oracle's exact
+    reconstruction + FFT (both FP64 at the end: equal to 2^-30 relative),
+    and the whole encode -> encrypt -> decrypt -> decode chain on the GPU."""
+    lib, orc = contexts(wname)
+    w = synth.WORKLOADS[wname]
+    scale = 2.0**w.log_scale
+    kd = synth.key_draws(w)
+    a_pk = synth.uniform_limbs(synth.SEED_KEYS, orc.q, w.N, 30)
+    a_evk = np.stack([synth.uniform_limbs(synth.SEED_KEYS, orc.moduli, w.N, 40 + j) for j in range(w.dnum)])
+    pk, _ = lib.keygen(kd.s, kd.e_pk, kd.e_evk, a_pk, a_evk)
+    z = synth.unit_disk(41, w.slots)
+    ed = synth.enc_draws(w, 42)
+    ct = lib.encrypt(level, lib.to_host(lib.encode(z, scale)).view(np.int64), ed.v, ed.e0, ed.e1, pk)
+    m = lib.decrypt_limbs(level, ct, kd.s)
+    got = lib.decode(level, m, scale)
+    want = oracle.decode(oracle.crt_centered(lib.to_host(m), orc.q[:level]), scale)
+    assert np.abs(got - want).max() < 2.0**-30 * max(1.0, np.abs(want).max())
+    assert np.abs(got - z).max() < 2.0**-20
+    few = lib.decode(level, m, scale, 5)
+    assert np.abs(few - got[:5]).max() == 0
