@@ -66,8 +66,12 @@ CFG_N17 = _mk("n17_L45", 17, 45, 15, 3, 192, 50, 60, 50, 60)
 CFG_N15 = _mk("n15_L12", 15, 12, 4, 3, 192, 40, 60, 50, 60)
 # Tiny rings used by big-integer pins.
 CFG_TINY = _mk("n16_tiny", 4, 5, 2, 3, 4, 20, 50, 50, 60)
+# The paper's GPU word size (beta = 2^32, primes below 2^30, Table VI) at
+# N=2^16: L=40 primes of 30 bits (log Q = 1200, the paper's), dnum=4,
+# K=11 special primes of 30 bits, scale 2^30 (one prime per rescale).
+CFG_N16_W30 = _mk("n16_L40_w30", 16, 40, 11, 4, 192, 30, 30, 30, 30)
 
-WORKLOADS = {w.name: w for w in (CFG_N12, CFG_N16, CFG_N17, CFG_N15, CFG_TINY)}
+WORKLOADS = {w.name: w for w in (CFG_N12, CFG_N16, CFG_N17, CFG_N15, CFG_TINY, CFG_N16_W30)}
 
 # Seeds of the measured workload.
 SEED_KEYS, SEED_MSG_A, SEED_MSG_B, SEED_ENC_A, SEED_ENC_B = 1, 2, 3, 4, 5

@@ -88,6 +88,12 @@ def test_he_mul_n17(level):
     _he_mul_case("n17_L45", level)
 
 
+@pytest.mark.parametrize("level", [40, 11, 2])
+def test_he_mul_w30_primes(level):
+    """The paper's GPU word size: 40 primes of 30 bits (log Q = 1200)."""
+    _he_mul_case("n16_L40_w30", level)
+
+
 def test_he_mul_extreme_inputs():
     lib, orc = contexts("n16_L24")
     level = 24

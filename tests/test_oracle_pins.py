@@ -89,7 +89,7 @@ def test_gen_primes_small_bruteforce():
     assert oracle.gen_primes(4, 20, 6) == want
 
 
-@pytest.mark.parametrize("wname", ["n12_L3", "n16_L24", "n17_L45", "n15_L12"])
+@pytest.mark.parametrize("wname", ["n12_L3", "n16_L24", "n17_L45", "n15_L12", "n16_L40_w30"])
 def test_workload_primes_are_largest_and_distinct(wname):
     w = synth.WORKLOADS[wname]
     q, p = oracle.workload_primes(w)
@@ -167,7 +167,7 @@ def test_ntt_product_equals_schoolbook(log_n):
             assert [int(v) for v in prod] == oracle.schoolbook_negacyclic(a, b, m)
 
 
-@pytest.mark.parametrize("wname", ["n12_L3", "n15_L12", "n16_L24", "n17_L45"])
+@pytest.mark.parametrize("wname", ["n12_L3", "n15_L12", "n16_L24", "n17_L45", "n16_L40_w30"])
 def test_ntt_roundtrip_identity(wname):
     w = synth.WORKLOADS[wname]
     q, p = oracle.workload_primes(w)
@@ -484,3 +484,21 @@ def test_rotation_decrypts_to_rotated_slots_n12(r):
     assert np.max(np.abs(got - want)) < 2.0**-20
     wrong = ctx.rotate(level, c1, ctx.keygen_rot(s, ctx.galois(r + 1), e_rk, a_rk), g)
     assert np.max(np.abs(ctx.decrypt(level, wrong, s, scale) - want)) > 2.0**-4
+
+
+def test_decrypt_of_he_mul_w30_primes():
+    """The 30-bit-prime variant (the paper's GPU word size): decrypt(HE Mul)
+    matches the FP64 product of the slots, before and after the rescale."""
+    w = synth.CFG_N16_W30
+    ctx = oracle.Context.for_workload(w)
+    level = 6
+    s, evk, za, zb, (c1, c2) = _fresh_pair(ctx, w, level)
+    scale = 2.0**w.log_scale
+    relin, out = ctx.he_mul(level, c1, c2, evk)
+    want = za * zb
+    got_pre = ctx.decrypt(level, relin, s, scale * scale)
+    got = ctx.decrypt(level - 1, out, s, scale * scale / ctx.q[level - 1])
+    # scale 2^30: fresh noise ~ sqrt(N h) sigma per slot, i.e. about 2^-13
+    # relative after the product; a wrong term errs by O(1)
+    assert np.linalg.norm(got_pre - want) / np.linalg.norm(want) < 2.0**-10
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2.0**-10
