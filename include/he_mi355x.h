@@ -66,10 +66,9 @@ he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uin
  * in bit-reversed order, with Shoup companions, Algorithms 2-3) and all
  * base-conversion constants on device `device`.  The context owns those
  * tables (freed by he_ctx_destroy).  Constraints: 12 <= log_n <= 17,
- * 1 <= dnum <= min(L, 4) (HE_EUNSUPPORTED above 4: the key-switch inner
- * product runs one digit per wavefront of a 4-wave workgroup), L <= 64,
- * 1 <= K <= 32, K special primes whose product exceeds every digit's
- * product.  */
+ * 1 <= dnum <= min(L, 64) (HE_EINVAL otherwise), digit size ceil(L/dnum)
+ * <= 32 and K <= 32 (HE_EUNSUPPORTED above), L <= 64, K special primes
+ * whose product exceeds every digit's product.  */
 he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
                         const uint64_t* p, int device, he_ctx** out);
 void he_ctx_destroy(he_ctx* ctx);
@@ -207,16 +206,19 @@ void he_batch_destroy(he_batch* batch);
  * captured graph keeps that structure.  Results are identical under every
  * schedule.  ip_fused (0 or 1): run the mod-up NTT blocks pass, the evk inner
  * product and the special limbs' INTT blocks pass as one fused pass (less
- * HBM traffic, longer dependency chains per workgroup) instead of three.
+ * HBM traffic, longer dependency chains per workgroup) instead of three;
+ * it runs one digit per wavefront of a 4-wave workgroup, so dnum <= 4.
  *
  * he_batch_set_sched: validates (HE_EUNSUPPORTED for tiles not available at
- * this ring degree, HE_EINVAL for a bad chunk count), re-uploads the item
+ * this ring degree or the fused pass with dnum > 4, HE_EINVAL for a bad
+ * chunk count), re-uploads the item
  * offsets on `stream` and waits for it, drops a captured graph.
  * he_batch_get_sched: the current schedule.
  * he_batch_autotune: runs the batch (overwriting its outputs with the same
  * values) as a graph `reps` times under each candidate schedule -- every
  * available tile pair with one chunk, then the best tiles with the fused
- * inner product, then the best of those with 2 and 4 chunks -- times each with HIP events on `stream`, and installs the
+ * inner product (dnum <= 4), then the best of those with 2 and 4 chunks --
+ * times each with HIP events on `stream`, and installs the
  * fastest; *best and *best_ms (may be NULL) receive it and its time per
  * replay.  Synchronizes `stream`. */
 typedef struct he_batch_sched {

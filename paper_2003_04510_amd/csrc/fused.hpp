@@ -45,6 +45,7 @@ struct TileCfg {
   u32 epw_c = EPW_C, epw_b = EPW_B, fused_ip = 0;
 };
 constexpr int CONV_CPT = 2, CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
+constexpr int CONV_RUN = 15;  // sources whose 30x30-bit products a 64-bit sum takes without a carry
 constexpr int IP_CPT = 2, IP_THREADS = 256;                        // inner product
 
 // Item index for workgroup `bid` of a grid of `grid` (grid % 8 == 0):
@@ -65,6 +66,8 @@ struct ConvJobDev {
   u32 src_off, ns, dst_off, nt, tg_off, pad;
 };
 
+constexpr int MAX_DIGITS = 64;  // key-switching digits (dnum) of a context
+
 // Per-level plan (device-resident, built once per context).
 struct PlanDev {
   const ConvJobDev* mu_jobs;  // [beta]
@@ -83,7 +86,7 @@ struct PlanDev {
   const u64* qlmod;    // q_{level-1} mod q_i
   u64 pinv_l, pinv_ls; // [P^-1]_{q_{level-1}} and its Shoup companion
   u32 level, beta, dt_limbs, pad;
-  u32 dt_first[8], lo[8], cnt[8];
+  u32 dt_first[MAX_DIGITS], lo[MAX_DIGITS], cnt[MAX_DIGITS];
 };
 
 // One HE Mul of a launch: operands, outputs, workspace, plan.
@@ -209,7 +212,8 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
 }
 
 // ---------------------------------------------------------------- base conversion helpers
-__device__ __forceinline__ u64 conv_finish(u64 sll, u64 slh, u64 shl, u64 shh, const ModInfo& m) {
+// sll + (slh + shl) 2^30 + shh 2^60 as a 128-bit value.
+__device__ __forceinline__ U128 conv_sum(u64 sll, u64 slh, u64 shl, u64 shh) {
   const u64 mid = slh + shl;
   const u64 cm = mid < slh ? 1 : 0;
   U128 x;
@@ -221,7 +225,7 @@ __device__ __forceinline__ u64 conv_finish(u64 sll, u64 slh, u64 shl, u64 shh, c
   const u64 blo = mid << 30;
   x.lo += blo;
   x.hi += ((mid >> 34) | (cm << 30)) + (x.lo < blo ? 1 : 0);
-  return reduce128(x, m);
+  return x;
 }
 
 // ---------------------------------------------------------------- tensor + INTT blocks
@@ -494,7 +498,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
 // with its delayed modulo): a thread owns CONV_CPT consecutive
 // coefficients, loads each source residue once (split into 30-bit halves),
 // then loops over a group of targets, accumulating four 64-bit sums of
-// 30x30-bit products (no carries for up to 15 sources) and reducing once.
+// 30x30-bit products (no carries for up to 15 sources, runs of 15 folded
+// into 128 bits beyond that) and reducing once.
 // Mod up: sources y, outputs dt (jobs = digits).  Mod down: sources the
 // special limbs of ks (coefficient form), outputs zc, one job per polynomial.
 // Mod-down constants carry P^-1 ([P/p_k]_t [P^-1]_t), so zc holds z P^-1.
@@ -542,29 +547,39 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       y1[s][k] = (u32)(y >> 30);
     }
   }
-  // sum_s y_s c_s mod t for target index t of the job, canonical
+  // sum_s y_s c_s mod t for target index t of the job, canonical.  The
+  // 64-bit partial sums take up to 15 sources without a carry; longer jobs
+  // fold each run of 15 into a 128-bit total before the one reduction.
   const auto convert = [&](u32 t, u64 (&v)[CONV_CPT]) {
     const ConvTarget T = ldc(tg + J.tg_off + t);
     const ModInfo m = ldc(c.mods + T.mi);
     const u32* C = consts + T.c_off;
-    u64 sll[CONV_CPT], slh[CONV_CPT], shl[CONV_CPT], shh[CONV_CPT];
+    U128 tot[CONV_CPT];
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
+    for (int k = 0; k < CONV_CPT; ++k) tot[k] = U128{0, 0};
 #pragma unroll
-    for (int s = 0; s < NSMAX; ++s) {
-      const u32 sc = min((u32)s, T.ns - 1);
-      const bool use = (u32)s < T.ns;
-      const u32 c0 = use ? ldc(C + 2 * sc) : 0u, c1 = use ? ldc(C + 2 * sc + 1) : 0u;
+    for (int s0 = 0; s0 < NSMAX; s0 += CONV_RUN) {
+      u64 sll[CONV_CPT], slh[CONV_CPT], shl[CONV_CPT], shh[CONV_CPT];
 #pragma unroll
-      for (int k = 0; k < CONV_CPT; ++k) {
-        sll[k] += (u64)y0[s][k] * c0;
-        slh[k] += (u64)y0[s][k] * c1;
-        shl[k] += (u64)y1[s][k] * c0;
-        shh[k] += (u64)y1[s][k] * c1;
+      for (int k = 0; k < CONV_CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
+#pragma unroll
+      for (int s = s0; s < s0 + CONV_RUN && s < NSMAX; ++s) {
+        const u32 sc = min((u32)s, T.ns - 1);
+        const bool use = (u32)s < T.ns;
+        const u32 c0 = use ? ldc(C + 2 * sc) : 0u, c1 = use ? ldc(C + 2 * sc + 1) : 0u;
+#pragma unroll
+        for (int k = 0; k < CONV_CPT; ++k) {
+          sll[k] += (u64)y0[s][k] * c0;
+          slh[k] += (u64)y0[s][k] * c1;
+          shl[k] += (u64)y1[s][k] * c0;
+          shh[k] += (u64)y1[s][k] * c1;
+        }
       }
+#pragma unroll
+      for (int k = 0; k < CONV_CPT; ++k) add_to(tot[k], conv_sum(sll[k], slh[k], shl[k], shh[k]));
     }
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) v[k] = conv_finish(sll[k], slh[k], shl[k], shh[k], m);
+    for (int k = 0; k < CONV_CPT; ++k) v[k] = reduce128(tot[k], m);
   };
   // The rescale's dropped limb in coefficient form, by linearity: with the
   // mod-down constants carrying P^-1 (z' = z P^-1),
@@ -629,7 +644,9 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
 }
 
 // Smallest source bound bucket covering ns (ns <= 15).
-inline int conv_bucket(u32 ns) { return ns <= 4 ? 4 : ns <= 8 ? 8 : ns <= 12 ? 12 : 15; }
+inline int conv_bucket(u32 ns) {
+  return ns <= 4 ? 4 : ns <= 8 ? 8 : ns <= 12 ? 12 : ns <= 15 ? 15 : ns <= 24 ? 24 : 32;
+}
 
 // ---------------------------------------------------------------- inner product
 // ks_u[e] = sum_j dt_j[e] * evk_j.u[e] for every limb e of the extended basis;
@@ -695,7 +712,9 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
   const auto xb = gbl(pd.ks + ((u64)(pd.level + c.K) << c.log_n) + n0);
 #pragma unroll
   for (int k = 0; k < IP_CPT; ++k) {
-    const u64 vb = barrett(accb[k], m), va = barrett(acca[k], m);
+    // beta <= 4: the sums stay below 4 q^2 < 2^(2b+2), Barrett's range
+    const u64 vb = beta <= 4 ? barrett(accb[k], m) : reduce128(accb[k], m);
+    const u64 va = beta <= 4 ? barrett(acca[k], m) : reduce128(acca[k], m);
     ob[k] = vb;
     ob[kz + k] = va;
     if (last) {

@@ -76,7 +76,7 @@ struct LevelPlan {
   size_t o_mu_jobs = 0, o_md_jobs = 0;
   const ConvJobDev* mu_jobs = nullptr;  // [beta]
   const ConvJobDev* md_jobs = nullptr;  // [1]
-  u32 lo[8] = {}, cnt[8] = {}, dt_first[8] = {};
+  u32 lo[MAX_DIGITS] = {}, cnt[MAX_DIGITS] = {}, dt_first[MAX_DIGITS] = {};
   size_t o_modup_scale = 0, o_dt_mod = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
   // resolved device pointers
   const u64* modup_scale = nullptr;
@@ -327,10 +327,8 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   if (!out || !q || !p) return fail(HE_EINVAL, "he_ctx_create: null pointer");
   *out = nullptr;
   if (log_n < 12 || log_n > 17) return fail(HE_EUNSUPPORTED, "log_n must be in [12, 17]");
-  if (L < 1 || L > 64 || K < 1 || K > 32 || dnum < 1 || dnum > L || dnum > 8)
-    return fail(HE_EINVAL, "need 1 <= dnum <= min(L, 8), L <= 64, 1 <= K <= 32");
-  if (dnum > (u32)IP_WAVES)
-    return fail(HE_EUNSUPPORTED, "dnum %u: the inner product handles at most %d digits", dnum, IP_WAVES);
+  if (L < 1 || L > 64 || K < 1 || K > 32 || dnum < 1 || dnum > L || dnum > (u32)MAX_DIGITS)
+    return fail(HE_EINVAL, "need 1 <= dnum <= min(L, %d), L <= 64, 1 <= K <= 32", MAX_DIGITS);
   const u64 N = 1ull << log_n;
   std::unique_ptr<he_ctx, void (*)(he_ctx*)> c(new he_ctx, he_ctx_destroy);  // frees device memory on errors
   c->log_n = log_n; c->L = L; c->K = K; c->dnum = dnum; c->N = N;
@@ -347,8 +345,8 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     for (u32 j = 0; j < i; ++j)
       if (c->mod[j] == m) return fail(HE_EINVAL, "moduli must be distinct");
   }
-  if (c->alpha > 15 || K > 15)
-    return fail(HE_EUNSUPPORTED, "digit size ceil(L/dnum) and K must be <= 15");
+  if (c->alpha > 32 || K > 32)
+    return fail(HE_EUNSUPPORTED, "digit size ceil(L/dnum) and K must be <= 32");
   // special primes must cover every digit: P > prod(digit)
   {
     long double lp = 0, ld = 0;
@@ -523,7 +521,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     pd.qlinv = (const u64*)(d + P.o_qlinv); pd.qlmod = (const u64*)(d + P.o_qlmod);
     pd.pinv_l = P.pinv_l; pd.pinv_ls = shoup(P.pinv_l, q[lvl - 1]);
     pd.level = lvl; pd.beta = P.beta; pd.dt_limbs = P.dt_limbs;
-    for (u32 j = 0; j < 8; ++j) { pd.dt_first[j] = P.dt_first[j]; pd.lo[j] = P.lo[j]; pd.cnt[j] = P.cnt[j]; }
+    for (u32 j = 0; j < (u32)MAX_DIGITS; ++j) { pd.dt_first[j] = P.dt_first[j]; pd.lo[j] = P.lo[j]; pd.cnt[j] = P.cnt[j]; }
     memcpy(B.bytes.data() + P.o_plan, &pd, sizeof pd);
   }
   {
@@ -645,7 +643,9 @@ void launch_conv(int bucket, const Common& c, const Batch& b, hipStream_t st) {
     case 4: hipLaunchKernelGGL((k_conv<MD, 4>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
     case 8: hipLaunchKernelGGL((k_conv<MD, 8>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
     case 12: hipLaunchKernelGGL((k_conv<MD, 12>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    default: hipLaunchKernelGGL((k_conv<MD, 15>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+    case 15: hipLaunchKernelGGL((k_conv<MD, 15>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+    case 24: hipLaunchKernelGGL((k_conv<MD, 24>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+    default: hipLaunchKernelGGL((k_conv<MD, 32>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
   }
 }
 
@@ -1051,6 +1051,8 @@ he_status he_batch_set_sched(he_batch* bt, const he_batch_sched* sc, he_stream s
   if (!tiles_supported(c->log_n, t))
     return fail(HE_EUNSUPPORTED, "he_batch_set_sched: tiles %u/%u not available at N = 2^%u", t.epw_c, t.epw_b,
                 c->log_n);
+  if (t.fused_ip && c->dnum > (u32)IP_WAVES)
+    return fail(HE_EUNSUPPORTED, "he_batch_set_sched: the fused inner product takes at most %d digits", IP_WAVES);
   if (sc->chunks < 1 || sc->chunks > 8 || sc->chunks > bt->n)
     return fail(HE_EINVAL, "he_batch_set_sched: chunks %u not in [1, min(8, pairs)]", sc->chunks);
   HIP_TRY(hipSetDevice(c->device));
@@ -1199,7 +1201,7 @@ he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32
     if ((r = run(sc, ms)) != HE_OK) break;
     if (ms < bms) { bms = ms; b = sc; }
   }
-  if (r == HE_OK) {  // the fused mod-up blocks + inner product pass
+  if (r == HE_OK && c->dnum <= (u32)IP_WAVES) {  // the fused mod-up blocks + inner product pass
     he_batch_sched sc = b;
     sc.ip_fused = 1;
     double ms = 0;

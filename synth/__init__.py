@@ -71,7 +71,17 @@ CFG_TINY = _mk("n16_tiny", 4, 5, 2, 3, 4, 20, 50, 50, 60)
 # K=11 special primes of 30 bits, scale 2^30 (one prime per rescale).
 CFG_N16_W30 = _mk("n16_L40_w30", 16, 40, 11, 4, 192, 30, 30, 30, 30)
 
-WORKLOADS = {w.name: w for w in (CFG_N12, CFG_N16, CFG_N17, CFG_N15, CFG_TINY, CFG_N16_W30)}
+# Key-switching variants at N=2^16, L=24 (Sec. III's evaluation key with
+# P ~ Q, and one digit per prime): dnum=1 with K=21 special primes of 60
+# bits (P > Q), dnum=L=24 with K=2 (P above the largest prime).
+CFG_N16_D1 = _mk("n16_L24_d1", 16, 24, 21, 1, 192, 40, 60, 50, 60)
+CFG_N16_DL = _mk("n16_L24_d24", 16, 24, 2, 24, 192, 40, 60, 50, 60)
+# Small rings of the same variants for the oracle pins.
+CFG_N12_D1 = _mk("n12_L6_d1", 12, 6, 6, 1, 64, 40, 60, 50, 60)
+CFG_N12_DL = _mk("n12_L6_d6", 12, 6, 2, 6, 64, 40, 60, 50, 60)
+
+WORKLOADS = {w.name: w for w in (CFG_N12, CFG_N16, CFG_N17, CFG_N15, CFG_TINY, CFG_N16_W30,
+                                 CFG_N16_D1, CFG_N16_DL, CFG_N12_D1, CFG_N12_DL)}
 
 # Seeds of the measured workload.
 SEED_KEYS, SEED_MSG_A, SEED_MSG_B, SEED_ENC_A, SEED_ENC_B = 1, 2, 3, 4, 5

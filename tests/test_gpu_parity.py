@@ -88,6 +88,15 @@ def test_he_mul_n17(level):
     _he_mul_case("n17_L45", level)
 
 
+@pytest.mark.parametrize("wname,level", [("n16_L24_d1", 24), ("n16_L24_d1", 9), ("n16_L24_d24", 24),
+                                         ("n16_L24_d24", 5), ("n12_L6_d1", 6), ("n12_L6_d6", 6)])
+def test_he_mul_dnum_variants(wname, level):
+    """Key switching with dnum = 1 (one digit of up to 24 primes, 21 special
+    primes: the conversion's runs of 15 sources folded in 128 bits) and
+    dnum = L (one prime per digit, 24 digits in the inner product)."""
+    _he_mul_case(wname, level)
+
+
 @pytest.mark.parametrize("level", [40, 11, 2])
 def test_he_mul_w30_primes(level):
     """The paper's GPU word size: 40 primes of 30 bits (log Q = 1200)."""

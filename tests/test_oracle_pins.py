@@ -502,3 +502,21 @@ def test_decrypt_of_he_mul_w30_primes():
     # relative after the product; a wrong term errs by O(1)
     assert np.linalg.norm(got_pre - want) / np.linalg.norm(want) < 2.0**-10
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2.0**-10
+
+
+
+@pytest.mark.parametrize("wname", ["n12_L6_d1", "n12_L6_d6"])
+def test_decrypt_of_he_mul_dnum_variants(wname):
+    """Key switching with one digit (P > Q, the paper's evaluation key) and
+    with one digit per prime: decrypt(HE Mul) matches the FP64 product."""
+    w = synth.WORKLOADS[wname]
+    ctx = oracle.Context.for_workload(w)
+    level = w.L
+    s, evk, za, zb, (c1, c2) = _fresh_pair(ctx, w, level)
+    scale = 2.0**w.log_scale
+    relin, out = ctx.he_mul(level, c1, c2, evk)
+    want = za * zb
+    got_pre = ctx.decrypt(level, relin, s, scale * scale)
+    got = ctx.decrypt(level - 1, out, s, scale * scale / ctx.q[level - 1])
+    assert np.linalg.norm(got_pre - want) / np.linalg.norm(want) < 2.0**-20
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 2.0**-20
