@@ -170,3 +170,26 @@ def test_fused_ip_other_rings(wname, levels):
     for k, use_graph in enumerate((False, True, True)):
         _run_check(lib, bt, items, dev, evk, use_graph, (wname, k))
     bt.close()
+
+
+@pytest.mark.parametrize("wname,levels", [("n16_L24_d24", [24, 7, 16]), ("n16_L24_d1", [24, 3, 11])])
+def test_batch_dnum_variants(wname, levels):
+    """Batches with 24 digits (no fused pass: the tuner skips it, set_sched
+    refuses it) and with one 24-prime digit give the plain he_mul results."""
+    import paper_2003_04510_amd as P
+    lib, orc = contexts(wname)
+    log("batch dnum variant", wname, levels)
+    evk = lib.to_device(random_evk(orc, 9))
+    dev = [(lv, lib.to_device(a), lib.to_device(b)) for lv, a, b in _pairs(orc, levels, 800)]
+    items = [(lv, a, b, lib.empty(2, lv, orc.N) if i == 0 else None, lib.empty(2, lv - 1, orc.N))
+             for i, (lv, a, b) in enumerate(dev)]
+    bt = lib.batch(items)
+    if orc.dnum > 4:
+        with pytest.raises(P.HeError):
+            bt.set_sched(4096, 1024, 1, 1)
+    sc, _ = bt.autotune(evk, reps=1)
+    if orc.dnum > 4:
+        assert sc["ip_fused"] == 0
+    for k, use_graph in enumerate((True, True)):
+        _run_check(lib, bt, items, dev, evk, use_graph, (wname, k))
+    bt.close()

@@ -21,6 +21,7 @@ def _rot_key(lib, orc, w, rot, seed):
 @pytest.mark.parametrize("wname,level,rot", [
     ("n12_L3", 3, 1), ("n12_L3", 2, 5), ("n12_L3", 1, -1), ("n12_L3", 3, 1023),
     ("n16_L24", 24, 1), ("n16_L24", 7, -3), ("n16_L24", 13, 32767),
+    ("n16_L24_d24", 9, 5), ("n12_L6_d1", 6, 2),
 ])
 def test_rotate_matches_oracle(wname, level, rot):
     lib, orc = contexts(wname)
