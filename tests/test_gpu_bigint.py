@@ -54,7 +54,15 @@ def _oracle_case(log_n, logQ, logq, seed, kind):
     (1200, 1200, "random"),    # the paper's log Q at N = 2^12
 ])
 def test_big_mul_matches_oracle(logQ, logq, kind):
-    log_n = 12
+    _big_case(12, logQ, logq, kind)
+
+
+def test_big_mul_other_ring():
+    """N = 2^13 (another transform size, twice the coefficients per launch)."""
+    _big_case(13, 300, 277, "random")
+
+
+def _big_case(log_n, logQ, logq, kind):
     lib = big_ctx(log_n, logQ)
     c1, c2, ev, c3 = _oracle_case(log_n, logQ, logq, 7, kind)
     W = lib.W

@@ -60,7 +60,7 @@ def test_he_add_bit_exact(wname, level):
     assert np.array_equal(lib.to_host(d1), want)
 
 
-@pytest.mark.parametrize("wname,level", [("n12_L3", 3), ("n16_L24", 24), ("n16_L24", 2)])
+@pytest.mark.parametrize("wname,level", [("n12_L3", 3), ("n16_L24", 24), ("n16_L24", 2), ("n17_L45", 45)])
 def test_decode_matches_oracle(wname, level):
     """GPU decoding of decrypted residues against the oracle's exact
     reconstruction + FFT (both FP64 at the end: equal to 2^-30 relative),
