@@ -88,6 +88,10 @@ __global__ __launch_bounds__(MF_THREADS) void k_big_crt(CrtArgs a) {
   const auto Bg = gbl(a.B + (u64)g * a.ncols + r);
   const u32 steps = (a.np + 3) / 4;
   for (u32 cp = 0; cp < steps; ++cp) {
+    // this lane's prime: its constants are loaded ahead of the products
+    const u32 i = 4 * cp + g, ic = min(i, a.np - 1);
+    const ModInfo m = a.mods[ic];
+    const u64 adj = a.adj[ic];
     v4i acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
     const u32 c0 = 32 * cp;
 #pragma unroll
@@ -105,7 +109,6 @@ __global__ __launch_bounds__(MF_THREADS) void k_big_crt(CrtArgs a) {
     }
     lds_wave_sync();
     // lane: coefficient r, prime 4 cp + g (digits at columns 8 g .. 8 g + 7)
-    const u32 i = 4 * cp + g;
     if (i < a.np) {
       const int* z = &zs[wave][r][8 * g];
       // V = sum_b 2^(8b) z_b, |V| < 2^79; U = V + 2^80 > 0
@@ -119,8 +122,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_big_crt(CrtArgs a) {
       U128 u;
       u.lo = (u64)v;
       u.hi = (u64)(v >> 64);
-      const ModInfo m = a.mods[i];
-      dst[(u64)i * N + n0 + r] = addmod(reduce128(u, m), a.adj[i], m.q);
+      dst[(u64)i * N + n0 + r] = addmod(reduce128(u, m), adj, m.q);
     }
     lds_wave_sync();
   }
