@@ -192,7 +192,7 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
   const u32 chunks_c = (1u << log_n) / (CONV_THREADS * CONV_CPT);
   const u32 ex = rs ? 1 : 0;
   switch (st) {
-    case ST_TENSOR: return (level + 2 * ex) * tb;
+    case ST_TENSOR: return (2 * level + 2 * ex) * tb;
     case ST_Y_ICOLS: return (level + 2 * ex) * tc;
     case ST_MU_CONV: return beta * CONV_GROUPS * chunks_c;
     case ST_DT_NCOLS: return dt_limbs * tc;
@@ -229,10 +229,14 @@ __device__ __forceinline__ U128 conv_sum(u64 sll, u64 slh, u64 shl, u64 shh) {
 }
 
 // ---------------------------------------------------------------- tensor + INTT blocks
-// Items (limb r, block tile).  r < level: limb r; stores d0, d1 into rl,
-// d2 (NTT form) into d2, and the INTT blocks pass of d2 into y[r].
-// r = level + u (rescale only): recomputes d_u of limb level-1 and writes
-// its INTT blocks pass to y[level + u] (used to rescale by linearity).
+// Items, for r < level, in pairs over (limb r, block tile), kind fastest:
+//   kind 0: d0, d1 of the tile into rl (a plain stream, no transform);
+//   kind 1: d2 (NTT form) into d2 and its INTT blocks pass into y[r].
+// The two items of a tile are adjacent, so they run on one XCD and the
+// second reads a1, a2 from its L2; splitting the tile doubles the waves
+// that hide the memory latency of a grid of about one wave per SIMD.
+// Then, when rescaling, items (level + u, block tile): d_u of limb level-1
+// again, its INTT blocks pass into y[level + u] (rescale by linearity).
 template <int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
@@ -247,9 +251,18 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
   const PairDesc pd = resolve(b, uniform(w), local);
   const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
-  const u32 r = uniform(local / tpl), pos = uniform(local % tpl);
+  const u32 npair = 2 * pd.level * tpl;
+  u32 r, pos, which;  // which: 0, 1 d_u of limb level-1; 2 d2 + transform; 3 d0, d1 stream
+  if (local < npair) {
+    r = uniform((local >> 1) / tpl);
+    pos = uniform((local >> 1) % tpl);
+    which = (local & 1) ? 2 : 3;
+  } else {
+    r = uniform(pd.level + (local - npair) / tpl);
+    pos = uniform((local - npair) % tpl);
+    which = r - pd.level;
+  }
   const u32 i = r < pd.level ? r : pd.level - 1;
-  const u32 which = r < pd.level ? 2 : r - pd.level;
   const u64 tot = (u64)pd.level << c.log_n;
   const ModInfo m = ldc(c.mods + i);
   const u64 blk0 = (u64)pos * PL::SUBS;
@@ -260,11 +273,10 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
     const int e = threadIdx.x + k * THREADS;
     lds[(e >> LOGS) * Gm::SUB + Gm::pad(e & (Gm::S - 1))] = v;
   };
-  // Operands are loaded TG elements at a time before any result is stored,
-  // so each thread keeps 4 TG loads in flight.
+  // Operands are loaded TG elements at a time before any result is stored.
   constexpr int TG = Gm::R < 8 ? Gm::R : 8;
-  if (which == 2) {
-    const auto rl0 = gbl(pd.rl + off), rl1 = gbl(pd.rl + tot + off), d2 = gbl(pd.d2 + off);
+  if (which == 3) {
+    const auto rl0 = gbl(pd.rl + off), rl1 = gbl(pd.rl + tot + off);
     // the products in FP64 for q < 2^50 (exact, see F64A::mulv), else on
     // the integer multipliers; both canonical
     const auto products = [&](auto f64) {
@@ -281,22 +293,50 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
 #pragma unroll
         for (int g = 0; g < TG; ++g) {
           const u64 idx = threadIdx.x + (k0 + g) * THREADS;
-          u64 v0, v1, v;
+          u64 v0, v1;
           if constexpr (F) {
             const double B1 = F64A::in(b1[g], M), A1 = F64A::in(a1[g], M);
             const double B2 = F64A::in(b2[g], M), A2 = F64A::in(a2[g], M);
             v0 = F64A::to_u64(F64A::mulv(B1, B2, M), M);
             v1 = F64A::to_u64(F64A::red(F64A::mulv(A1, B2, M) + F64A::mulv(A2, B1, M), M), M);
-            v = F64A::to_u64(F64A::mulv(A1, A2, M), M);
           } else {
             U128 s1 = mul_wide(a1[g], b2[g]);
             add_to(s1, mul_wide(a2[g], b1[g]));
-            v = barrett(mul_wide(a1[g], a2[g]), m);
             v0 = barrett(mul_wide(b1[g], b2[g]), m);
             v1 = barrett(s1, m);
           }
           rl0[idx] = v0;
           rl1[idx] = v1;
+        }
+      }
+    };
+    if (f64_mod(m.q)) products(std::true_type{});
+    else products(std::false_type{});
+    return;
+  }
+  if (which == 2) {
+    const auto d2 = gbl(pd.d2 + off);
+    constexpr int TA = Gm::R < 16 ? Gm::R : 16;  // two operands: twice the loads in flight
+    const auto products = [&](auto f64) {
+      constexpr bool F = decltype(f64)::value;
+      const F64A::Mod M = F64A::mod(m.q, m.qinv);
+#pragma unroll
+      for (int k0 = 0; k0 < Gm::R; k0 += TA) {
+        u64 a1[TA], a2[TA];
+#pragma unroll
+        for (int g = 0; g < TA; ++g) {
+          const u64 idx = threadIdx.x + (k0 + g) * THREADS;
+          a1[g] = ct1[tot + idx]; a2[g] = ct2[tot + idx];
+        }
+#pragma unroll
+        for (int g = 0; g < TA; ++g) {
+          const u64 idx = threadIdx.x + (k0 + g) * THREADS;
+          u64 v;
+          if constexpr (F) {
+            v = F64A::to_u64(F64A::mulv(F64A::in(a1[g], M), F64A::in(a2[g], M), M), M);
+          } else {
+            v = barrett(mul_wide(a1[g], a2[g]), m);
+          }
           d2[idx] = v;
           put(k0 + g, v);
         }
