@@ -180,7 +180,7 @@ __host__ __device__ constexpr u32 blocks_tiles(u32 log_n, u32 epw = EPW_B) {
 // of 64 / T sub-transforms per wave (T threads per sub-transform).
 constexpr int IP_WAVES = 4;
 __host__ __device__ constexpr u32 ipw_elems(u32 log_n) {
-  return 64u * (1u << ((log_n - log_n / 2) >= 9 ? 5 : ((log_n - log_n / 2) <= 6 ? 3 : 4)));
+  return 64u * (1u << radix_log(log_n - log_n / 2));
 }
 __host__ __device__ constexpr u32 ipw_tiles(u32 log_n) { return (1u << log_n) / ipw_elems(log_n); }
 

@@ -342,10 +342,16 @@ __device__ __forceinline__ void with_arith(u64 q, Body&& body) {
   else body(IntA{});
 }
 
-// Radix per sub-transform size.
+// log2 of the register radix of a 2^logs-point sub-transform.  256 points
+// take three radix-8 rounds rather than two radix-16 rounds: twice the
+// waves per pass, which hides more memory latency in passes of about one
+// wave per SIMD (the passes over one HE Mul's limbs at N = 2^16).
+__host__ __device__ constexpr int radix_log(int logs) {
+  return logs >= 9 ? 5 : (logs <= 6 || logs == 8 ? 3 : 4);
+}
 template <int LOGS>
 struct Radix {
-  static constexpr int LOGR = LOGS >= 9 ? 5 : (LOGS <= 6 ? 3 : 4);
+  static constexpr int LOGR = radix_log(LOGS);
 };
 
 // Workgroup shape of a pass: EPW elements (8*EPW bytes) per workgroup.
@@ -361,7 +367,7 @@ struct PassGeo {
 };
 // threads of a pass workgroup (a plain function so it fits a macro argument)
 constexpr int pass_threads(int logs, int epw) {
-  return (epw >> logs) * ((1 << logs) >> (logs >= 9 ? 5 : (logs <= 6 ? 3 : 4)));
+  return (epw >> logs) * ((1 << logs) >> radix_log(logs));
 }
 template <int LOGS, bool COLS, int EPW = NTT_EPW>
 struct PassLayout {
