@@ -288,7 +288,9 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
 #pragma unroll
         for (int g = 0; g < TG; ++g) {
           const u64 idx = threadIdx.x + (k0 + g) * THREADS;
-          b1[g] = ct1[idx]; a1[g] = ct1[tot + idx]; b2[g] = ct2[idx]; a2[g] = ct2[tot + idx];
+          // b1, b2: read by this item only (a1, a2 again by the d2 item)
+          b1[g] = __builtin_nontemporal_load(&ct1[idx]); a1[g] = ct1[tot + idx];
+          b2[g] = __builtin_nontemporal_load(&ct2[idx]); a2[g] = ct2[tot + idx];
         }
 #pragma unroll
         for (int g = 0; g < TG; ++g) {
@@ -693,7 +695,9 @@ inline int conv_bucket(u32 ns) {
 // dt_j[e] = d2[e] when q_e is in digit j, else the NTT-form mod-up limb.
 // When rescaling, the NTT-form ks_u[level-1] is also copied to limb
 // level+K (it is inverse-transformed with the special limbs).
-// Items (e, coefficient chunk).
+// Items (e, coefficient chunk).  KEY_NT: the key is read by one HE Mul
+// (a single pair), so its loads bypass the caches.
+template <bool KEY_NT>
 __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
@@ -730,9 +734,17 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
       const auto ea = eb + (nm << c.log_n);
 #pragma unroll
       for (int k = 0; k < IP_CPT; ++k) {
-        xv[jj][k] = x[n0 + k];
-        bv[jj][k] = eb[n0 + k];
-        av[jj][k] = ea[n0 + k];
+        // the mod-up limbs (last use) stay out of the caches, and so does
+        // the key when one HE Mul reads it (the pairs of a batch share it):
+        // the caches then keep the intermediates of the stages that follow
+        xv[jj][k] = __builtin_nontemporal_load(&x[n0 + k]);
+        if constexpr (KEY_NT) {
+          bv[jj][k] = __builtin_nontemporal_load(&eb[n0 + k]);
+          av[jj][k] = __builtin_nontemporal_load(&ea[n0 + k]);
+        } else {
+          bv[jj][k] = eb[n0 + k];
+          av[jj][k] = ea[n0 + k];
+        }
       }
     }
 #pragma unroll
@@ -994,8 +1006,9 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 #pragma unroll
       for (int g = 0; g < TG; ++g) {
         const int idx = threadIdx.x + (k0 + g) * THREADS;
-        kv[g] = ksu[idx];
-        dv[g] = rlu[idx];
+        // last reads of ks and d; the output is not read again by the HE Mul
+        kv[g] = __builtin_nontemporal_load(&ksu[idx]);
+        dv[g] = __builtin_nontemporal_load(&rlu[idx]);
       }
 #pragma unroll
       for (int g = 0; g < TG; ++g) {
@@ -1005,7 +1018,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
         if (pd.wrl) rlu[idx] = v;
         if (resc) {
           const u64 S = two ? A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M) : 0;
-          ou[idx] = csub(shoup_lazy(v + m.q - S, qw, qws, m.q), m.q);
+          __builtin_nontemporal_store(csub(shoup_lazy(v + m.q - S, qw, qws, m.q), m.q), &ou[idx]);
         }
       }
     }

@@ -660,7 +660,10 @@ void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) 
     case ST_MU_CONV: launch_conv<false>(conv_bucket((c.L + c.dnum - 1) / c.dnum), c, b, st); break;
     case ST_DT_NCOLS: launch_lcols<true, N1, EC, ST_DT_NCOLS>(c, b, st); break;
     case ST_DT_NBLOCKS: launch_lblocks<true, N2, EB, ST_DT_NBLOCKS>(c, b, st); break;
-    case ST_IP: hipLaunchKernelGGL(k_ip, g, dim3(IP_THREADS), 0, st, c, b); break;
+    case ST_IP:
+      if (b.pairs) hipLaunchKernelGGL(k_ip<false>, g, dim3(IP_THREADS), 0, st, c, b);
+      else hipLaunchKernelGGL(k_ip<true>, g, dim3(IP_THREADS), 0, st, c, b);
+      break;
     case ST_KS_IBLOCKS: launch_lblocks<false, N2, EB, ST_KS_IBLOCKS>(c, b, st); break;
     case ST_BLOCKS_IP: hipLaunchKernelGGL((k_blocks_ip<N2>), g, dim3(64 * IP_WAVES), 0, st, c, b); break;
     case ST_KS_ICOLS: launch_lcols<false, N1, EC, ST_KS_ICOLS>(c, b, st); break;
