@@ -17,7 +17,9 @@
  *   - Full-RNS form (mod up / mod down): Table XI and the Discussion section
  *     ("applicability to other libraries"); the paper only names these
  *     functions, so the formulas below are the standard fast base conversion
- *     of full-RNS CKKS, with the readings listed in the design doc.
+ *     of full-RNS CKKS: non-centred sources, no overflow correction, mod down
+ *     without a rounding offset, rescale rounding to nearest by the centred
+ *     lift of the dropped limb.
  *
  * Parity status: NTT/INTT pinned (closed form, schoolbook convolution,
  * round trip); ModUp, ModDown, rescale pinned by big-integer identities at
