@@ -61,8 +61,8 @@ def lib():
         L.orc_ctx_free.argtypes = [ctypes.c_void_p]
         L.orc_psi.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
         L.orc_psi.restype = ctypes.c_uint64
-        L.orc_twiddles.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
-        L.orc_twiddles.restype = u64p
+        L.orc_powers.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+        L.orc_powers.restype = u64p
         for f in ("orc_ntt", "orc_intt"):
             getattr(L, f).argtypes = [ctypes.c_void_p, ctypes.c_uint32, u64p]
         L.orc_tensor.argtypes = [ctypes.c_void_p, ctypes.c_uint32, u64p, u64p, u64p]
@@ -177,9 +177,10 @@ class Context:
     def psi(self, idx: int) -> int:
         return int(lib().orc_psi(self._h, idx))
 
-    def twiddles(self, idx: int) -> np.ndarray:
-        ptr = lib().orc_twiddles(self._h, idx)
-        return np.ctypeslib.as_array(ptr, shape=(self.N,)).copy()
+    def powers(self, idx: int) -> np.ndarray:
+        """psi^k mod modulus idx for 0 <= k < 2N (the transform's table)."""
+        ptr = lib().orc_powers(self._h, idx)
+        return np.ctypeslib.as_array(ptr, shape=(2 * self.N,)).copy()
 
     # -- transforms (idx indexes q_0..q_{L-1}, p_0..p_{K-1})
     def ntt(self, idx: int, a: np.ndarray) -> np.ndarray:

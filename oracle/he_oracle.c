@@ -9,9 +9,11 @@
  * stored residue is canonical, in [0, m).
  *
  * Paper: "HEAAN Demystified" (arXiv 2003.04510).
- *   - NTT: Algorithm 3 (NTT) with Algorithm 4 (butt), powers of the 2N-th
- *     root of unity indexed TB_W[m+j] (Sec. IV); iNTT: inverse butterflies
- *     with TB_invW and a final division by N (Sec. IV, iNTT paragraph).
+ *   - NTT: the negacyclic transform of Sec. IV (values at the odd powers of
+ *     the 2N-th root psi, bit-reversed order, the map Algorithms 3-4
+ *     compute), written as the recursive Chinese-remainder split of
+ *     X^N + 1; iNTT: each split undone, then a final division by N
+ *     (Sec. IV, iNTT paragraph).
  *   - HE Mul flow: Fig. 2 (region 1 tensor, region 2 key switching with evk,
  *     shift), rescale by division (Sec. III-A).
  *   - Full-RNS form (mod up / mod down): Table XI and the Discussion section
@@ -111,47 +113,59 @@ uint64_t orc_min_root(uint64_t q, uint32_t log_n) {
   return best;
 }
 
-static uint32_t bitrev(uint32_t x, uint32_t bits) {
-  uint32_t r = 0;
-  for (uint32_t i = 0; i < bits; ++i) { r = (r << 1) | (x & 1); x >>= 1; }
-  return r;
+/* ---------- negacyclic NTT by recursive factorisation ---------- */
+/* The forward transform evaluates a in Z_q[X]/(X^N + 1) at the N roots of
+ * X^N + 1, which are the odd powers of psi (Sec. IV, NTT: the negacyclic
+ * transform with the 2N-th root merged in).  It is written here as the
+ * Chinese-remainder split of the modulus polynomial rather than as a loop
+ * nest.  Write the modulus of a node of n coefficients as X^n - psi^E.  With
+ * s = psi^(E/2) it factors as (X^(n/2) - s)(X^(n/2) + s), and for
+ * a = lo + X^(n/2) hi
+ *     a mod (X^(n/2) - s) = lo + s hi,      a mod (X^(n/2) + s) = lo - s hi,
+ * where X^(n/2) + s = X^(n/2) - psi^(E/2 + N) because psi^N = -1.  The root
+ * node is X^N + 1 = X^N - psi^N; a leaf (n = 1) holds a mod (X - psi^E) =
+ * a(psi^E).  Placing the first factor's residue in the first half and the
+ * second's in the second half leaves a(psi^(2 brv(i) + 1)) at position i
+ * (bit-reversed order).  One modular product per coefficient pair and
+ * level: N/2 log N in all, the count of Table IV.
+ * pw[k] = psi^k mod q for 0 <= k < 2N. */
+static void ntt_split(uint64_t* a, uint64_t n, uint64_t E, uint64_t q, const uint64_t* pw, uint64_t N) {
+  if (n < 2) return;
+  uint64_t h = n / 2, s = pw[E / 2];
+  for (uint64_t k = 0; k < h; ++k) {
+    uint64_t t = mmul(s, a[h + k], q);
+    g_ntt_modmul++;
+    uint64_t lo = a[k];
+    a[k] = madd(lo, t, q);
+    a[h + k] = msub(lo, t, q);
+  }
+  ntt_split(a, h, E / 2, q, pw, N);
+  ntt_split(a + h, h, E / 2 + N, q, pw, N);
 }
-
-/* ---------- NTT (Algorithm 3 + Algorithm 4) ---------- */
-/* Forward negacyclic NTT, in place.  tbw[k] = psi^{bitrev(k)}.  Output order
- * is bit-reversed: out[i] = a(psi^{2*bitrev(i)+1}). */
-static void ntt_core(uint64_t* a, uint32_t log_n, uint64_t q, const uint64_t* tbw) {
-  uint64_t N = 1ull << log_n, t = N;
-  for (uint64_t m = 1; m < N; m *= 2) {
-    t /= 2;
-    for (uint64_t j = 0; j < m; ++j) {
-      uint64_t W = tbw[m + j];
-      for (uint64_t k = j * 2 * t; k < j * 2 * t + t; ++k) {
-        /* butt(A, B, W): U = B*W mod q; B = A - U; A = A + U (all mod q) */
-        uint64_t U = mmul(a[k + t], W, q);
-        g_ntt_modmul++;
-        a[k + t] = msub(a[k], U, q);
-        a[k] = madd(a[k], U, q);
-      }
-    }
+/* The inverse undoes each split from the leaves up: from u = lo + s hi and
+ * v = lo - s hi it forms u + v = 2 lo and (u - v) s^(-1) = 2 hi, with
+ * s^(-1) = psi^(2N - E/2).  Every level doubles the values, so the result
+ * is N a, and a final product by N^(-1) gives a: N/2 log N + N modular
+ * products, the iNTT count of Table IV. */
+static void intt_split(uint64_t* a, uint64_t n, uint64_t E, uint64_t q, const uint64_t* pw, uint64_t N) {
+  if (n < 2) return;
+  uint64_t h = n / 2, sinv = pw[2 * N - E / 2];
+  intt_split(a, h, E / 2, q, pw, N);
+  intt_split(a + h, h, E / 2 + N, q, pw, N);
+  for (uint64_t k = 0; k < h; ++k) {
+    uint64_t u = a[k], v = a[h + k];
+    a[k] = madd(u, v, q);
+    a[h + k] = mmul(msub(u, v, q), sinv, q);
+    g_intt_modmul++;
   }
 }
-/* Inverse: the same butterflies undone in reverse stage order
- * (A, B) <- (A + B, (A - B) * W^{-1}), then every element times N^{-1}. */
-static void intt_core(uint64_t* a, uint32_t log_n, uint64_t q, const uint64_t* tbinvw) {
-  uint64_t N = 1ull << log_n, t = 1;
-  for (uint64_t m = N / 2; m >= 1; m /= 2) {
-    for (uint64_t j = 0; j < m; ++j) {
-      uint64_t Wi = tbinvw[m + j];
-      for (uint64_t k = j * 2 * t; k < j * 2 * t + t; ++k) {
-        uint64_t A = a[k], B = a[k + t];
-        a[k] = madd(A, B, q);
-        a[k + t] = mmul(msub(A, B, q), Wi, q);
-        g_intt_modmul++;
-      }
-    }
-    t *= 2;
-  }
+static void ntt_core(uint64_t* a, uint32_t log_n, uint64_t q, const uint64_t* pw) {
+  uint64_t N = 1ull << log_n;
+  ntt_split(a, N, N, q, pw, N);
+}
+static void intt_core(uint64_t* a, uint32_t log_n, uint64_t q, const uint64_t* pw) {
+  uint64_t N = 1ull << log_n;
+  intt_split(a, N, N, q, pw, N);
   uint64_t ninv = minv(N % q, q);
   for (uint64_t i = 0; i < N; ++i) { a[i] = mmul(a[i], ninv, q); g_intt_modmul++; }
 }
@@ -162,8 +176,7 @@ typedef struct {
   uint64_t N;
   uint64_t* mod;    /* [L+K]: q_0..q_{L-1}, p_0..p_{K-1} */
   uint64_t* psi;    /* [L+K] */
-  uint64_t* tbw;    /* [L+K][N] */
-  uint64_t* tbinvw; /* [L+K][N] */
+  uint64_t* pw;     /* [L+K][2N]: psi^k, 0 <= k < 2N */
 } orc_ctx;
 
 orc_ctx* orc_ctx_new(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
@@ -176,34 +189,31 @@ orc_ctx* orc_ctx_new(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, cons
   for (uint32_t i = 0; i < L; ++i) c->mod[i] = q[i];
   for (uint32_t k = 0; k < K; ++k) c->mod[L + k] = p[k];
   c->psi = (uint64_t*)malloc(sizeof(uint64_t) * nm);
-  c->tbw = (uint64_t*)malloc(sizeof(uint64_t) * nm * c->N);
-  c->tbinvw = (uint64_t*)malloc(sizeof(uint64_t) * nm * c->N);
+  c->pw = (uint64_t*)malloc(sizeof(uint64_t) * nm * 2 * c->N);
 #pragma omp parallel for schedule(dynamic)
   for (uint32_t i = 0; i < nm; ++i) {
     uint64_t m = c->mod[i];
-    uint64_t psi = orc_min_root(m, log_n), psii = minv(psi, m);
+    uint64_t psi = orc_min_root(m, log_n);
+    uint64_t* pw = c->pw + (uint64_t)i * 2 * c->N;
     c->psi[i] = psi;
-    for (uint64_t k = 0; k < c->N; ++k) {
-      uint32_t e = bitrev((uint32_t)k, log_n);
-      c->tbw[i * c->N + k] = mpow(psi, e, m);
-      c->tbinvw[i * c->N + k] = mpow(psii, e, m);
-    }
+    pw[0] = 1 % m;
+    for (uint64_t k = 1; k < 2 * c->N; ++k) pw[k] = mmul(pw[k - 1], psi, m);
   }
   return c;
 }
 void orc_ctx_free(orc_ctx* c) {
   if (!c) return;
-  free(c->mod); free(c->psi); free(c->tbw); free(c->tbinvw); free(c);
+  free(c->mod); free(c->psi); free(c->pw); free(c);
 }
 uint64_t orc_psi(const orc_ctx* c, uint32_t idx) { return c->psi[idx]; }
-const uint64_t* orc_twiddles(const orc_ctx* c, uint32_t idx) { return c->tbw + (uint64_t)idx * c->N; }
+const uint64_t* orc_powers(const orc_ctx* c, uint32_t idx) { return c->pw + (uint64_t)idx * 2 * c->N; }
 
 /* NTT / INTT of one limb modulo basis element `idx` (0..L+K-1). */
 void orc_ntt(const orc_ctx* c, uint32_t idx, uint64_t* a) {
-  ntt_core(a, c->log_n, c->mod[idx], c->tbw + (uint64_t)idx * c->N);
+  ntt_core(a, c->log_n, c->mod[idx], c->pw + (uint64_t)idx * 2 * c->N);
 }
 void orc_intt(const orc_ctx* c, uint32_t idx, uint64_t* a) {
-  intt_core(a, c->log_n, c->mod[idx], c->tbinvw + (uint64_t)idx * c->N);
+  intt_core(a, c->log_n, c->mod[idx], c->pw + (uint64_t)idx * 2 * c->N);
 }
 
 /* basis position e of the extended basis E_l = {q_0..q_{l-1}, p_0..p_{K-1}}

@@ -40,6 +40,27 @@ def test_library_prime_search_matches_oracle():
         assert P.workload_primes(w) == oracle.workload_primes(w), w.name
 
 
+def test_library_primality_against_a_sieve():
+    """The library's prime search (its own Baillie-PSW test, written apart
+    from the oracle's Miller-Rabin) lists exactly the primes = 1 mod 4 below
+    2^21 that a sieve finds, strong base-2 pseudoprimes such as 15841,
+    29341, 1373653 among the candidates it must reject."""
+    import numpy as np
+
+    import paper_2003_04510_amd as P
+    n = 1 << 21
+    sieve = np.ones(n, dtype=bool)
+    sieve[:2] = False
+    for i in range(2, int(n ** 0.5) + 1):
+        if sieve[i]:
+            sieve[i * i::i] = False
+    want = [int(x) for x in np.nonzero(sieve)[0][::-1] if x % 4 == 1 and x > 4]
+    got = P.binding.gen_primes(1, 21, len(want))
+    assert got == want
+    for psp in (15841, 29341, 1373653):
+        assert pow(2, psp - 1, psp) == 1 and not sieve[psp] and psp % 4 == 1
+
+
 def test_status_strings_and_argument_errors():
     import paper_2003_04510_amd as P
     lib = P.load_library()

@@ -4,6 +4,7 @@ the paper's operation counts (Table IV)."""
 import json
 import os
 import random
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -178,12 +179,13 @@ def test_ntt_roundtrip_identity(wname):
         assert (ctx.ntt(idx, ctx.intt(idx, a)) == a).all()
 
 
-def test_twiddle_table_is_bitreversed_powers():
+def test_power_table_is_powers_of_psi():
     ctx = _tiny_ctx(log_n=5)
     for idx in (0, ctx.L):
         m, psi = ctx.moduli[idx], ctx.psi(idx)
-        tw = ctx.twiddles(idx)
-        assert [int(x) for x in tw] == [pow(psi, oracle.bitrev(k, 5), m) for k in range(ctx.N)]
+        pw = ctx.powers(idx)
+        assert [int(x) for x in pw] == [pow(psi, k, m) for k in range(2 * ctx.N)]
+        assert int(pw[ctx.N]) == m - 1
 
 
 # ---------------------------------------------------------------- P9 op counts (Table IV)
@@ -227,11 +229,18 @@ def test_tensor_equals_karatsuba_and_definition():
 # ---------------------------------------------------------------- O7 / P4 ModUp
 @pytest.mark.parametrize("level", [5, 4, 1])
 def test_modup_fast_conversion_identity(level):
+    """Fast conversion without overflow correction: with X the exact CRT
+    value of the digit's coefficients and y_i = x_i [(Qt/q_i)^-1]_{q_i},
+    every target limb holds X + u Qt with u = floor(sum_i y_i / q_i), the
+    overflow count of the matrix form of "CRT right after iCRT" (Table XI,
+    Algorithm 6); u is computed here from Python integers, and an exact
+    conversion (u = 0 everywhere) fails the check."""
     ctx = _tiny_ctx(log_n=4, L=5, K=2, dnum=3)
     d2 = synth.uniform_limbs(9, ctx.q[:level], ctx.N)
     dt = ctx.modup(level, d2)
     ext = list(range(level)) + [ctx.L + k for k in range(ctx.K)]
     x = _coef(ctx, d2, list(range(level)))
+    overflow_seen = False
     for j in range(ctx.num_digits(level)):
         D = ctx.digit(j, level)
         Qt = _prod(ctx.q[i] for i in D)
@@ -241,11 +250,17 @@ def test_modup_fast_conversion_identity(level):
             if e in D:
                 assert (dt[j][e] == d2[e]).all()     # own limbs copied in NTT form
         for k in range(ctx.N):
-            us = []
-            for u in range(len(D)):
-                if all(int(z[e][k]) == (X[k] + u * Qt) % ctx.moduli[bi] for e, bi in enumerate(ext) if e not in D):
-                    us.append(u)
-            assert len(us) == 1, (j, k)
+            # y_i in [0, q_i); sum_i y_i Qt/q_i = X + u Qt exactly
+            ys = [int(x[i][k]) * pow(Qt // ctx.q[i] % ctx.q[i], -1, ctx.q[i]) % ctx.q[i] for i in D]
+            u = sum(F * (Qt // ctx.q[i]) for F, i in zip(ys, D)) // Qt
+            assert sum(Fraction(F, ctx.q[i]) for F, i in zip(ys, D)) // 1 == u   # = floor(sum y_i / q_i)
+            assert 0 <= u < len(D)
+            overflow_seen |= u > 0
+            for e, bi in enumerate(ext):
+                if e not in D:
+                    assert int(z[e][k]) == (X[k] + u * Qt) % ctx.moduli[bi], (j, k, e)
+    if level > 1:
+        assert overflow_seen    # the reading "no overflow correction" is visible
 
 
 def test_modup_alpha1_is_plain_reduction():
@@ -265,24 +280,31 @@ def test_modup_alpha1_is_plain_reduction():
 # ---------------------------------------------------------------- O9 / P5 ModDown
 @pytest.mark.parametrize("K", [1, 2])
 def test_moddown_floor_identity(K):
+    """ModDown and the combine with the tensor terms: out_u = d_u + ModDown(ks_u)
+    with ModDown(X) = floor(X / P) - v, v in [0, K) (exactly floor(X / P)
+    when K = 1), for nonzero d so the combine's sign and operand are pinned."""
     ctx = _tiny_ctx(log_n=4, L=4, K=K, dnum=2)
     level = 4
     ext = list(range(level)) + [ctx.L + k for k in range(K)]
     ks = np.stack([synth.uniform_limbs(20 + u, [ctx.moduli[b] for b in ext], ctx.N) for u in range(2)])
-    d = np.zeros((3, level, ctx.N), dtype=np.uint64)
+    d = np.stack([synth.uniform_limbs(40 + u, ctx.q[:level], ctx.N) for u in range(3)])
     out = ctx.moddown_combine(level, ks, d)
     P = _prod(ctx.p)
     QP = _prod(ctx.q[:level]) * P
     Ql = _prod(ctx.q[:level])
+    vs_seen = set()
     for u in range(2):
         X = oracle.crt(_coef(ctx, ks[u], ext), [ctx.moduli[b] for b in ext])
+        D = oracle.crt(_coef(ctx, d[u], list(range(level))), ctx.q[:level])
         o = oracle.crt(_coef(ctx, out[u], list(range(level))), ctx.q[:level])
         for k in range(ctx.N):
-            assert 0 <= X[k] < QP
-            vs = [v for v in range(K) if (X[k] // P - v) % Ql == o[k]]
+            assert 0 <= X[k] < QP and D[k] != 0
+            vs = [v for v in range(K) if (D[k] + X[k] // P - v) % Ql == o[k]]
             assert len(vs) == 1
+            vs_seen.add(vs[0])
             if K == 1:
-                assert o[k] == X[k] // P
+                assert o[k] == (D[k] + X[k] // P) % Ql
+    assert vs_seen <= set(range(K))
 
 
 # ---------------------------------------------------------------- O10 / P6 rescale
