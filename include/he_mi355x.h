@@ -46,7 +46,8 @@ typedef enum he_status {
   HE_ELEVEL = -2,        /* level out of range or mismatched */
   HE_ENOMEM = -3,        /* workspace too small or device allocation failed */
   HE_EDEVICE = -4,       /* a HIP call failed */
-  HE_EUNSUPPORTED = -5   /* parameter combination not implemented */
+  HE_EUNSUPPORTED = -5,  /* parameter combination not implemented */
+  HE_EBUSY = -6          /* a bounded queue is full: retry after progress */
 } he_status;
 
 typedef struct he_ctx he_ctx;
@@ -64,13 +65,22 @@ he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uin
 /* Create a context: moduli q (host, [L]) and p (host, [K]), dnum key-switch
  * digits.  Builds twiddle tables (powers of the smallest primitive 2N-th root
  * in bit-reversed order, with Shoup companions, Algorithms 2-3) and all
- * base-conversion constants on device `device`.  The context owns those
- * tables (freed by he_ctx_destroy).  Constraints: 12 <= log_n <= 17,
+ * base-conversion constants on device `device`.  The tables go to
+ * d_tables, device memory of at least he_ctx_device_bytes(...) bytes that
+ * the caller owns and keeps valid until he_ctx_destroy (HE_ENOMEM if
+ * tables_bytes is smaller); with d_tables = NULL the context allocates them
+ * itself and frees them in he_ctx_destroy.  Constraints: 12 <= log_n <= 17,
  * 1 <= dnum <= min(L, 64) (HE_EINVAL otherwise), digit size ceil(L/dnum)
  * <= 32 and K <= 32 (HE_EUNSUPPORTED above), L <= 64, K special primes
- * whose product exceeds every digit's product.  */
+ * whose product exceeds every digit's product.  Synchronous (the tables are
+ * uploaded before return). */
 he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
-                        const uint64_t* p, int device, he_ctx** out);
+                        const uint64_t* p, int device, void* d_tables, size_t tables_bytes, he_ctx** out);
+/* Device bytes of the tables he_ctx_create builds for these parameters (0 if
+ * they are invalid); he_ctx_table_bytes: the same for an existing context. */
+size_t he_ctx_device_bytes(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                           const uint64_t* p);
+size_t he_ctx_table_bytes(const he_ctx* ctx);
 void he_ctx_destroy(he_ctx* ctx);
 
 /* Sizes in bytes. */
@@ -234,30 +244,44 @@ he_status he_batch_autotune(he_ctx* ctx, he_batch* batch, const uint64_t* d_evk,
 
 /* Serving: a request loop with continuous batching (host side, native).
  * he_server_add_ring registers a context with its resident evk and a
- * workspace arena of arena_bytes (device memory the server allocates; the
- * sum over rings must not exceed cfg->hbm_budget).  he_server_submit queues
- * one HE Mul with rescale (level >= 2) on operands ct1, ct2 [2][level][N]
- * into out [2][level-1][N] (device buffers owned by the caller, untouched
- * until the request completes); the arrival time is taken at submission.
+ * caller-owned device arena d_arena of arena_bytes (256-byte aligned; its
+ * first he_server_arena_min_bytes(cfg) bytes hold batch descriptors, the
+ * rest request workspaces).  Admission by HBM footprint: a ring counts its
+ * context tables (he_ctx_table_bytes), its evk (he_evk_bytes) and its arena,
+ * and the rings together must stay within cfg->hbm_budget (HE_ENOMEM);
+ * a request runs only when its workspace fits the free part of its ring's
+ * arena.  he_server_submit queues one HE Mul with rescale (level >= 2) on
+ * operands ct1, ct2 [2][level][N] into out [2][level-1][N] (device buffers
+ * owned by the caller, untouched until the request completes); the arrival
+ * time is taken at submission; HE_EBUSY when the ring already holds
+ * cfg->max_queue queued requests (0 = unbounded).
  * The server runs on streams of its own that do not wait for any caller
  * stream: ct1 and ct2 must hold their final values when submitted (for
- * example, the caller synchronized the stream that wrote them).
+ * example, the caller synchronized the stream that wrote them), and the
+ * caller keeps all three buffers alive until poll returns the request.
  * he_server_progress never blocks: it retires batches whose work finished
  * and, per ring, admits queued requests in arrival order while their
- * workspace fits the arena (HBM footprint) and at most max_batch per batch,
- * launching each group as one batched HE Mul on the ring's stream while at
- * most max_inflight batches of that ring are in flight.  he_server_poll
- * returns completed request ids with their latency (seconds from
- * submission to the moment progress observed completion).  Errors are
- * he_status codes; a failed launch leaves the request queue untouched. */
+ * workspace fits the arena and at most max_batch per batch, launching each
+ * group as one batched HE Mul on the ring's stream while at most
+ * max_inflight batches of that ring are in flight.  While a batch of the
+ * ring is in flight, a group smaller than max_batch is held back until its
+ * oldest request has waited hold_us microseconds (0: no hold), so that
+ * arrivals coalesce into fuller batches.  he_server_poll returns completed
+ * request ids with their latency (seconds from submission to the moment
+ * progress observed completion).  Errors are he_status codes; a failed
+ * launch leaves the request queue untouched.  The server never allocates
+ * device memory. */
 typedef struct he_server he_server;
 typedef struct he_server_cfg {
-  size_t hbm_budget;     /* bytes of workspace arenas over all rings */
+  size_t hbm_budget;     /* bytes of tables + evks + arenas over all rings */
   uint32_t max_batch;    /* requests per batch */
   uint32_t max_inflight; /* batches in flight per ring */
+  uint32_t max_queue;    /* queued requests per ring before HE_EBUSY (0 = no limit) */
+  uint32_t hold_us;      /* coalescing hold while the ring is busy (0 = none) */
 } he_server_cfg;
 he_status he_server_create(const he_server_cfg* cfg, he_server** out);
-he_status he_server_add_ring(he_server* srv, he_ctx* ctx, const uint64_t* d_evk, size_t arena_bytes,
+size_t he_server_arena_min_bytes(const he_server_cfg* cfg);
+he_status he_server_add_ring(he_server* srv, he_ctx* ctx, const uint64_t* d_evk, void* d_arena, size_t arena_bytes,
                              uint32_t* ring_id);
 he_status he_server_submit(he_server* srv, uint32_t ring, uint64_t id, uint32_t level, const uint64_t* d_ct1,
                            const uint64_t* d_ct2, uint64_t* d_out);
@@ -268,9 +292,41 @@ he_status he_server_stats(const he_server* srv, uint64_t* queued, uint64_t* infl
 void he_server_destroy(he_server* srv);
 
 /* Rescale (Sec. III-A, division by the last prime, rounded to nearest):
- * d_in [2][level][N] -> d_out [2][level-1][N].  level >= 2. */
+ * d_in [2][level][N] -> d_out [2][level-1][N].  level >= 2.  d_out and the
+ * workspace must not overlap d_in or each other (HE_EINVAL): the kernels
+ * read input limbs while other workgroups write output limbs. */
 he_status he_rescale(he_ctx* ctx, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,
                      size_t ws_bytes, he_stream stream);
+
+/* Ciphertext descriptors.  A ciphertext carries its level and its scale
+ * (Sec. III-A: a message m is encrypted as the integer polynomial of
+ * m * scale; a product has scale a.scale * b.scale, and rescaling by the
+ * dropped prime q_{level-1} divides the scale by that prime).  `data` is
+ * device memory [2][level][N] owned by the caller; the scale is metadata
+ * computed in double precision. */
+typedef struct he_ct {
+  uint64_t* data;
+  uint32_t level;
+  double scale;
+} he_ct;
+
+/* Import raw residues: host [2][level][N] (every residue of limb i below
+ * q_i, HE_EINVAL otherwise) into ct->data (device, preset by the caller);
+ * sets ct->level and ct->scale.  Synchronizes `stream`. */
+he_status he_ct_import(he_ctx* ctx, const uint64_t* host, uint32_t level, double scale, he_ct* ct,
+                       he_stream stream);
+/* Export ct's residues to host [2][ct->level][N].  Synchronizes `stream`. */
+he_status he_ct_export(he_ctx* ctx, const he_ct* ct, uint64_t* host, he_stream stream);
+/* he_mul on descriptors: a->level must equal b->level (HE_ELEVEL; the paper
+ * multiplies ciphertexts under the same modulus).  relin and out (either may
+ * be NULL, not both) name caller-owned data; on success relin gets level
+ * a->level and scale a->scale * b->scale, out level a->level - 1 and that
+ * scale divided by q_{level-1}.  Errors and workspace as he_mul. */
+he_status he_mul_ct(he_ctx* ctx, const uint64_t* d_evk, const he_ct* a, const he_ct* b, he_ct* relin, he_ct* out,
+                    void* ws, size_t ws_bytes, he_stream stream);
+/* he_rescale on descriptors: out gets level in->level - 1 and scale
+ * in->scale / q_{in->level - 1}. */
+he_status he_rescale_ct(he_ctx* ctx, const he_ct* in, he_ct* out, void* ws, size_t ws_bytes, he_stream stream);
 
 /* Negacyclic NTT (Algorithm 3) or its inverse of `nlimbs` limbs in place:
  * limb r is taken modulo modulus index first_mod + r.  Output order is
@@ -354,6 +410,18 @@ he_status he_big_mul(he_big_ctx* ctx, uint32_t logq, const uint64_t* d_ct1, cons
  * big_icrt, big_pointwise and big_finish (element-wise work). */
 he_status he_big_timing_enable(he_big_ctx* ctx, int enable);
 he_status he_big_timing_read(he_big_ctx* ctx, he_kernel_stat* out, uint32_t max, uint32_t* n);
+
+/* Diagnostics: measured issue rates of the vector ALU instructions the HE
+ * Mul is made of, in lane-operations per second over the whole device
+ * `device`: rates[0] v_mad_u64_u32 (32x32+64-bit multiply-add, the 64-bit
+ * modular products' building block), rates[1] v_mul_hi_u32, rates[2]
+ * v_mul_lo_u32, rates[3] v_fma_f64 (the FP64 butterflies), rates[4] a
+ * full-rate 32-bit integer instruction (v_lshl_add_u32).  Each kind runs
+ * `blocks` workgroups of 256 threads, 8 independent chains of `iters`
+ * instructions per thread; the best of 4 timed launches counts.  The
+ * measured peaks the per-stage VALU fractions are taken against.
+ * Allocates and frees a small sink buffer; synchronizes `stream`. */
+he_status he_valu_peaks(int device, uint32_t blocks, uint32_t iters, double* rates, he_stream stream);
 
 const char* he_status_str(he_status s);
 const char* he_last_error(void);

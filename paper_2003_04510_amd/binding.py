@@ -26,6 +26,10 @@ class HeError(RuntimeError):
     pass
 
 
+class HeBusy(HeError):
+    """HE_EBUSY: a bounded queue is full; retry after progress()."""
+
+
 class BatchItem(ctypes.Structure):
     _fields_ = [("level", ctypes.c_uint32), ("ct1", vp), ("ct2", vp), ("relin", vp), ("out", vp)]
 
@@ -36,7 +40,12 @@ class BatchSched(ctypes.Structure):
 
 
 class ServerCfg(ctypes.Structure):
-    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
+                ("max_queue", ctypes.c_uint32), ("hold_us", ctypes.c_uint32)]
+
+
+class HeCt(ctypes.Structure):
+    _fields_ = [("data", vp), ("level", ctypes.c_uint32), ("scale", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -55,7 +64,17 @@ def load_library():
     L = ctypes.CDLL(LIB_PATH)
     st = ctypes.c_int
     L.he_gen_primes.argtypes = [u32, u32, u32, u64p, u32, u64p]
-    L.he_ctx_create.argtypes = [u32, u32, u32, u32, u64p, u64p, ctypes.c_int, ctypes.POINTER(vp)]
+    L.he_ctx_create.argtypes = [u32, u32, u32, u32, u64p, u64p, ctypes.c_int, vp, ctypes.c_size_t,
+                                ctypes.POINTER(vp)]
+    L.he_ctx_device_bytes.argtypes = [u32, u32, u32, u32, u64p, u64p]
+    L.he_ctx_device_bytes.restype = ctypes.c_size_t
+    L.he_ctx_table_bytes.argtypes = [vp]
+    L.he_ctx_table_bytes.restype = ctypes.c_size_t
+    L.he_ct_import.argtypes = [vp, u64p, u32, ctypes.c_double, ctypes.POINTER(HeCt), vp]
+    L.he_ct_export.argtypes = [vp, ctypes.POINTER(HeCt), u64p, vp]
+    L.he_mul_ct.argtypes = [vp, vp, ctypes.POINTER(HeCt), ctypes.POINTER(HeCt), ctypes.POINTER(HeCt),
+                            ctypes.POINTER(HeCt), vp, ctypes.c_size_t, vp]
+    L.he_rescale_ct.argtypes = [vp, ctypes.POINTER(HeCt), ctypes.POINTER(HeCt), vp, ctypes.c_size_t, vp]
     L.he_ctx_destroy.argtypes = [vp]
     L.he_ctx_destroy.restype = None
     for f in ("he_ct_bytes", "he_workspace_bytes"):
@@ -85,7 +104,9 @@ def load_library():
     L.he_batch_autotune.argtypes = [vp, vp, vp, u32, vp, ctypes.POINTER(BatchSched),
                                     ctypes.POINTER(ctypes.c_double)]
     L.he_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
-    L.he_server_add_ring.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(u32)]
+    L.he_server_arena_min_bytes.argtypes = [ctypes.POINTER(ServerCfg)]
+    L.he_server_arena_min_bytes.restype = ctypes.c_size_t
+    L.he_server_add_ring.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(u32)]
     L.he_server_submit.argtypes = [vp, u32, ctypes.c_uint64, u32, vp, vp, vp]
     L.he_server_progress.argtypes = [vp, ctypes.POINTER(u32)]
     L.he_server_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), u32,
@@ -109,6 +130,7 @@ def load_library():
     L.he_decode.argtypes = [vp, u32, vp, ctypes.c_double, u32, vp, vp, ctypes.c_size_t, vp]
     L.he_rotate.argtypes = [vp, u32, vp, vp, ctypes.c_int32, vp, vp, ctypes.c_size_t, vp]
     L.he_keygen_rot.argtypes = [vp, i64p, ctypes.c_int32, i64p, u64p, vp, vp, ctypes.c_size_t, vp]
+    L.he_valu_peaks.argtypes = [ctypes.c_int, u32, u32, ctypes.POINTER(ctypes.c_double), vp]
     L.he_status_str.argtypes = [st]
     L.he_status_str.restype = ctypes.c_char_p
     L.he_last_error.restype = ctypes.c_char_p
@@ -117,7 +139,7 @@ def load_library():
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
               "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
               "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_decode", "he_add", "he_rotate",
-              "he_keygen_rot"):
+              "he_keygen_rot", "he_ct_import", "he_ct_export", "he_mul_ct", "he_rescale_ct", "he_valu_peaks"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -126,7 +148,8 @@ def load_library():
 def _check(code: int, what: str):
     if code != 0:
         L = load_library()
-        raise HeError("%s: %s (%s)" % (what, L.he_status_str(code).decode(), L.he_last_error().decode()))
+        msg = "%s: %s (%s)" % (what, L.he_status_str(code).decode(), L.he_last_error().decode())
+        raise (HeBusy if code == -6 else HeError)(msg)
 
 
 def _u64arr(xs):
@@ -162,8 +185,29 @@ def workload_primes(w) -> tuple:
     return q, p
 
 
+VALU_KINDS = ("mad_u64_u32", "mul_hi_u32", "mul_lo_u32", "fma_f64", "int32_full_rate")
+
+
+def valu_peaks(device: int = 0, blocks: int = 8192, iters: int = 2048) -> dict:
+    """Measured issue rates (lane-ops/s over the device) of the VALU
+    instruction kinds in VALU_KINDS (he_valu_peaks)."""
+    import torch
+    out = (ctypes.c_double * len(VALU_KINDS))()
+    st = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    _check(load_library().he_valu_peaks(device, blocks, iters, out, st), "he_valu_peaks")
+    return dict(zip(VALU_KINDS, list(out)))
+
+
 def _ptr(t) -> int:
     return t.data_ptr() if t is not None else None
+
+
+def _host(a, n: int, dtype, name: str):
+    """A contiguous host copy of `a` with exactly n elements of dtype."""
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if arr.size != n:
+        raise HeError("%s: expected %d elements, got %d" % (name, n, arr.size))
+    return arr
 
 
 class Context:
@@ -179,8 +223,14 @@ class Context:
         self.device = device
         qa, qp = _u64arr(self.q)
         pa, pp = _u64arr(self.p)
+        nbytes = int(L.he_ctx_device_bytes(log_n, self.L, self.K, dnum, qp, pp))
+        if nbytes == 0:
+            raise HeError("he_ctx_device_bytes: invalid parameters")
+        # the context's constant tables live in torch memory the binding owns
+        self._tables = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=torch.device("cuda", device))
         h = vp()
-        _check(L.he_ctx_create(log_n, self.L, self.K, dnum, qp, pp, device, ctypes.byref(h)), "he_ctx_create")
+        _check(L.he_ctx_create(log_n, self.L, self.K, dnum, qp, pp, device, vp(self._tables.data_ptr()),
+                               self._tables.numel() * 8, ctypes.byref(h)), "he_ctx_create")
         self._h = h
         self._ws = {}
 
@@ -214,11 +264,37 @@ class Context:
     def evk_bytes(self):
         return int(load_library().he_evk_bytes(self._h))
 
+    def table_bytes(self):
+        return int(load_library().he_ctx_table_bytes(self._h))
+
     def workspace_bytes(self, level):
         return int(load_library().he_workspace_bytes(self._h, level))
 
     def empty(self, *shape):
         return self.torch.empty(shape, dtype=self.torch.int64, device=self.dev)
+
+    def _dev(self, t, words: int, name: str, dtype=None):
+        """Check that t can be handed to the library as `words` 8-byte
+        elements: a contiguous tensor on this context's GPU, of dtype int64
+        (or `dtype`), with at least that many elements.  Raises HeError
+        before any library call."""
+        dtype = self.torch.int64 if dtype is None else dtype
+        if t is None:
+            raise HeError("%s: missing tensor" % name)
+        if not t.is_cuda or t.device.index != self.dev.index:
+            raise HeError("%s: tensor must live on cuda:%d" % (name, self.device))
+        if t.dtype != dtype:
+            raise HeError("%s: dtype %s, expected %s" % (name, t.dtype, dtype))
+        if not t.is_contiguous():
+            raise HeError("%s: tensor must be contiguous" % name)
+        if t.numel() < words:
+            raise HeError("%s: %d elements, need at least %d" % (name, t.numel(), words))
+        return vp(t.data_ptr())
+
+    def _ct(self, t, level: int, name: str):
+        if level > self.L:
+            raise HeError("%s: level %d not in [1, L = %d]" % (name, level, self.L))
+        return self._dev(t, 2 * max(level, 0) * self.N, name)
 
     def workspace(self, level):
         """A cached workspace tensor large enough for `level`."""
@@ -241,26 +317,27 @@ class Context:
     def keygen(self, s, e_pk, e_evk, a_pk, a_evk):
         """Keys from supplied random draws -> (pk [2][L][N], evk [dnum][2][L+K][N]) on the GPU."""
         L = load_library()
-        pk = self.empty(2, self.L, self.N)
-        evk = self.empty(self.dnum, 2, self.L + self.K, self.N)
+        N, nm = self.N, self.L + self.K
+        pk = self.empty(2, self.L, N)
+        evk = self.empty(self.dnum, 2, nm, N)
         ws = self.workspace(self.L)
-        s_, sp = _i64(s)
-        e_, ep = _i64(e_pk)
-        ee_, eep = _i64(e_evk)
-        ap_ = np.ascontiguousarray(a_pk, dtype=np.uint64)
-        ae_ = np.ascontiguousarray(a_evk, dtype=np.uint64)
-        _check(L.he_keygen(self._h, sp, ep, ap_.ctypes.data_as(u64p), eep, ae_.ctypes.data_as(u64p),
-                           vp(pk.data_ptr()), vp(evk.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8,
-                           self._stream()), "he_keygen")
+        s_ = _host(s, N, np.int64, "keygen: s")
+        e_ = _host(e_pk, N, np.int64, "keygen: e_pk")
+        ee_ = _host(e_evk, self.dnum * N, np.int64, "keygen: e_evk")
+        ap_ = _host(a_pk, self.L * N, np.uint64, "keygen: a_pk")
+        ae_ = _host(a_evk, self.dnum * nm * N, np.uint64, "keygen: a_evk")
+        _check(L.he_keygen(self._h, s_.ctypes.data_as(i64p), e_.ctypes.data_as(i64p), ap_.ctypes.data_as(u64p),
+                           ee_.ctypes.data_as(i64p), ae_.ctypes.data_as(u64p), vp(pk.data_ptr()),
+                           vp(evk.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_keygen")
         return pk, evk
 
     def encrypt(self, level, m, v, e0, e1, pk):
         ct = self.empty(2, level, self.N)
         ws = self.workspace(level)
-        arrs = [_i64(x) for x in (m, v, e0, e1)]
-        _check(load_library().he_encrypt(self._h, level, arrs[0][1], arrs[1][1], arrs[2][1], arrs[3][1],
-                                         vp(pk.data_ptr()), vp(ct.data_ptr()), vp(ws.data_ptr()),
-                                         ws.numel() * 8, self._stream()), "he_encrypt")
+        arrs = [_host(x, self.N, np.int64, "encrypt: " + nm) for x, nm in ((m, "m"), (v, "v"), (e0, "e0"), (e1, "e1"))]
+        _check(load_library().he_encrypt(self._h, level, *[x.ctypes.data_as(i64p) for x in arrs],
+                                         self._dev(pk, 2 * self.L * self.N, "encrypt: pk"), vp(ct.data_ptr()),
+                                         vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_encrypt")
         return ct
 
     def encode(self, z, scale: float):
@@ -275,21 +352,25 @@ class Context:
 
     def keygen_rot(self, s, rot: int, e_rk, a_rk):
         """Rotation key of `rot` slots from supplied draws -> [dnum][2][L+K][N] on the GPU."""
-        rk = self.empty(self.dnum, 2, self.L + self.K, self.N)
+        N, nm = self.N, self.L + self.K
+        rk = self.empty(self.dnum, 2, nm, N)
         ws = self.workspace(self.L)
-        s_, sp = _i64(s)
-        e_, ep = _i64(e_rk)
-        a_ = np.ascontiguousarray(a_rk, dtype=np.uint64)
-        _check(load_library().he_keygen_rot(self._h, sp, int(rot), ep, a_.ctypes.data_as(u64p), vp(rk.data_ptr()),
-                                            vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_keygen_rot")
+        s_ = _host(s, N, np.int64, "keygen_rot: s")
+        e_ = _host(e_rk, self.dnum * N, np.int64, "keygen_rot: e_rk")
+        a_ = _host(a_rk, self.dnum * nm * N, np.uint64, "keygen_rot: a_rk")
+        _check(load_library().he_keygen_rot(self._h, s_.ctypes.data_as(i64p), int(rot), e_.ctypes.data_as(i64p),
+                                            a_.ctypes.data_as(u64p), vp(rk.data_ptr()), vp(ws.data_ptr()),
+                                            ws.numel() * 8, self._stream()), "he_keygen_rot")
         return rk
 
     def rotate(self, level, ct, rk, rot: int, out=None, ws=None):
         out = self.empty(2, level, self.N) if out is None else out
         ws = self.workspace(level) if ws is None else ws
-        _check(load_library().he_rotate(self._h, level, vp(ct.data_ptr()), vp(rk.data_ptr()), int(rot),
-                                        vp(out.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8, self._stream()),
-               "he_rotate")
+        _check(load_library().he_rotate(self._h, level, self._ct(ct, level, "rotate: ct"),
+                                        self._dev(rk, self.evk_bytes() // 8, "rotate: rk"), int(rot),
+                                        self._ct(out, level, "rotate: out"),
+                                        self._dev(ws, self.workspace_bytes(level) // 8, "rotate: workspace"),
+                                        ws.numel() * 8, self._stream()), "he_rotate")
         return out
 
     def decode(self, level, m_limbs, scale: float, n: int = None):
@@ -297,22 +378,24 @@ class Context:
         n = self.N // 2 if n is None else n
         z = self.torch.empty(2 * max(n, 1), dtype=self.torch.float64, device=self.dev)
         ws = self.workspace(level)
-        _check(load_library().he_decode(self._h, level, vp(m_limbs.data_ptr()), float(scale), n, vp(z.data_ptr()),
-                                        vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_decode")
+        _check(load_library().he_decode(self._h, level, self._dev(m_limbs, level * self.N, "decode: m"), float(scale),
+                                        n, vp(z.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8, self._stream()),
+               "he_decode")
         return z.cpu().numpy()[:2 * n].view(np.complex128)
 
     def add(self, level, ct1, ct2, out=None):
         out = self.empty(2, level, self.N) if out is None else out
-        _check(load_library().he_add(self._h, level, vp(ct1.data_ptr()), vp(ct2.data_ptr()), vp(out.data_ptr()),
-                                     self._stream()), "he_add")
+        _check(load_library().he_add(self._h, level, self._ct(ct1, level, "add: ct1"), self._ct(ct2, level, "add: ct2"),
+                                     self._ct(out, level, "add: out"), self._stream()), "he_add")
         return out
 
     def decrypt_limbs(self, level, ct, s):
         out = self.empty(level, self.N)
         ws = self.workspace(level)
-        s_, sp = _i64(s)
-        _check(load_library().he_decrypt(self._h, level, vp(ct.data_ptr()), sp, vp(out.data_ptr()),
-                                         vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_decrypt")
+        s_ = _host(s, self.N, np.int64, "decrypt: s")
+        _check(load_library().he_decrypt(self._h, level, self._ct(ct, level, "decrypt: ct"), s_.ctypes.data_as(i64p),
+                                         vp(out.data_ptr()), vp(ws.data_ptr()), ws.numel() * 8, self._stream()),
+               "he_decrypt")
         return out
 
     def he_mul(self, level, ct1, ct2, evk, relin=True, rescale=True, ws=None, out_relin=None, out=None):
@@ -322,18 +405,67 @@ class Context:
         if rescale and out is None:
             out = self.empty(2, max(level - 1, 1), self.N)
         ws = self.workspace(level) if ws is None else ws
-        _check(load_library().he_mul(self._h, level, vp(ct1.data_ptr()), vp(ct2.data_ptr()),
-                                     vp(evk.data_ptr()), vp(_ptr(out_relin) if relin else None),
-                                     vp(_ptr(out) if rescale else None), vp(ws.data_ptr()), ws.numel() * 8,
+        _check(load_library().he_mul(self._h, level, self._ct(ct1, level, "he_mul: ct1"),
+                                     self._ct(ct2, level, "he_mul: ct2"),
+                                     self._dev(evk, self.evk_bytes() // 8, "he_mul: evk"),
+                                     self._ct(out_relin, level, "he_mul: relin") if relin else None,
+                                     self._ct(out, level - 1, "he_mul: out") if rescale else None,
+                                     self._dev(ws, self.workspace_bytes(level) // 8, "he_mul: workspace"), ws.numel() * 8,
                                      self._stream()), "he_mul")
         return (out_relin if relin else None), (out if rescale else None)
 
     def rescale(self, level, ct, out=None):
         out = self.empty(2, max(level - 1, 1), self.N) if out is None else out
         ws = self.workspace(level)
-        _check(load_library().he_rescale(self._h, level, vp(ct.data_ptr()), vp(out.data_ptr()),
-                                         vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_rescale")
+        _check(load_library().he_rescale(self._h, level, self._ct(ct, level, "rescale: ct"),
+                                         self._ct(out, level - 1, "rescale: out"), vp(ws.data_ptr()),
+                                         ws.numel() * 8, self._stream()), "he_rescale")
         return out
+
+    # ---------------------------------------------------------- ciphertext descriptors
+    def ct_import(self, host, level: int, scale: float):
+        """Host residues [2][level][N] -> Ciphertext on the GPU (he_ct_import)."""
+        h = _host(host, 2 * level * self.N, np.uint64, "ct_import: host")
+        data = self.empty(2, level, self.N)
+        ct = HeCt(data.data_ptr(), 0, 0.0)
+        _check(load_library().he_ct_import(self._h, h.ctypes.data_as(u64p), level, float(scale), ctypes.byref(ct),
+                                           self._stream()), "he_ct_import")
+        return Ciphertext(data, ct.level, ct.scale)
+
+    def ct_export(self, c: "Ciphertext") -> np.ndarray:
+        """Ciphertext -> host residues [2][level][N] (he_ct_export)."""
+        out = np.empty((2, c.level, self.N), dtype=np.uint64)
+        ct = HeCt(self._ct(c.data, c.level, "ct_export").value, c.level, c.scale)
+        _check(load_library().he_ct_export(self._h, ctypes.byref(ct), out.ctypes.data_as(u64p), self._stream()),
+               "he_ct_export")
+        return out
+
+    def mul_ct(self, a: "Ciphertext", b: "Ciphertext", evk, relin: bool = True, rescale: bool = True):
+        """he_mul_ct: returns (relinearized Ciphertext or None, rescaled Ciphertext or None)."""
+        lv = a.level
+        ws = self.workspace(lv)
+        ca = HeCt(self._ct(a.data, lv, "mul_ct: a").value, a.level, a.scale)
+        cb = HeCt(self._ct(b.data, b.level, "mul_ct: b").value, b.level, b.scale)
+        r_t = self.empty(2, lv, self.N) if relin else None
+        o_t = self.empty(2, max(lv - 1, 1), self.N) if rescale else None
+        cr = HeCt(r_t.data_ptr(), 0, 0.0) if relin else None
+        co = HeCt(o_t.data_ptr(), 0, 0.0) if rescale else None
+        _check(load_library().he_mul_ct(self._h, self._dev(evk, self.evk_bytes() // 8, "mul_ct: evk"),
+                                        ctypes.byref(ca), ctypes.byref(cb),
+                                        ctypes.byref(cr) if cr is not None else None,
+                                        ctypes.byref(co) if co is not None else None,
+                                        vp(ws.data_ptr()), ws.numel() * 8, self._stream()), "he_mul_ct")
+        return (Ciphertext(r_t, cr.level, cr.scale) if relin else None,
+                Ciphertext(o_t, co.level, co.scale) if rescale else None)
+
+    def rescale_ct(self, c: "Ciphertext"):
+        ws = self.workspace(c.level)
+        out = self.empty(2, max(c.level - 1, 1), self.N)
+        ci = HeCt(self._ct(c.data, c.level, "rescale_ct").value, c.level, c.scale)
+        co = HeCt(out.data_ptr(), 0, 0.0)
+        _check(load_library().he_rescale_ct(self._h, ctypes.byref(ci), ctypes.byref(co), vp(ws.data_ptr()),
+                                            ws.numel() * 8, self._stream()), "he_rescale_ct")
+        return Ciphertext(out, co.level, co.scale)
 
     def timing(self, enable: bool, only: str = None):
         """Bracket library kernels with HIP events (all kinds, or only `only`)."""
@@ -354,10 +486,20 @@ class Context:
 
     def ntt(self, data, first_mod: int, inverse: bool = False):
         """In-place transform of data [nlimbs][N]; limb r modulo modulus first_mod + r."""
+        if data.numel() % self.N:
+            raise HeError("ntt: size is not a multiple of N")
         nl = data.numel() // self.N
-        _check(load_library().he_ntt(self._h, vp(data.data_ptr()), nl, first_mod, int(inverse), self._stream()),
-               "he_ntt")
+        _check(load_library().he_ntt(self._h, self._dev(data, nl * self.N, "ntt: data"), nl, first_mod, int(inverse),
+                                     self._stream()), "he_ntt")
         return data
+
+
+class Ciphertext:
+    """A ciphertext on the GPU: data [2][level][N] (int64 tensor holding the
+    uint64 residues), its level and its scale (he_ct)."""
+
+    def __init__(self, data, level: int, scale: float):
+        self.data, self.level, self.scale = data, int(level), float(scale)
 
 
 class Batch:
@@ -370,8 +512,10 @@ class Batch:
         self.items = list(items)
         arr = (BatchItem * len(self.items))()
         for i, (level, ct1, ct2, relin, out) in enumerate(self.items):
-            arr[i] = BatchItem(level, ct1.data_ptr(), ct2.data_ptr(), relin.data_ptr() if relin is not None else None,
-                               out.data_ptr() if out is not None else None)
+            tag = "batch item %d" % i
+            arr[i] = BatchItem(level, ctx._ct(ct1, level, tag + " ct1").value, ctx._ct(ct2, level, tag + " ct2").value,
+                               ctx._ct(relin, level, tag + " relin").value if relin is not None else None,
+                               ctx._ct(out, level - 1, tag + " out").value if out is not None else None)
         self._arr = arr
         nbytes = int(L.he_batch_workspace_bytes(ctx._h, arr, len(self.items)))
         if nbytes == 0:
@@ -383,7 +527,8 @@ class Batch:
         self._h = h
 
     def run(self, evk, use_graph: bool = False):
-        _check(load_library().he_mul_batch(self.ctx._h, self._h, vp(evk.data_ptr()), int(use_graph),
+        _check(load_library().he_mul_batch(self.ctx._h, self._h,
+                                           self.ctx._dev(evk, self.ctx.evk_bytes() // 8, "batch: evk"), int(use_graph),
                                            self.ctx._stream()), "he_mul_batch")
 
     def set_sched(self, cols_tile: int, blocks_tile: int, chunks: int, ip_fused: int = 0):
@@ -400,7 +545,9 @@ class Batch:
         """Time every candidate schedule (graph replays) and keep the
         fastest; returns (schedule, ms per replay)."""
         sc, ms = BatchSched(), ctypes.c_double()
-        _check(load_library().he_batch_autotune(self.ctx._h, self._h, vp(evk.data_ptr()), reps, self.ctx._stream(),
+        _check(load_library().he_batch_autotune(self.ctx._h, self._h,
+                                                self.ctx._dev(evk, self.ctx.evk_bytes() // 8, "autotune: evk"), reps,
+                                                self.ctx._stream(),
                                                 ctypes.byref(sc), ctypes.byref(ms)), "he_batch_autotune")
         return ({"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks,
                  "ip_fused": sc.ip_fused}, ms.value)
@@ -418,26 +565,44 @@ class Batch:
 
 
 class Server:
-    """Continuous-batching HE Mul server (the loop runs in the native library)."""
+    """Continuous-batching HE Mul server (the loop runs in the native library).
+    The binding allocates each ring's arena (torch memory) and keeps every
+    request's tensors alive until poll() has returned the request."""
 
-    def __init__(self, hbm_budget: int, max_batch: int = 64, max_inflight: int = 2):
+    def __init__(self, hbm_budget: int, max_batch: int = 64, max_inflight: int = 2, max_queue: int = 0,
+                 hold_us: int = 0):
         L = load_library()
         h = vp()
-        cfg = ServerCfg(hbm_budget, max_batch, max_inflight)
-        _check(L.he_server_create(ctypes.byref(cfg), ctypes.byref(h)), "he_server_create")
+        self._cfg = ServerCfg(hbm_budget, max_batch, max_inflight, max_queue, hold_us)
+        _check(L.he_server_create(ctypes.byref(self._cfg), ctypes.byref(h)), "he_server_create")
         self._h = h
         self._keep = []
+        self._rings = []
+        self._live = {}
+
+    def arena_min_bytes(self) -> int:
+        return int(load_library().he_server_arena_min_bytes(ctypes.byref(self._cfg)))
 
     def add_ring(self, ctx: "Context", evk, arena_bytes: int) -> int:
+        ev = ctx._dev(evk, ctx.evk_bytes() // 8, "add_ring: evk")
+        arena = ctx.empty((int(arena_bytes) + 7) // 8)
         rid = u32(0)
-        _check(load_library().he_server_add_ring(self._h, ctx._h, vp(evk.data_ptr()), arena_bytes, ctypes.byref(rid)),
-               "he_server_add_ring")
-        self._keep.append((ctx, evk))
+        _check(load_library().he_server_add_ring(self._h, ctx._h, ev, vp(arena.data_ptr()), arena.numel() * 8,
+                                                 ctypes.byref(rid)), "he_server_add_ring")
+        self._keep.append((ctx, evk, arena))
+        self._rings.append(ctx)
         return rid.value
 
     def submit(self, ring: int, rid: int, level: int, ct1, ct2, out):
-        _check(load_library().he_server_submit(self._h, ring, rid, level, vp(ct1.data_ptr()), vp(ct2.data_ptr()),
-                                               vp(out.data_ptr())), "he_server_submit")
+        if ring >= len(self._rings):
+            raise HeError("submit: unknown ring %d" % ring)
+        if rid in self._live:
+            raise HeError("submit: request id %d is still in flight" % rid)
+        ctx = self._rings[ring]
+        _check(load_library().he_server_submit(self._h, ring, rid, level, ctx._ct(ct1, level, "submit: ct1"),
+                                               ctx._ct(ct2, level, "submit: ct2"),
+                                               ctx._ct(out, level - 1, "submit: out")), "he_server_submit")
+        self._live[rid] = (ct1, ct2, out)
 
     def progress(self) -> int:
         n = u32(0)
@@ -449,7 +614,10 @@ class Server:
         lat = (ctypes.c_double * maxn)()
         n = u32(0)
         _check(load_library().he_server_poll(self._h, ids, lat, maxn, ctypes.byref(n)), "he_server_poll")
-        return [(ids[i], lat[i]) for i in range(n.value)]
+        done = [(ids[i], lat[i]) for i in range(n.value)]
+        for k, _ in done:
+            self._live.pop(k, None)
+        return done
 
     def stats(self) -> dict:
         v = [ctypes.c_uint64(0) for _ in range(4)]
@@ -458,8 +626,9 @@ class Server:
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().he_server_destroy(self._h)
+            load_library().he_server_destroy(self._h)   # waits for the rings' streams
             self._h = None
+            self._live.clear()
 
     def __del__(self):
         try:

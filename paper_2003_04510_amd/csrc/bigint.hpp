@@ -7,23 +7,25 @@
 // (consecutive coefficients) read consecutive addresses.  RNS form is
 // limb-major, [np][N].
 //
-//   k_big_crt    BigInt -> RNS in matrix form (Sec. IV-A, "GPU-C"): the
-//                coefficient is cut into 28-bit digits d_h and
-//                x mod p = sum_h d_h [2^(28h)]_p, accumulated as two 64-bit
-//                sums of 28x30-bit products (no carries for <= 64 digits),
-//                one reduction per prime.
+//   k_big_crt    BigInt -> RNS in matrix form (Sec. IV-A, "GPU-C") on the
+//                int8 matrix cores (v_mfma_i32_16x16x32_i8): x mod p_i =
+//                sum_h u_h [2^(8h)]_{p_i} over the bytes u_h of x, with
+//                rows = coefficients, k = bytes (offset binary u - 128) and
+//                columns = (prime, digit) for the balanced base-256 digits
+//                of the constants; per (coefficient, prime) the digit
+//                columns are recombined in 128 bits and reduced once.
 //   k_big_mul    element-wise products of NTT-form limbs.
-//   k_big_icrt   RNS -> BigInt in matrix form (Algorithm 6): with
-//                y_i = [x_i (M/p_i)^-1]_{p_i} (folded into the inverse NTT's
-//                scale), X = sum_i y_i (M/p_i) - k M, k = round(sum_i y_i/p_i)
-//                (the centred value), only modulo 2^(32 C): the products of
-//                y (two 32-bit halves) with the 32-bit words of (M/p_i) are
-//                summed column by column (product scanning, eight columns
-//                per pass over the primes, y staged in LDS) in 64 bits plus
-//                a 32-bit carry count, so no partial product is ever stored.
-//                The output is a bit field of X: bits [shift, shift + outbits)
-//                with optional round-half-up at bit shift - 1 (region 2's
-//                shift by log Q).
+//   k_big_icrt   RNS -> BigInt in matrix form (Algorithm 6), also an int8
+//                matrix-core product: with y_i = [x_i (M/p_i)^-1]_{p_i}
+//                (folded into the inverse NTT's scale), X = sum_i y_i (M/p_i)
+//                - k M, k = round(sum_i y_i / p_i) in FP64, only modulo
+//                2^(32 C): k = (prime, byte of y), columns = byte positions,
+//                B a Toeplitz expansion of the balanced bytes of M/p_i staged
+//                per 16-column tile in LDS; byte columns are folded four at a
+//                time into 32-bit words and carried serially per
+//                coefficient.  The output is a bit field of X: bits
+//                [shift, shift + outbits) with optional round-half-up at bit
+//                shift - 1 (region 2's shift by log Q).
 //   k_big_finish the additions of HE Mul (c3) and the optional rescale by 2^logp.
 #pragma once
 #include "modarith.hpp"

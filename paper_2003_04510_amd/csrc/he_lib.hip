@@ -18,6 +18,7 @@
 #include "ntt.hpp"
 #include "fused.hpp"
 #include "rns_kernels.hpp"
+#include "ubench.hpp"
 
 using namespace he;
 
@@ -35,6 +36,14 @@ he_status fail(he_status s, const char* fmt, ...) {
   return s;
 }
 
+}  // namespace
+
+// Error message of a failing call, for the other translation units of the
+// library (the serving loop).
+void he_set_last_error(const char* msg) { g_err = msg ? msg : ""; }
+
+namespace {
+
 #define HIP_TRY(x)                                                                   \
   do {                                                                               \
     hipError_t e_ = (x);                                                             \
@@ -43,13 +52,20 @@ he_status fail(he_status s, const char* fmt, ...) {
                   __FILE__, __LINE__);                                               \
   } while (0)
 
-// Host-side builder for one device blob of constant tables.
+// Host-side builder for one device blob of constant tables.  With `sizing`
+// set it only accounts for the layout (offsets and total size), so the size
+// query needs neither the tables nor their memory.
 struct Blob {
+  bool sizing = false;
+  size_t size = 0;
   std::vector<uint8_t> bytes;
   size_t add(const void* p, size_t n) {
-    size_t off = (bytes.size() + 255) & ~size_t(255);
-    bytes.resize(off + n);
-    if (n) memcpy(bytes.data() + off, p, n);
+    const size_t off = (size + 255) & ~size_t(255);
+    size = off + n;
+    if (!sizing) {
+      bytes.resize(size);
+      if (n && p) memcpy(bytes.data() + off, p, n);
+    }
     return off;
   }
   template <class T>
@@ -98,6 +114,8 @@ struct he_ctx {
   std::vector<u64> mod;        // [L+K]
   std::vector<u64> pmod_host;  // [P]_{m} for every modulus m
   uint8_t* blob = nullptr;     // device constant tables
+  size_t blob_bytes = 0;
+  bool owns_blob = true;       // false: caller-provided table memory
   // device pointers into blob
   const ModInfo* mods = nullptr;
   const Tw2 *tw = nullptr, *itw = nullptr;
@@ -270,6 +288,7 @@ const char* he_status_str(he_status s) {
     case HE_ENOMEM: return "insufficient memory or workspace";
     case HE_EDEVICE: return "device error";
     case HE_EUNSUPPORTED: return "unsupported";
+    case HE_EBUSY: return "busy";
   }
   return "unknown";
 }
@@ -322,10 +341,17 @@ he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uin
   return HE_OK;
 }
 
-he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
-                        const uint64_t* p, int device, he_ctx** out) {
-  if (!out || !q || !p) return fail(HE_EINVAL, "he_ctx_create: null pointer");
-  *out = nullptr;
+}  // extern "C"
+
+// Validates the parameters and lays out (sizing) or builds the context's
+// constant tables.  sizing: only *table_bytes is produced.  Otherwise the
+// tables go to d_tables (caller-owned, at least table_bytes long) or, when
+// d_tables is null, to device memory the context allocates and owns.
+static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                          const uint64_t* p, int device, bool sizing, void* d_tables, size_t tables_bytes,
+                          size_t* table_bytes, he_ctx** out) {
+  if ((!out && !sizing) || !q || !p) return fail(HE_EINVAL, "he_ctx_create: null pointer");
+  if (out) *out = nullptr;
   if (log_n < 12 || log_n > 17) return fail(HE_EUNSUPPORTED, "log_n must be in [12, 17]");
   if (L < 1 || L > 64 || K < 1 || K > 32 || dnum < 1 || dnum > L || dnum > (u32)MAX_DIGITS)
     return fail(HE_EINVAL, "need 1 <= dnum <= min(L, %d), L <= 64, 1 <= K <= 32", MAX_DIGITS);
@@ -366,10 +392,11 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   // moduli
   std::vector<ModInfo> mi(nm);
   for (u32 i = 0; i < nm; ++i) mi[i] = make_modinfo(c->mod[i], N);
+  B.sizing = sizing;
   const size_t o_mods = B.add(mi);
   // twiddles: TB_W[k] = psi^bitrev(k), TB_invW[k] = psi^-bitrev(k), + Shoup companions
-  std::vector<Tw2> tw(nm * N), itw(nm * N);
-  for (u32 i = 0; i < nm; ++i) {
+  std::vector<Tw2> tw(sizing ? 0 : nm * N), itw(sizing ? 0 : nm * N);
+  for (u32 i = 0; i < nm && !sizing; ++i) {
     const u64 m = c->mod[i];
     const u64 psi = min_root_2n(m, log_n), psii = invmod(psi, m);
     std::vector<u64> pw(N), ipw(N);
@@ -384,7 +411,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     tw_fill(tw.data() + i * N, bw, m, N);
     tw_fill(itw.data() + i * N, ibw, m, N);
   }
-  const size_t o_tw = B.add(tw), o_itw = B.add(itw);
+  const size_t o_tw = B.add(tw.data(), nm * N * sizeof(Tw2)), o_itw = B.add(itw.data(), nm * N * sizeof(Tw2));
   const size_t o_iota = B.add(all_idx);
   // ModDown constants (level independent)
   std::vector<u64> spec_scale(2 * K), pinv(2 * L), pm(nm);
@@ -505,8 +532,20 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
     (void)md;
   }
 
+  if (sizing) {
+    *table_bytes = B.size;
+    return HE_OK;
+  }
   HIP_TRY(hipSetDevice(device));
-  HIP_TRY(hipMalloc(&c->blob, B.bytes.size()));
+  if (d_tables) {
+    if (tables_bytes < B.size)
+      return fail(HE_ENOMEM, "he_ctx_create: table memory of %zu bytes, need %zu", tables_bytes, B.size);
+    c->blob = (uint8_t*)d_tables;
+    c->owns_blob = false;
+  } else {
+    HIP_TRY(hipMalloc(&c->blob, B.size));
+  }
+  c->blob_bytes = B.size;
   for (u32 lvl = 1; lvl <= L; ++lvl) {
     LevelPlan& P = c->lv[lvl];
     uint8_t* d = c->blob;
@@ -526,10 +565,7 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   }
   {
     hipError_t e = hipMemcpy(c->blob, B.bytes.data(), B.bytes.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(c->blob);
-      return fail(HE_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return fail(HE_EDEVICE, "table upload failed: %s", hipGetErrorString(e));
   }
   uint8_t* b = c->blob;
   c->mods = (const ModInfo*)(b + o_mods);
@@ -556,6 +592,23 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   return HE_OK;
 }
 
+extern "C" {
+
+size_t he_ctx_device_bytes(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                           const uint64_t* p) {
+  size_t n = 0;
+  if (ctx_make(log_n, L, K, dnum, q, p, 0, true, nullptr, 0, &n, nullptr) != HE_OK) return 0;
+  return n;
+}
+
+he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                        const uint64_t* p, int device, void* d_tables, size_t tables_bytes, he_ctx** out) {
+  if (!out) return fail(HE_EINVAL, "he_ctx_create: null pointer");
+  return ctx_make(log_n, L, K, dnum, q, p, device, false, d_tables, tables_bytes, nullptr, out);
+}
+
+size_t he_ctx_table_bytes(const he_ctx* c) { return c ? c->blob_bytes : 0; }
+
 void he_ctx_destroy(he_ctx* c) {
   if (!c) return;
   for (auto& r : c->trecs) {
@@ -563,7 +616,7 @@ void he_ctx_destroy(he_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->tpool) (void)hipEventDestroy(e);
-  if (c->blob) {
+  if (c->blob && c->owns_blob) {
     (void)hipSetDevice(c->device);
     (void)hipFree(c->blob);
   }
@@ -601,6 +654,42 @@ size_t he_workspace_bytes(const he_ctx* c, uint32_t level) {
   if (level == c->L) l = std::max(l, keygen_ws_limbs(c));
   l = std::max(l, 3 * (size_t)level + 4);  // encrypt / decrypt
   return l * c->N * 8;
+}
+
+he_status he_valu_peaks(int device, uint32_t blocks, uint32_t iters, double* rates, he_stream stream) {
+  if (!rates || blocks == 0 || blocks > (1u << 16) || iters == 0 || iters > (1u << 20))
+    return fail(HE_EINVAL, "he_valu_peaks: bad arguments");
+  HIP_TRY(hipSetDevice(device));
+  hipStream_t st = (hipStream_t)stream;
+  uint64_t* sink = nullptr;
+  HIP_TRY(hipMalloc(&sink, (size_t)blocks * ub::THREADS * sizeof(uint64_t)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  he_status r = HE_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = fail(HE_EDEVICE, "event creation");
+  using KFn = void (*)(uint32_t, uint32_t, uint64_t*);
+  const KFn fns[ub::KINDS] = {ub::k_peak_mad, ub::k_peak_mulhi, ub::k_peak_mullo, ub::k_peak_fma64, ub::k_peak_add};
+  const double lane_ops = (double)blocks * ub::THREADS * iters * ub::CHAINS;
+  for (int k = 0; k < ub::KINDS && r == HE_OK; ++k) {
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {  // the first launch also loads the kernel
+      hipLaunchKernelGGL(fns[k], dim3(blocks), dim3(ub::THREADS), 0, st, iters, 0x9e3779b1u, sink);
+      (void)hipEventRecord(e0, st);
+      hipLaunchKernelGGL(fns[k], dim3(blocks), dim3(ub::THREADS), 0, st, iters, 0x9e3779b1u, sink);
+      (void)hipEventRecord(e1, st);
+      float ms = 0;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        r = fail(HE_EDEVICE, "he_valu_peaks: timing failed");
+        break;
+      }
+      best = std::min(best, ms);
+    }
+    rates[k] = lane_ops / (best * 1e-3);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(sink);
+  if (r == HE_OK && hipGetLastError() != hipSuccess) r = fail(HE_EDEVICE, "he_valu_peaks: launch failed");
+  return r;
 }
 
 he_status he_ntt(he_ctx* c, uint64_t* d, uint32_t nlimbs, uint32_t first_mod, int inverse,
@@ -785,6 +874,10 @@ Common make_common(const he_ctx* c, const u64* evk) {
   return cm;
 }
 
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  return (const uint8_t*)a < (const uint8_t*)b + nb && (const uint8_t*)b < (const uint8_t*)a + na;
+}
+
 // Lay out one pair's workspace starting at ws; returns words used.
 u64 pair_layout(const he_ctx* c, u32 level, u64* ws, PairDesc& pd) {
   const LevelPlan& P = c->lv[level];
@@ -812,14 +905,13 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
   if (out && level < 2) return fail(HE_ELEVEL, "he_mul: rescale needs level >= 2");
   if (ws_bytes < mul_ws_limbs(c, level) * c->N * 8) return fail(HE_ENOMEM, "he_mul: workspace too small");
   const u64 N = c->N, ct_words = 2ull * level * N;
-  auto overlaps = [](const void* a, size_t na, const void* b, size_t nb) {
-    return (const uint8_t*)a < (const uint8_t*)b + nb && (const uint8_t*)b < (const uint8_t*)a + na;
-  };
   for (const u64* o : {(const u64*)relin, (const u64*)out}) {
     if (!o) continue;
     if (overlaps(o, ct_words * 8, ct1, ct_words * 8) || overlaps(o, ct_words * 8, ct2, ct_words * 8))
       return fail(HE_EINVAL, "he_mul: output aliases an input");
   }
+  if (relin && out && overlaps(relin, ct_words * 8, out, (ct_words - 2 * N) * 8))
+    return fail(HE_EINVAL, "he_mul: the two outputs overlap");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const LevelPlan& P = c->lv[level];
@@ -849,6 +941,11 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
   if (!c || !d_in || !d_out || !ws) return fail(HE_EINVAL, "he_rescale: null pointer");
   if (level < 2 || level > c->L) return fail(HE_ELEVEL, "he_rescale: level %u not in [2, L]", level);
   if (ws_bytes < (2 + 2 * (size_t)level) * c->N * 8) return fail(HE_ENOMEM, "he_rescale: workspace too small");
+  // one launch reads every input limb while others write output limbs
+  if (overlaps(d_out, 2ull * (level - 1) * c->N * 8, d_in, 2ull * level * c->N * 8))
+    return fail(HE_EINVAL, "he_rescale: output overlaps the input");
+  if (overlaps(ws, ws_bytes, d_in, 2ull * level * c->N * 8) || overlaps(ws, ws_bytes, d_out, 2ull * (level - 1) * c->N * 8))
+    return fail(HE_EINVAL, "he_rescale: workspace overlaps a ciphertext");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const u64 N = c->N;
@@ -871,6 +968,64 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
     launch_stage(c, s, cm, b, ops, bytes, st, default_tiles(c->log_n));
   }
   HIP_TRY(hipGetLastError());
+  return HE_OK;
+}
+
+// ---- ciphertext descriptors: data plus level and scale (Sec. III-A)
+
+he_status he_ct_import(he_ctx* c, const uint64_t* host, uint32_t level, double scale, he_ct* ct,
+                       he_stream stream) {
+  if (!c || !host || !ct || !ct->data) return fail(HE_EINVAL, "he_ct_import: null pointer");
+  if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_ct_import: level %u not in [1, L]", level);
+  if (!(scale > 0) || !std::isfinite(scale)) return fail(HE_EINVAL, "he_ct_import: scale must be positive");
+  const u64 N = c->N;
+  for (u32 u = 0; u < 2; ++u)
+    for (u32 i = 0; i < level; ++i) {
+      const uint64_t* row = host + ((u64)u * level + i) * N;
+      const u64 m = c->mod[i];
+      for (u64 k = 0; k < N; ++k)
+        if (row[k] >= m)
+          return fail(HE_EINVAL, "he_ct_import: poly %u limb %u coefficient %llu is not below q_%u", u, i,
+                      (unsigned long long)k, i);
+    }
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(ct->data, host, 2ull * level * N * 8, hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  ct->level = level;
+  ct->scale = scale;
+  return HE_OK;
+}
+
+he_status he_ct_export(he_ctx* c, const he_ct* ct, uint64_t* host, he_stream stream) {
+  if (!c || !ct || !ct->data || !host) return fail(HE_EINVAL, "he_ct_export: null pointer");
+  if (ct->level < 1 || ct->level > c->L) return fail(HE_ELEVEL, "he_ct_export: level %u not in [1, L]", ct->level);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpyAsync(host, ct->data, 2ull * ct->level * c->N * 8, hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return HE_OK;
+}
+
+he_status he_mul_ct(he_ctx* c, const uint64_t* d_evk, const he_ct* a, const he_ct* b, he_ct* relin, he_ct* out,
+                    void* ws, size_t ws_bytes, he_stream stream) {
+  if (!c || !a || !b) return fail(HE_EINVAL, "he_mul_ct: null pointer");
+  if (a->level != b->level) return fail(HE_ELEVEL, "he_mul_ct: operand levels %u and %u differ", a->level, b->level);
+  if ((relin && !relin->data) || (out && !out->data)) return fail(HE_EINVAL, "he_mul_ct: output without data");
+  const uint32_t level = a->level;
+  const he_status r = he_mul(c, level, a->data, b->data, d_evk, relin ? relin->data : nullptr,
+                             out ? out->data : nullptr, ws, ws_bytes, stream);
+  if (r != HE_OK) return r;
+  const double sc = a->scale * b->scale;
+  if (relin) { relin->level = level; relin->scale = sc; }
+  if (out) { out->level = level - 1; out->scale = sc / (double)c->mod[level - 1]; }
+  return HE_OK;
+}
+
+he_status he_rescale_ct(he_ctx* c, const he_ct* in, he_ct* out, void* ws, size_t ws_bytes, he_stream stream) {
+  if (!c || !in || !out || !out->data) return fail(HE_EINVAL, "he_rescale_ct: null pointer");
+  const he_status r = he_rescale(c, in->level, in->data, out->data, ws, ws_bytes, stream);
+  if (r != HE_OK) return r;
+  out->level = in->level - 1;
+  out->scale = in->scale / (double)c->mod[in->level - 1];
   return HE_OK;
 }
 

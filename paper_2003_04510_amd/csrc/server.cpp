@@ -5,9 +5,13 @@
 // whose completion event has fired (recording each request's latency and
 // returning its workspace), then, for every ring with spare in-flight
 // capacity, admits queued requests in arrival order while their workspace
-// fits the HBM budget and launches them as one batched HE Mul on that
-// ring's stream.  Requests arriving while earlier batches run join the next
-// batch; batches of different rings run concurrently on their own streams.
+// fits the ring's arena (HBM footprint) and launches them as one batched HE
+// Mul on that ring's stream.  Requests arriving while earlier batches run
+// join the next batch; batches of different rings run concurrently on their
+// own streams.  While a ring has a batch in flight, a batch that is not full
+// may be held back for a bounded time so that arrivals coalesce.  All device
+// memory (context tables, evaluation keys, arenas) belongs to the caller; the
+// server only carves the arenas.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -20,6 +24,8 @@
 #include <vector>
 
 #include "../../include/he_mi355x.h"
+
+void he_set_last_error(const char* msg);  // defined with the library's other entry points
 
 namespace {
 
@@ -46,9 +52,10 @@ struct Ring {
   he_ctx* ctx = nullptr;
   const uint64_t* evk = nullptr;
   hipStream_t stream = nullptr;
-  uint8_t* arena = nullptr;  // workspace ring buffer
+  uint8_t* arena = nullptr;  // workspace ring buffer (after the descriptor slots)
   size_t arena_size = 0;
-  uint8_t* desc = nullptr;   // max_inflight descriptor slots
+  size_t footprint = 0;      // tables + evk + whole arena
+  uint8_t* desc = nullptr;   // max_inflight descriptor slots at the head of the caller's arena
   size_t desc_slot = 0;
   uint32_t next_slot = 0;
   std::deque<Request> queue;
@@ -101,6 +108,7 @@ size_t arena_fit(const Ring& r, size_t& off) {
 
 he_status set_err(he_server* s, he_status st, const char* msg) {
   s->err = msg;
+  he_set_last_error(msg);
   return st;
 }
 
@@ -116,30 +124,32 @@ he_status he_server_create(const he_server_cfg* cfg, he_server** out) {
   return HE_OK;
 }
 
-he_status he_server_add_ring(he_server* s, he_ctx* ctx, const uint64_t* d_evk, size_t arena_bytes,
+size_t he_server_arena_min_bytes(const he_server_cfg* cfg) {
+  if (!cfg || cfg->max_batch == 0 || cfg->max_inflight == 0) return 0;
+  return he_batch_desc_bytes(cfg->max_batch) * cfg->max_inflight;
+}
+
+he_status he_server_add_ring(he_server* s, he_ctx* ctx, const uint64_t* d_evk, void* d_arena, size_t arena_bytes,
                              uint32_t* ring_id) {
-  if (!s || !ctx || !d_evk || !ring_id || arena_bytes == 0) return HE_EINVAL;
-  uint32_t log_n = 0;
-  he_ctx_info(ctx, &log_n, nullptr, nullptr, nullptr, nullptr);
-  size_t total = arena_bytes;
-  for (auto& r : s->rings) total += r.arena_size;
-  if (total > s->cfg.hbm_budget) return set_err(s, HE_ENOMEM, "ring arenas exceed the HBM budget");
+  if (!s) return HE_EINVAL;
+  if (!ctx || !d_evk || !d_arena || !ring_id) return set_err(s, HE_EINVAL, "null pointer");
+  const size_t desc = he_server_arena_min_bytes(&s->cfg);
+  if (arena_bytes <= desc) return set_err(s, HE_ENOMEM, "arena smaller than the descriptor slots");
+  const size_t footprint = he_ctx_table_bytes(ctx) + he_evk_bytes(ctx) + arena_bytes;
+  size_t total = footprint;
+  for (auto& r : s->rings) total += r.footprint;
+  if (total > s->cfg.hbm_budget)
+    return set_err(s, HE_ENOMEM, "context tables, evaluation keys and arenas exceed the HBM budget");
   Ring r;
   r.ctx = ctx;
   r.evk = d_evk;
-  r.arena_size = arena_bytes;
+  r.footprint = footprint;
+  r.desc_slot = he_batch_desc_bytes(s->cfg.max_batch);
+  r.desc = (uint8_t*)d_arena;
+  r.arena = (uint8_t*)d_arena + desc;
+  r.arena_size = arena_bytes - desc;
   if (hipStreamCreateWithFlags(&r.stream, hipStreamNonBlocking) != hipSuccess)
     return set_err(s, HE_EDEVICE, "stream creation failed");
-  if (hipMalloc(&r.arena, arena_bytes) != hipSuccess) {
-    (void)hipStreamDestroy(r.stream);
-    return set_err(s, HE_ENOMEM, "arena allocation failed");
-  }
-  r.desc_slot = he_batch_desc_bytes(s->cfg.max_batch);
-  if (hipMalloc(&r.desc, r.desc_slot * s->cfg.max_inflight) != hipSuccess) {
-    (void)hipFree(r.arena);
-    (void)hipStreamDestroy(r.stream);
-    return set_err(s, HE_ENOMEM, "descriptor allocation failed");
-  }
   s->rings.push_back(std::move(r));
   *ring_id = (uint32_t)s->rings.size() - 1;
   return HE_OK;
@@ -147,12 +157,15 @@ he_status he_server_add_ring(he_server* s, he_ctx* ctx, const uint64_t* d_evk, s
 
 he_status he_server_submit(he_server* s, uint32_t ring, uint64_t id, uint32_t level, const uint64_t* d_ct1,
                            const uint64_t* d_ct2, uint64_t* d_out) {
-  if (!s || ring >= s->rings.size() || !d_ct1 || !d_ct2 || !d_out) return HE_EINVAL;
+  if (!s) return HE_EINVAL;
+  if (ring >= s->rings.size() || !d_ct1 || !d_ct2 || !d_out) return set_err(s, HE_EINVAL, "bad ring or null pointer");
   Ring& r = s->rings[ring];
   he_batch_item it{level, d_ct1, d_ct2, nullptr, d_out};
   const size_t ws = he_batch_workspace_bytes(r.ctx, &it, 1);
   if (ws == 0 || level < 2) return set_err(s, HE_ELEVEL, "level out of range");
   if (round256(ws) > r.arena_size) return set_err(s, HE_ENOMEM, "request larger than its ring arena");
+  if (s->cfg.max_queue && r.queue.size() >= s->cfg.max_queue)
+    return set_err(s, HE_EBUSY, "the ring's request queue is full");
   r.queue.push_back(Request{id, level, d_ct1, d_ct2, d_out, clk::now(), ws});
   return HE_OK;
 }
@@ -190,6 +203,11 @@ he_status he_server_progress(he_server* s, uint32_t* launched) {
         bytes = nb;
       }
       if (take.empty()) break;  // wait for a retirement to free workspace
+      // coalescing: with a batch of this ring already running, a batch that
+      // is not full waits until its oldest request has waited hold_us
+      if (!r.inflight.empty() && take.size() < s->cfg.max_batch && s->cfg.hold_us &&
+          std::chrono::duration<double>(clk::now() - take.front().arrival).count() * 1e6 < s->cfg.hold_us)
+        break;
       std::vector<he_batch_item> items;
       for (auto& rq : take) items.push_back(he_batch_item{rq.level, rq.ct1, rq.ct2, nullptr, rq.out});
       InFlight f;
@@ -254,8 +272,6 @@ void he_server_destroy(he_server* s) {
       he_batch_destroy(f.batch);
       (void)hipEventDestroy(f.done);
     }
-    (void)hipFree(r.arena);
-    (void)hipFree(r.desc);
     (void)hipStreamDestroy(r.stream);
   }
   delete s;

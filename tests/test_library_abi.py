@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 import oracle
@@ -65,17 +67,86 @@ def test_status_strings_and_argument_errors():
     import paper_2003_04510_amd as P
     lib = P.load_library()
     assert lib.he_status_str(0) == b"ok"
+    assert lib.he_status_str(-6) == b"busy"
     h = ctypes.c_void_p()
     # null moduli -> HE_EINVAL before any device call
-    assert lib.he_ctx_create(16, 3, 1, 3, None, None, 0, ctypes.byref(h)) == -1
+    assert lib.he_ctx_create(16, 3, 1, 3, None, None, 0, None, 0, ctypes.byref(h)) == -1
     q = (ctypes.c_uint64 * 3)(*oracle.workload_primes(synth.CFG_N12)[0])
     p = (ctypes.c_uint64 * 1)(*oracle.workload_primes(synth.CFG_N12)[1])
-    assert lib.he_ctx_create(11, 3, 1, 3, q, p, 0, ctypes.byref(h)) == -5   # log_n out of range
-    assert lib.he_ctx_create(12, 3, 1, 9, q, p, 0, ctypes.byref(h)) == -1   # dnum > L
+    assert lib.he_ctx_create(11, 3, 1, 3, q, p, 0, None, 0, ctypes.byref(h)) == -5   # log_n out of range
+    assert lib.he_ctx_create(12, 3, 1, 9, q, p, 0, None, 0, ctypes.byref(h)) == -1   # dnum > L
     bad = (ctypes.c_uint64 * 3)(q[0], q[1], q[1])
-    assert lib.he_ctx_create(12, 3, 1, 3, bad, p, 0, ctypes.byref(h)) == -1  # duplicate
+    assert lib.he_ctx_create(12, 3, 1, 3, bad, p, 0, None, 0, ctypes.byref(h)) == -1  # duplicate
     with pytest.raises(Exception):
         P.binding.gen_primes(12, 70, 1)
+
+
+def _table_bytes(w):
+    import paper_2003_04510_amd as P
+    lib = P.load_library()
+    lib.he_ctx_device_bytes.restype = ctypes.c_size_t
+    q, p = oracle.workload_primes(w)
+    qa = (ctypes.c_uint64 * len(q))(*q)
+    pa = (ctypes.c_uint64 * len(p))(*p)
+    return lib.he_ctx_device_bytes(w.log_n, len(q), len(p), w.dnum, qa, pa), qa, pa
+
+
+def test_context_table_size_query():
+    """he_ctx_device_bytes sizes the caller-owned table memory without a
+    device: twice N 16-byte twiddle entries per modulus (forward and
+    inverse) plus the per-level conversion constants; 0 for invalid
+    parameters."""
+    for w in (synth.CFG_N12, synth.CFG_N16, synth.CFG_N17):
+        n, _, _ = _table_bytes(w)
+        tw = 2 * (w.L + w.K) * w.N * 16
+        assert tw < n < tw + (64 << 20), (w.name, n)
+    import paper_2003_04510_amd as P
+    lib = P.load_library()
+    n, q, p = _table_bytes(synth.CFG_N12)
+    assert lib.he_ctx_device_bytes(11, 3, 1, 3, q, p) == 0
+    assert lib.he_ctx_device_bytes(12, 3, 1, 4, q, p) == 0
+    assert lib.he_ctx_device_bytes(12, 3, 1, 3, None, p) == 0
+
+
+def test_server_arena_and_budget_errors_without_device():
+    import paper_2003_04510_amd as P
+    lib = P.load_library()
+    cfg = P.binding.ServerCfg(1 << 30, 8, 2, 4, 100)
+    lib.he_server_arena_min_bytes.restype = ctypes.c_size_t
+    n = lib.he_server_arena_min_bytes(ctypes.byref(cfg))
+    assert n > 0 and n % 256 == 0
+    assert lib.he_server_arena_min_bytes(ctypes.byref(P.binding.ServerCfg(1 << 30, 0, 2, 0, 0))) == 0
+    h = ctypes.c_void_p()
+    assert lib.he_server_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+    rid = ctypes.c_uint32()
+    assert lib.he_server_add_ring(h, None, None, None, 0, ctypes.byref(rid)) == -1
+    assert lib.he_server_submit(h, 0, 1, 3, None, None, None) == -1
+    lib.he_server_destroy(h)
+
+
+class _FakeCtx:
+    """Just the fields the binding's argument checks read."""
+
+
+def test_binding_rejects_bad_tensors_before_any_call():
+    """The binding checks device, dtype, contiguity and size of every tensor
+    it hands to the library, and the length of host draws, before any C
+    call (CPU tensors stand in for device ones here)."""
+    import torch
+
+    import paper_2003_04510_amd as P
+    ctx = P.Context.__new__(P.Context)
+    ctx.torch, ctx.N, ctx.L, ctx.device = torch, 16, 3, 0
+    t = torch.zeros(2 * 3 * 16, dtype=torch.int64)
+    with pytest.raises(P.HeError, match="cuda"):
+        ctx._ct(t, 3, "x")
+    with pytest.raises(P.HeError, match="level"):
+        ctx._ct(t, 4, "x")
+    with pytest.raises(P.HeError, match="missing"):
+        ctx._dev(None, 1, "x")
+    with pytest.raises(P.HeError, match="elements"):
+        P.binding._host(np.zeros(15), 16, np.int64, "s")
+    assert P.binding._host(np.zeros(16), 16, np.int64, "s").dtype == np.int64
 
 
 def test_big_context_argument_errors():
