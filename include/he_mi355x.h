@@ -165,6 +165,22 @@ he_status he_mul(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint6
                  const uint64_t* d_evk, uint64_t* d_relin, uint64_t* d_out, void* ws,
                  size_t ws_bytes, he_stream stream);
 
+/* HE Mul without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same computation, arguments and errors as he_mul, but the
+ * workspace is a scratch array of HE_NOALLOC_SCRATCH_BYTES (64 MiB) that the
+ * library holds per GPU until the process ends; the call allocates nothing.
+ * HE_ENOMEM when he_mul_noalloc_bytes(ctx, level) exceeds it (it fits every
+ * level at N <= 2^15 with L <= 12, and N = 2^16 up to level 8 with K = 8).
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time
+ * on the same GPU (different streams, host threads) race and must not be
+ * issued; calls ordered on one stream are safe.  The scratch's contents on
+ * entry are ignored. */
+#define HE_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t he_mul_noalloc_bytes(const he_ctx* ctx, uint32_t level);
+he_status he_mul_noalloc(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint64_t* d_ct2,
+                         const uint64_t* d_evk, uint64_t* d_relin, uint64_t* d_out, he_stream stream);
+
 /* Batched HE Mul: many independent products (each with its own level) of
  * one context executed as one sequence of stage kernels, each kernel
  * covering the work of every pair (the batch analogue of he_mul; the

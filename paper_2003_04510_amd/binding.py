@@ -88,6 +88,9 @@ def load_library():
     L.he_decrypt.argtypes = [vp, u32, vp, i64p, vp, vp, ctypes.c_size_t, vp]
     L.he_mul.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.he_rescale.argtypes = [vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.he_mul_noalloc.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp]
+    L.he_mul_noalloc_bytes.argtypes = [vp, u32]
+    L.he_mul_noalloc_bytes.restype = ctypes.c_size_t
     L.he_ntt.argtypes = [vp, vp, u32, u32, ctypes.c_int, vp]
     L.he_ctx_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32),
                               ctypes.POINTER(u32), u64p]
@@ -139,7 +142,7 @@ def load_library():
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
               "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
               "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_decode", "he_add", "he_rotate",
-              "he_keygen_rot", "he_ct_import", "he_ct_export", "he_mul_ct", "he_rescale_ct", "he_valu_peaks"):
+              "he_keygen_rot", "he_ct_import", "he_ct_export", "he_mul_ct", "he_rescale_ct", "he_mul_noalloc", "he_valu_peaks"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -413,6 +416,21 @@ class Context:
                                      self._dev(ws, self.workspace_bytes(level) // 8, "he_mul: workspace"), ws.numel() * 8,
                                      self._stream()), "he_mul")
         return (out_relin if relin else None), (out if rescale else None)
+
+    def he_mul_noalloc(self, level, ct1, ct2, evk, out_relin=None, out=None):
+        """he_mul_noalloc: HE Mul into caller tensors with the library's
+        per-GPU scratch as workspace (no allocation in the library)."""
+        _check(load_library().he_mul_noalloc(self._h, level, self._ct(ct1, level, "he_mul_noalloc: ct1"),
+                                             self._ct(ct2, level, "he_mul_noalloc: ct2"),
+                                             self._dev(evk, self.evk_bytes() // 8, "he_mul_noalloc: evk"),
+                                             self._ct(out_relin, level, "he_mul_noalloc: relin")
+                                             if out_relin is not None else None,
+                                             self._ct(out, level - 1, "he_mul_noalloc: out") if out is not None
+                                             else None, self._stream()), "he_mul_noalloc")
+        return out_relin, out
+
+    def noalloc_bytes(self, level):
+        return int(load_library().he_mul_noalloc_bytes(self._h, level))
 
     def rescale(self, level, ct, out=None):
         out = self.empty(2, max(level - 1, 1), self.N) if out is None else out

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,15 @@ using namespace he;
 namespace {
 
 thread_local std::string g_err;
+
+// Scratch of he_mul_noalloc: one array per GPU, alive until the process
+// ends.  In host code `scratch` is only a handle for the symbol lookup; the
+// device address of each GPU's copy is taken once per device (with that
+// device current) and kept in g_scratch.
+static __device__ __align__(256) uint64_t scratch[HE_NOALLOC_SCRATCH_BYTES / 8];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[MAX_DEVICES] = {};
 
 he_status fail(he_status s, const char* fmt, ...) {
   char buf[512];
@@ -537,6 +547,17 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
     return HE_OK;
   }
   HIP_TRY(hipSetDevice(device));
+  if (device < 0 || device >= MAX_DEVICES) return fail(HE_EINVAL, "he_ctx_create: device %d out of range", device);
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(HE_EDEVICE, "he_ctx_create: scratch symbol lookup failed: %s", hipGetErrorString(e));
+      g_scratch[device] = ptr;
+    }
+  }
   if (d_tables) {
     if (tables_bytes < B.size)
       return fail(HE_ENOMEM, "he_ctx_create: table memory of %zu bytes, need %zu", tables_bytes, B.size);
@@ -690,6 +711,24 @@ he_status he_valu_peaks(int device, uint32_t blocks, uint32_t iters, double* rat
   (void)hipFree(sink);
   if (r == HE_OK && hipGetLastError() != hipSuccess) r = fail(HE_EDEVICE, "he_valu_peaks: launch failed");
   return r;
+}
+
+size_t he_mul_noalloc_bytes(const he_ctx* c, uint32_t level) {
+  if (!c || level < 1 || level > c->L) return 0;
+  return mul_ws_limbs(c, level) * c->N * 8;
+}
+
+he_status he_mul_noalloc(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t* ct2, const uint64_t* evk,
+                         uint64_t* relin, uint64_t* out, he_stream stream) {
+  if (!c) return fail(HE_EINVAL, "he_mul_noalloc: null context");
+  if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_mul_noalloc: level %u not in [1, L]", level);
+  const size_t need = he_mul_noalloc_bytes(c, level);
+  if (need > (size_t)HE_NOALLOC_SCRATCH_BYTES)
+    return fail(HE_ENOMEM, "he_mul_noalloc: level %u at N = 2^%u needs %zu bytes of scratch, the maximum is %zu", level,
+                c->log_n, need, (size_t)HE_NOALLOC_SCRATCH_BYTES);
+  void* ws = g_scratch[c->device];  // set when the context was created on this device
+  if (!ws) return fail(HE_EDEVICE, "he_mul_noalloc: no scratch address for device %d", c->device);
+  return he_mul(c, level, ct1, ct2, evk, relin, out, ws, HE_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 he_status he_ntt(he_ctx* c, uint64_t* d, uint32_t nlimbs, uint32_t first_mod, int inverse,
