@@ -50,6 +50,8 @@ def lib():
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         L = ctypes.CDLL(_LIB)
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         L.orc_is_prime.argtypes = [ctypes.c_uint64]
         L.orc_is_prime.restype = ctypes.c_int
         L.orc_gen_primes.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, u64p, ctypes.c_uint32, u64p]
@@ -97,6 +99,11 @@ def _i(a: np.ndarray):
 
 
 # ---------------------------------------------------------------- primes
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's limb loops (timing only)."""
+    return int(lib().orc_set_threads(int(n)))
+
+
 def is_prime(n: int) -> bool:
     return bool(lib().orc_is_prime(n))
 
