@@ -83,6 +83,22 @@ size_t he_ctx_device_bytes(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum
 size_t he_ctx_table_bytes(const he_ctx* ctx);
 void he_ctx_destroy(he_ctx* ctx);
 
+/* 32-bit words: the paper's GPU choice of word size (Table VI, GPU column:
+ * primes below 2^30, residues in 32-bit words; Sec. V-C).  A context made by
+ * he_ctx_create_w32 (same arguments as he_ctx_create; every prime must be
+ * below 2^31, HE_EINVAL otherwise; 12 <= log_n <= 16, HE_EUNSUPPORTED
+ * above) stores every residue as a uint32_t:
+ * ciphertexts are uint32 [2][level][N], the evaluation key uint32
+ * [dnum][2][L+K][N], and he_ct_bytes / he_evk_bytes / he_workspace_bytes
+ * count 4-byte words.  Such a context runs he_mul32 only; the other entry
+ * points return HE_EUNSUPPORTED for it.  With every prime below 2^30 the
+ * NTT butterflies run in 32-bit integer arithmetic (Shoup's product with a
+ * 2^32-scaled companion on the 32-bit multipliers), else in exact FP64.
+ * he_ctx_word_bytes: 8 or 4. */
+he_status he_ctx_create_w32(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                            const uint64_t* p, int device, void* d_tables, size_t tables_bytes, he_ctx** out);
+uint32_t he_ctx_word_bytes(const he_ctx* ctx);
+
 /* Sizes in bytes. */
 size_t he_ct_bytes(const he_ctx* ctx, uint32_t level);      /* 2*level*N*8 */
 size_t he_evk_bytes(const he_ctx* ctx);                     /* dnum*2*(L+K)*N*8 */
@@ -180,6 +196,13 @@ he_status he_mul(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint6
 size_t he_mul_noalloc_bytes(const he_ctx* ctx, uint32_t level);
 he_status he_mul_noalloc(he_ctx* ctx, uint32_t level, const uint64_t* d_ct1, const uint64_t* d_ct2,
                          const uint64_t* d_evk, uint64_t* d_relin, uint64_t* d_out, he_stream stream);
+
+/* HE Mul of a 32-bit-word context (he_ctx_create_w32): the computation,
+ * arguments, outputs and errors of he_mul on uint32 words; the results are
+ * the same residues he_mul gives for the same primes on 64-bit words.
+ * HE_EUNSUPPORTED for a 64-bit-word context. */
+he_status he_mul32(he_ctx* ctx, uint32_t level, const uint32_t* d_ct1, const uint32_t* d_ct2, const uint32_t* d_evk,
+                   uint32_t* d_relin, uint32_t* d_out, void* ws, size_t ws_bytes, he_stream stream);
 
 /* Batched HE Mul: many independent products (each with its own level) of
  * one context executed as one sequence of stage kernels, each kernel

@@ -66,6 +66,10 @@ def load_library():
     L.he_gen_primes.argtypes = [u32, u32, u32, u64p, u32, u64p]
     L.he_ctx_create.argtypes = [u32, u32, u32, u32, u64p, u64p, ctypes.c_int, vp, ctypes.c_size_t,
                                 ctypes.POINTER(vp)]
+    L.he_ctx_create_w32.argtypes = L.he_ctx_create.argtypes
+    L.he_ctx_word_bytes.argtypes = [vp]
+    L.he_ctx_word_bytes.restype = u32
+    L.he_mul32.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.he_ctx_device_bytes.argtypes = [u32, u32, u32, u32, u64p, u64p]
     L.he_ctx_device_bytes.restype = ctypes.c_size_t
     L.he_ctx_table_bytes.argtypes = [vp]
@@ -142,7 +146,7 @@ def load_library():
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
               "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
               "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_decode", "he_add", "he_rotate",
-              "he_keygen_rot", "he_ct_import", "he_ct_export", "he_mul_ct", "he_rescale_ct", "he_mul_noalloc", "he_valu_peaks"):
+              "he_keygen_rot", "he_ct_import", "he_ct_export", "he_mul_ct", "he_rescale_ct", "he_mul_noalloc", "he_valu_peaks", "he_ctx_create_w32", "he_mul32"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -214,9 +218,11 @@ def _host(a, n: int, dtype, name: str):
 
 
 class Context:
-    """A device context: moduli, NTT and base-conversion tables on GPU `device`."""
+    """A device context: moduli, NTT and base-conversion tables on GPU `device`.
+    word32=True stores residues as 32-bit words (every prime below 2^31):
+    such a context runs he_mul32 only and its tensors are int32."""
 
-    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0):
+    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0, word32: bool = False):
         import torch
         self.torch = torch
         L = load_library()
@@ -232,15 +238,18 @@ class Context:
         # the context's constant tables live in torch memory the binding owns
         self._tables = torch.empty((nbytes + 7) // 8, dtype=torch.int64, device=torch.device("cuda", device))
         h = vp()
-        _check(L.he_ctx_create(log_n, self.L, self.K, dnum, qp, pp, device, vp(self._tables.data_ptr()),
-                               self._tables.numel() * 8, ctypes.byref(h)), "he_ctx_create")
+        self.word32 = bool(word32)
+        self.wdtype = torch.int32 if self.word32 else torch.int64
+        create = L.he_ctx_create_w32 if self.word32 else L.he_ctx_create
+        _check(create(log_n, self.L, self.K, dnum, qp, pp, device, vp(self._tables.data_ptr()),
+                      self._tables.numel() * 8, ctypes.byref(h)), "he_ctx_create")
         self._h = h
         self._ws = {}
 
     @classmethod
-    def for_workload(cls, w, device: int = 0):
+    def for_workload(cls, w, device: int = 0, word32: bool = False):
         q, p = workload_primes(w)
-        return cls(w.log_n, q, p, w.dnum, device)
+        return cls(w.log_n, q, p, w.dnum, device, word32)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -274,14 +283,15 @@ class Context:
         return int(load_library().he_workspace_bytes(self._h, level))
 
     def empty(self, *shape):
-        return self.torch.empty(shape, dtype=self.torch.int64, device=self.dev)
+        """Uninitialized residue words (int64, or int32 for 32-bit words)."""
+        return self.torch.empty(shape, dtype=self.wdtype, device=self.dev)
 
     def _dev(self, t, words: int, name: str, dtype=None):
         """Check that t can be handed to the library as `words` 8-byte
         elements: a contiguous tensor on this context's GPU, of dtype int64
         (or `dtype`), with at least that many elements.  Raises HeError
         before any library call."""
-        dtype = self.torch.int64 if dtype is None else dtype
+        dtype = self.wdtype if dtype is None else dtype
         if t is None:
             raise HeError("%s: missing tensor" % name)
         if not t.is_cuda or t.device.index != self.dev.index:
@@ -301,20 +311,31 @@ class Context:
 
     def workspace(self, level):
         """A cached workspace tensor large enough for `level`."""
-        need = self.workspace_bytes(level) // 8
+        need = (self.workspace_bytes(level) + 7) // 8
         ws = self._ws.get("ws")
         if ws is None or ws.numel() < need:
-            ws = self.empty(need)
+            ws = self.torch.empty(need, dtype=self.torch.int64, device=self.dev)
             self._ws["ws"] = ws
         return ws
 
     def to_device(self, arr: np.ndarray):
-        a = np.ascontiguousarray(arr, dtype=np.uint64).view(np.int64)
+        """Host residues (uint64 values) -> device words of this context."""
+        if self.word32:
+            a64 = np.ascontiguousarray(arr, dtype=np.uint64)
+            if a64.size and int(a64.max()) >> 32:
+                raise HeError("to_device: a residue does not fit a 32-bit word")
+            a = a64.astype(np.uint32).view(np.int32)
+        else:
+            a = np.ascontiguousarray(arr, dtype=np.uint64).view(np.int64)
         return self.torch.from_numpy(a.copy()).to(self.dev)
 
     @staticmethod
     def to_host(t) -> np.ndarray:
-        return t.detach().cpu().numpy().view(np.uint64)
+        """Device words -> host residues as uint64 (32-bit words widened)."""
+        h = t.detach().cpu().numpy()
+        if h.dtype == np.int32:
+            return h.view(np.uint32).astype(np.uint64)
+        return h.view(np.uint64)
 
     # ---------------------------------------------------------- operations
     def keygen(self, s, e_pk, e_evk, a_pk, a_evk):
@@ -372,7 +393,7 @@ class Context:
         _check(load_library().he_rotate(self._h, level, self._ct(ct, level, "rotate: ct"),
                                         self._dev(rk, self.evk_bytes() // 8, "rotate: rk"), int(rot),
                                         self._ct(out, level, "rotate: out"),
-                                        self._dev(ws, self.workspace_bytes(level) // 8, "rotate: workspace"),
+                                        self._dev(ws, self.workspace_bytes(level) // 8, "rotate: workspace", self.torch.int64),
                                         ws.numel() * 8, self._stream()), "he_rotate")
         return out
 
@@ -402,18 +423,20 @@ class Context:
         return out
 
     def he_mul(self, level, ct1, ct2, evk, relin=True, rescale=True, ws=None, out_relin=None, out=None):
-        """HE Mul; returns (relinearized ct or None, rescaled ct or None)."""
+        """HE Mul; returns (relinearized ct or None, rescaled ct or None).
+        32-bit-word contexts go through he_mul32."""
         if relin and out_relin is None:
             out_relin = self.empty(2, level, self.N)
         if rescale and out is None:
             out = self.empty(2, max(level - 1, 1), self.N)
         ws = self.workspace(level) if ws is None else ws
-        _check(load_library().he_mul(self._h, level, self._ct(ct1, level, "he_mul: ct1"),
+        fn = load_library().he_mul32 if self.word32 else load_library().he_mul
+        _check(fn(self._h, level, self._ct(ct1, level, "he_mul: ct1"),
                                      self._ct(ct2, level, "he_mul: ct2"),
                                      self._dev(evk, self.evk_bytes() // 8, "he_mul: evk"),
                                      self._ct(out_relin, level, "he_mul: relin") if relin else None,
                                      self._ct(out, level - 1, "he_mul: out") if rescale else None,
-                                     self._dev(ws, self.workspace_bytes(level) // 8, "he_mul: workspace"), ws.numel() * 8,
+                                     self._dev(ws, self.workspace_bytes(level) // 8, "he_mul: workspace", self.torch.int64), ws.numel() * 8,
                                      self._stream()), "he_mul")
         return (out_relin if relin else None), (out if rescale else None)
 

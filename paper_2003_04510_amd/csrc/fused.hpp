@@ -34,6 +34,20 @@ namespace he {
 
 constexpr u64 M30 = (1ull << 30) - 1;
 
+// Residues are stored in HBM as words of type W: uint64_t, or uint32_t for
+// contexts whose primes are below 2^31 (32-bit words).  Descriptors carry
+// untyped base pointers; a kernel converts a base to W before adding
+// element offsets.  Arithmetic is the same for both word types: a word is
+// widened on load and every stored value is canonical, so it fits W.
+template <class W>
+__device__ __forceinline__ gptr<W> gw(u64* p) {
+  return (gptr<W>)reinterpret_cast<W*>(p);
+}
+template <class W>
+__device__ __forceinline__ gptr<const W> gw(const u64* p) {
+  return (gptr<const W>)reinterpret_cast<const W*>(p);
+}
+
 // Workgroup tiles (elements per workgroup) of the NTT passes.  Defaults:
 // "cols" passes 4096 elements (16 adjacent columns at N = 2^16), "blocks"
 // passes 2048; batches at N = 2^16 may select other tiles (TileCfg).
@@ -237,7 +251,7 @@ __device__ __forceinline__ U128 conv_sum(u64 sll, u64 slh, u64 shl, u64 shh) {
 // that hide the memory latency of a grid of about one wave per SIMD.
 // Then, when rescaling, items (level + u, block tile): d_u of limb level-1
 // again, its INTT blocks pass into y[level + u] (rescale by linearity).
-template <int LOGS, int EPW>
+template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
@@ -268,7 +282,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
   const u64 blk0 = (u64)pos * PL::SUBS;
   const u64 off = ((u64)i << c.log_n) + (blk0 << LOGS);
   const int sub = PL::sub(), tt = PL::tt();
-  const auto ct1 = gbl(pd.ct1 + off), ct2 = gbl(pd.ct2 + off);
+  const auto ct1 = gw<W>(pd.ct1) + off, ct2 = gw<W>(pd.ct2) + off;
   const auto put = [&](int k, u64 v) {
     const int e = threadIdx.x + k * THREADS;
     lds[(e >> LOGS) * Gm::SUB + Gm::pad(e & (Gm::S - 1))] = v;
@@ -276,7 +290,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
   // Operands are loaded TG elements at a time before any result is stored.
   constexpr int TG = Gm::R < 8 ? Gm::R : 8;
   if (which == 3) {
-    const auto rl0 = gbl(pd.rl + off), rl1 = gbl(pd.rl + tot + off);
+    const auto rl0 = gw<W>(pd.rl) + off, rl1 = gw<W>(pd.rl) + tot + off;
     // the products in FP64 for q < 2^50 (exact, see F64A::mulv), else on
     // the integer multipliers; both canonical
     const auto products = [&](auto f64) {
@@ -317,7 +331,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
     return;
   }
   if (which == 2) {
-    const auto d2 = gbl(pd.d2 + off);
+    const auto d2 = gw<W>(pd.d2) + off;
     constexpr int TA = Gm::R < 16 ? Gm::R : 16;  // two operands: twice the loads in flight
     const auto products = [&](auto f64) {
       constexpr bool F = decltype(f64)::value;
@@ -367,16 +381,19 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
     }
   }
   lds_barrier();
-  const auto out = gbl(pd.y + ((u64)r << c.log_n) + (blk0 << LOGS) + ((u64)sub << LOGS));
+  const auto out = gw<W>(pd.y) + ((u64)r << c.log_n) + (blk0 << LOGS) + ((u64)sub << LOGS);
   u64 xi[Gm::R];
   lds_get<LOGS, LOGR, FIRST>(lds + sub * Gm::SUB, xi, tt);
   // the transform writes only tile positions this thread has just read
-  with_arith(m.q, [&](auto ar) {
+  // (for 8-byte values; with 4-byte values the positions differ, so every
+  // thread must have read its operands first)
+  with_arith<W>(m, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
     typename A::V x[Gm::R];
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    if constexpr (sizeof(typename A::V) != 8) lds_barrier();
     sub_transform_regs<A, false, LOGS, LOGR, false>(
         x, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, c.itw + ((u64)i << c.log_n),
         (1ull << n1) + blk0 + sub, M, [&](int e, typename A::V v) { out[e] = A::template out<false>(v, M); });
@@ -385,8 +402,9 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
 
 // ---------------------------------------------------------------- NTT passes over limb lists
 struct ListView {
-  const u64* src;
+  const u64* src;  // base pointers (word type of the kernel) ...
   u64* dst;
+  u64 so, dof;     // ... and element offsets from them
   u64 zs, zd;  // polynomial strides
   const u32* limb_mod;
   const u64* scale;  // inverse cols pass: per-limb Shoup pairs (null: N^-1)
@@ -407,7 +425,7 @@ __device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& p
     v.limb_mod = ldc(&P->dt_mod); v.scale = nullptr;
   } else if constexpr (ST == ST_KS_IBLOCKS || ST == ST_KS_ICOLS) {
     const u64 ne = pd.level + c.K;
-    v.src = pd.ks + ((u64)pd.level << c.log_n); v.dst = pd.ks + ((u64)pd.level << c.log_n);
+    v.src = pd.ks; v.dst = pd.ks; v.so = v.dof = (u64)pd.level << c.log_n;
     v.zs = v.zd = (ne + 1) * N; v.nl = c.K + ex; v.np = 2;
     v.limb_mod = ldc(&P->s_mod); v.scale = ldc(&P->s_scale);
   } else if constexpr (ST == ST_Y_IBLOCKS) {
@@ -420,7 +438,7 @@ __device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& p
   return v;
 }
 
-template <bool FWD, int LOGS, int EPW, int ST>
+template <class W, bool FWD, int LOGS, int EPW, int ST>
 __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& pd, u32 local, u64* lds) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
@@ -436,8 +454,8 @@ __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& 
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 col = (u64)pos * PL::SUBS + sub;
-  const auto in = gbl(v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + col);
-  const auto out = gbl(v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + col);
+  const auto in = gw<W>(v.src) + v.so + (u64)z * v.zs + ((u64)limb << c.log_n) + col;
+  const auto out = gw<W>(v.dst) + v.dof + (u64)z * v.zd + ((u64)limb << c.log_n) + col;
   u64 sw = mo.ninv, sws = mo.ninvs;
   if (!FWD && v.scale) {
     sw = ldc(v.scale + 2 * (u64)limb);
@@ -446,7 +464,7 @@ __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& 
   u64 xi[Gm::R];
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) xi[k] = in[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
-  with_arith(mo.q, [&](auto ar) {
+  with_arith<W>(mo, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(mo.q, mo.qinv);
     const typename A::Scale sc = A::scale(sw, sws, M);
@@ -461,20 +479,20 @@ __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& 
   });
 }
 
-template <bool FWD, int LOGS, int EPW, int ST>
+template <class W, bool FWD, int LOGS, int EPW, int ST>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c, Batch b) {
   __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
   const PairDesc pd = resolve(b, uniform(w), local);
-  list_cols_item<FWD, LOGS, EPW, ST>(c, pd, local, lds);
+  list_cols_item<W, FWD, LOGS, EPW, ST>(c, pd, local, lds);
 }
 
 // Blocks pass; the side whose register layout is thread-contiguous
 // (forward output, inverse input) goes through LDS so global accesses stay
 // coalesced.
-template <bool FWD, int LOGS, int EPW, int ST>
+template <class W, bool FWD, int LOGS, int EPW, int ST>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
@@ -496,8 +514,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();
   const u64 blk0 = (u64)pos * PL::SUBS;
-  const auto in0 = gbl(v.src + (u64)z * v.zs + ((u64)limb << c.log_n) + (blk0 << LOGS));
-  const auto out0 = gbl(v.dst + (u64)z * v.zd + ((u64)limb << c.log_n) + (blk0 << LOGS));
+  const auto in0 = gw<W>(v.src) + v.so + (u64)z * v.zs + ((u64)limb << c.log_n) + (blk0 << LOGS);
+  const auto out0 = gw<W>(v.dst) + v.dof + (u64)z * v.zd + ((u64)limb << c.log_n) + (blk0 << LOGS);
   u64 xi[Gm::R];
   if constexpr (!FWD) {
 #pragma unroll
@@ -514,13 +532,16 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
     for (int k = 0; k < Gm::R; ++k) xi[k] = in[RF::elem(tt, k / RF::G, k % RF::G)];
   }
   const auto out = out0 + ((u64)sub << LOGS);
-  with_arith(mo.q, [&](auto ar) {
+  with_arith<W>(mo, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(mo.q, mo.qinv);
     typename A::V* tl = reinterpret_cast<typename A::V*>(lds);
     typename A::V x[Gm::R];
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
+    // 4-byte values: the inverse input tile (8-byte words) is read by every
+    // thread before the transform reuses it
+    if constexpr (!FWD && sizeof(typename A::V) != 8) lds_barrier();
     sub_transform_regs<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
                                                 (1ull << n1) + blk0 + sub, M,
                                                 [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); });
@@ -550,7 +571,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
 // down): all NSMAX source loads are issued unconditionally (index clamped to
 // the job's ns, constants of unused sources zero), so each thread waits for
 // its loads once instead of once per source.
-template <bool MD, int NSMAX>
+template <class W, bool MD, int NSMAX>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
@@ -567,8 +588,8 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32* consts = MD ? ldc(&P->md_c) : ldc(&P->mu_c);
   const u64 N = 1ull << c.log_n;
   const u64 ne1 = pd.level + c.K + 1;
-  const u64* src = MD ? pd.ks + (u64)jz * ne1 * N : pd.y;
-  u64* dst = MD ? pd.zc + (u64)jz * pd.level * N : pd.dt;
+  const auto src = MD ? gw<W>(pd.ks) + (u64)jz * ne1 * N : gw<W>(pd.y);
+  const auto dst = MD ? gw<W>(pd.zc) + (u64)jz * pd.level * N : gw<W>(pd.dt);
   // merged rescale (mod down, rescaling, relinearized value not an output):
   // targets q_0 .. q_{l-2} receive z'_t + [r]_t, see below
   const bool merged = MD && pd.rs && !pd.wrl;
@@ -577,7 +598,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 t0 = grp * per, t1 = min(nt, t0 + per);
   if (t0 >= t1) return;
   const u64 n0 = ((u64)chunk * CONV_THREADS + threadIdx.x) * CONV_CPT;
-  const auto s0 = gbl(src + ((u64)J.src_off << c.log_n) + n0);
+  const auto s0 = src + ((u64)J.src_off << c.log_n) + n0;
   u32 y0[NSMAX][CONV_CPT], y1[NSMAX][CONV_CPT];
 #pragma unroll
   for (int s = 0; s < NSMAX; ++s) {
@@ -630,8 +651,8 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const auto dropped = [&](const u64 (&zl)[CONV_CPT], u64 (&r)[CONV_CPT]) {
     const u64 ql = ldc(&c.mods[pd.level - 1].q);
     const u64 pw = ldc(&P->pinv_l), pws = ldc(&P->pinv_ls);
-    const auto yy = gbl(pd.y + ((u64)(pd.level + jz) << c.log_n) + n0);
-    const auto kk = gbl(src + ((u64)(pd.level + c.K) << c.log_n) + n0);
+    const auto yy = gw<W>(pd.y) + ((u64)(pd.level + jz) << c.log_n) + n0;
+    const auto kk = src + ((u64)(pd.level + c.K) << c.log_n) + n0;
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) {
       const u64 a = csub(yy[k] + csub(shoup_lazy(kk[k], pw, pws, ql), ql), ql);
@@ -655,7 +676,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       convert(t, v);
       const ModInfo m = ldc(c.mods + t);
       const u64 qm = ldc(qlm + t);
-      const auto o = gbl(dst + ((u64)t << c.log_n) + n0);
+      const auto o = dst + ((u64)t << c.log_n) + n0;
 #pragma unroll
       for (int k = 0; k < CONV_CPT; ++k) {
         u64 s = csub(r[k] - mulhi(r[k], m.one_s) * m.q, m.q);  // r mod q_t
@@ -668,7 +689,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   for (u32 t = t0; t < t1; ++t) {
     u64 v[CONV_CPT];
     convert(t, v);
-    const auto o = gbl(dst + ((u64)(J.dst_off + t) << c.log_n) + n0);
+    const auto o = dst + ((u64)(J.dst_off + t) << c.log_n) + n0;
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) o[k] = v[k];
     if constexpr (MD) {
@@ -677,7 +698,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       if (pd.rs && t == pd.level - 1) {
         u64 r[CONV_CPT];
         dropped(v, r);
-        const auto yy = gbl(pd.y + ((u64)(pd.level + jz) << c.log_n) + n0);
+        const auto yy = gw<W>(pd.y) + ((u64)(pd.level + jz) << c.log_n) + n0;
 #pragma unroll
         for (int k = 0; k < CONV_CPT; ++k) yy[k] = r[k];
       }
@@ -697,7 +718,7 @@ inline int conv_bucket(u32 ns) {
 // level+K (it is inverse-transformed with the special limbs).
 // Items (e, coefficient chunk).  KEY_NT: the key is read by one HE Mul
 // (a single pair), so its loads bypass the caches.
-template <bool KEY_NT>
+template <class W, bool KEY_NT>
 __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
@@ -723,14 +744,14 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
     for (int jj = 0; jj < JG; ++jj) {
       const u32 j = min(j0 + jj, beta - 1);
       const u32 lo = ldc(&P->lo[j]), cnt = ldc(&P->cnt[j]);
-      gptr<const u64> x;
+      gptr<const W> x;
       if (e < pd.level && e >= lo && e < lo + cnt) {
-        x = gbl(pd.d2 + ((u64)e << c.log_n));
+        x = gw<W>((const u64*)pd.d2) + ((u64)e << c.log_n);
       } else {
         const u32 o = e < lo ? e : e - cnt;
-        x = gbl(pd.dt + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n));
+        x = gw<W>((const u64*)pd.dt) + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n);
       }
-      const auto eb = gbl(c.evk + ((((u64)j * 2) * nm + mi) << c.log_n));
+      const auto eb = gw<W>(c.evk) + ((((u64)j * 2) * nm + mi) << c.log_n);
       const auto ea = eb + (nm << c.log_n);
 #pragma unroll
       for (int k = 0; k < IP_CPT; ++k) {
@@ -759,9 +780,9 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
     }
   }
   const u64 kz = (u64)(pd.level + c.K + 1) << c.log_n;
-  const auto ob = gbl(pd.ks + ((u64)e << c.log_n) + n0);
+  const auto ob = gw<W>(pd.ks) + ((u64)e << c.log_n) + n0;
   const bool last = pd.rs && e == pd.level - 1;
-  const auto xb = gbl(pd.ks + ((u64)(pd.level + c.K) << c.log_n) + n0);
+  const auto xb = gw<W>(pd.ks) + ((u64)(pd.level + c.K) << c.log_n) + n0;
 #pragma unroll
   for (int k = 0; k < IP_CPT; ++k) {
     // beta <= 4: the sums stay below 4 q^2 < 2^(2b+2), Barrett's range
@@ -791,7 +812,7 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
 // 0 and 1, one polynomial each), leaving them the inverse cols pass.
 // Items (e, tile), tile fastest; e < level + K (+1).
 
-template <int LOGS>
+template <class W, int LOGS>
 __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
@@ -825,7 +846,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
   const u64 base = (1ull << n1) + blk0 + sub;
   const auto lpos = [](int idx) { return (idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1)); };
   const u64 kz = (u64)(pd.level + c.K + 1) << c.log_n;
-  with_arith(m.q, [&](auto ar) {
+  with_arith<W>(m, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
     typename A::V* const tiles = reinterpret_cast<typename A::V*>(lds);
@@ -835,7 +856,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
       const u32 j = wave;
       const u32 lo = ldc(&P->lo[j]), cnt = ldc(&P->cnt[j]);
       if (e < pd.level && e >= lo && e < lo + cnt) {
-        const auto x = gbl(pd.d2 + ((u64)e << c.log_n) + toff);
+        const auto x = gw<W>(pd.d2) + ((u64)e << c.log_n) + toff;
 #pragma unroll
         for (int k = 0; k < EW / 64; ++k) {
           const int idx = lane + k * 64;
@@ -843,7 +864,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
         }
       } else {
         const u32 o = e < lo ? e : e - cnt;
-        const auto src = gbl(pd.dt + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n) + toff + ((u64)sub << LOGS));
+        const auto src = gw<W>(pd.dt) + ((u64)(ldc(&P->dt_first[j]) + o) << c.log_n) + toff + ((u64)sub << LOGS);
         typename A::V x[Gm::R];
 #pragma unroll
         for (int k = 0; k < Gm::R; ++k) x[k] = A::in(src[RF::elem(tt, k / RF::G, k % RF::G)], M);
@@ -859,7 +880,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
 #pragma unroll
     for (int j = 0; j < IP_WAVES; ++j) {
       const u32 jc = min((u32)j, beta - 1);
-      const auto eb = gbl(c.evk + ((((u64)jc * 2) * nm + mi) << c.log_n) + toff);
+      const auto eb = gw<W>(c.evk) + ((((u64)jc * 2) * nm + mi) << c.log_n) + toff;
       const auto ea = eb + (nm << c.log_n);
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
@@ -895,7 +916,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
       }
     }
     if (!coef) {
-      const auto ob = gbl(pd.ks + ((u64)e << c.log_n) + toff);
+      const auto ob = gw<W>(pd.ks) + ((u64)e << c.log_n) + toff;
 #pragma unroll
       for (int k = 0; k < PER; ++k) {
         const int idx = threadIdx.x + k * THREADS;
@@ -917,7 +938,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
       typename A::V x[Gm::R];
       lds_get<LOGS, LOGR, IFIRST>(mine + sub * Gm::SUB, x, tt);
       const u64 slot = copy ? pd.level + c.K : e;
-      const auto out = gbl(pd.ks + (wave ? kz : 0) + (slot << c.log_n) + toff + ((u64)sub << LOGS));
+      const auto out = gw<W>(pd.ks) + (wave ? kz : 0) + (slot << c.log_n) + toff + ((u64)sub << LOGS);
       sub_transform_regs<A, false, LOGS, LOGR, false, true>(
           x, mine + sub * Gm::SUB, tt, c.itw + ((u64)mi << c.log_n), base, M,
           [&](int e2, typename A::V v) { out[e2] = A::template out<false>(v, M); });
@@ -935,7 +956,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
 // input of z' + s and out_u[i] = v_u[i] * [q_{l-1}^-1]_{q_i}.  v never
 // makes a trip through HBM unless it is an output.
 // Items (i, u, block tile), tile fastest.
-template <int LOGS, int EPW>
+template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
@@ -959,14 +980,14 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   const int sub = PL::sub(), tt = PL::tt();
   const u64 limb_off = ((u64)(u * pd.level + i) << c.log_n) + toff;
   u64 xi[Gm::R];
-  const auto zp = gbl(pd.z + limb_off + ((u64)sub << LOGS));
+  const auto zp = gw<W>(pd.z) + limb_off + ((u64)sub << LOGS);
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) xi[k] = zp[RF::elem(tt, k / RF::G, k % RF::G)];
   const u64 pw = ldc(c.pinv + 2 * i), pws = ldc(c.pinv + 2 * i + 1);
-  const auto ksu = gbl(pd.ks + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff);
-  const auto rlu = gbl(pd.rl + limb_off);
-  const auto sp = gbl(pd.d2 + limb_off + ((u64)sub << LOGS));
-  const auto ou = gbl(pd.out + ((u64)(u * (pd.level - 1) + i) << c.log_n) + toff);
+  const auto ksu = gw<W>(pd.ks) + ((u64)(u * (pd.level + c.K + 1) + i) << c.log_n) + toff;
+  const auto rlu = gw<W>(pd.rl) + limb_off;
+  const auto sp = gw<W>(pd.d2) + limb_off + ((u64)sub << LOGS);
+  const auto ou = gw<W>(pd.out) + ((u64)(u * (pd.level - 1) + i) << c.log_n) + toff;
   u64 qw = 0, qws = 0;
   if (resc) {
     const u64* ql = ldc(&P->qlinv);
@@ -975,7 +996,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   }
   const Tw2* twl = c.tw + ((u64)i << c.log_n);
   const u64 base = (1ull << n1) + blk0 + sub;
-  with_arith(m.q, [&](auto ar) {
+  with_arith<W>(m, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
     typename A::V* tl = reinterpret_cast<typename A::V*>(lds);
@@ -1018,7 +1039,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
         if (pd.wrl) rlu[idx] = v;
         if (resc) {
           const u64 S = two ? A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M) : 0;
-          __builtin_nontemporal_store(csub(shoup_lazy(v + m.q - S, qw, qws, m.q), m.q), &ou[idx]);
+          __builtin_nontemporal_store((W)csub(shoup_lazy(v + m.q - S, qw, qws, m.q), m.q), &ou[idx]);
         }
       }
     }
@@ -1030,7 +1051,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 // y[level + u] (assembled by the mod-down conversion, see k_conv).  Then
 // s = centered(r) mod q_i.
 // Items (u, column tile, i < level-1), i fastest.
-template <int LOGS, int EPW>
+template <class W, int LOGS, int EPW>
 __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u32 local, u64* lds) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
@@ -1050,7 +1071,7 @@ __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u
   const u64 col = (u64)pos * PL::SUBS + sub;
   // r_u: pd.r (stand-alone rescale) or y[level + u], where the mod-down
   // conversion left it
-  const auto rr = gbl(pd.r ? pd.r + (u64)u * N + col : pd.y + ((u64)(pd.level + u) << c.log_n) + col);
+  const auto rr = pd.r ? gw<W>(pd.r) + (u64)u * N + col : gw<W>((const u64*)pd.y) + ((u64)(pd.level + u) << c.log_n) + col;
   u64 x[Gm::R];
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) x[k] = rr[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
@@ -1061,8 +1082,8 @@ __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u
     if (2 * r >= ql) v = submod(v, qlm, m.q);
     x[k] = v;
   }
-  const auto out = gbl(pd.d2 + ((u64)(u * pd.level + i) << c.log_n) + col);
-  with_arith(m.q, [&](auto ar) {
+  const auto out = gw<W>(pd.d2) + ((u64)(u * pd.level + i) << c.log_n) + col;
+  with_arith<W>(m, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
     typename A::V xa[Gm::R];
@@ -1074,14 +1095,14 @@ __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u
   });
 }
 
-template <int LOGS, int EPW>
+template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Common c, Batch b) {
   __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
   const PairDesc pd = resolve(b, uniform(w), local);
-  lift_item<LOGS, EPW>(c, pd, local, lds);
+  lift_item<W, LOGS, EPW>(c, pd, local, lds);
 }
 
 // NTT cols pass of z' (mod-down) and, when rescaling with rl an output, the
@@ -1089,7 +1110,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
 // z's, the rest s's.  The two touch disjoint buffers (z cols: zc -> z; lift:
 // y -> s over d2).  Rescaling without rl as an output, s is already in z'
 // and only limbs i < level-1 are transformed.
-template <int LOGS, int EPW>
+template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c, Batch b) {
   __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
@@ -1097,8 +1118,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c
   u32 local;
   const PairDesc pd = resolve(b, uniform(w), local);
   const u32 nz = uniform(2 * (pd.rs && !pd.wrl ? pd.level - 1 : pd.level) * cols_tiles(c.log_n, EPW));
-  if (local < nz) list_cols_item<true, LOGS, EPW, ST_Z_NCOLS>(c, pd, local, lds);
-  else lift_item<LOGS, EPW>(c, pd, local - nz, lds);
+  if (local < nz) list_cols_item<W, true, LOGS, EPW, ST_Z_NCOLS>(c, pd, local, lds);
+  else lift_item<W, LOGS, EPW>(c, pd, local - nz, lds);
 }
 
 // ---------------------------------------------------------------- rotation: automorphism
@@ -1107,7 +1128,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c
 // sigma_g(a)[k] = a[k'] with 2 brv(k') + 1 = (2 brv(k) + 1) g mod 2N.
 // Writes the triple key switching expects: rl = (sigma_g(b), 0), d2 = sigma_g(a).
 // One thread per (limb, coefficient) of [level][N].
-__global__ __launch_bounds__(256) void k_automorphism(const u64* ct, u64* rl, u64* d2, u64 g, u32 level,
+static __global__ __launch_bounds__(256) void k_automorphism(const u64* ct, u64* rl, u64* d2, u64 g, u32 level,
                                                       u32 log_n) {
   const u64 N = 1ull << log_n, tot = (u64)level * N;
   const u64 t = (u64)blockIdx.x * 256 + threadIdx.x;
@@ -1126,7 +1147,7 @@ __global__ __launch_bounds__(256) void k_automorphism(const u64* ct, u64* rl, u6
 // ---------------------------------------------------------------- NTT blocks + rescale combine
 // out_u[i] = (rl_u[i] - NTT(s_u[i])) * [q_{l-1}^-1]_{q_i}; s lives over d2.
 // Items (i < level-1, u, block tile), tile fastest.
-template <int LOGS, int EPW>
+template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common c, Batch b) {
   constexpr int LOGR = Radix<LOGS>::LOGR;
   using Gm = Geo<LOGS, LOGR>;
@@ -1148,14 +1169,14 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
   const u64 blk0 = (u64)pos * PL::SUBS, toff = blk0 << LOGS;
   const int sub = PL::sub(), tt = PL::tt();
   u64 xi[Gm::R];
-  const auto p = gbl(pd.d2 + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS));
+  const auto p = gw<W>(pd.d2) + ((u64)(u * pd.level + i) << c.log_n) + toff + ((u64)sub << LOGS);
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) xi[k] = p[RF::elem(tt, k / RF::G, k % RF::G)];
   const u64* ql = ldc(&P->qlinv);
   const u64 qw = ldc(ql + 2 * i), qws = ldc(ql + 2 * i + 1);
-  const auto cu = gbl(pd.rl + ((u64)(u * pd.level + i) << c.log_n) + toff);
-  const auto ou = gbl(pd.out + ((u64)(u * nl + i) << c.log_n) + toff);
-  with_arith(m.q, [&](auto ar) {
+  const auto cu = gw<W>(pd.rl) + ((u64)(u * pd.level + i) << c.log_n) + toff;
+  const auto ou = gw<W>(pd.out) + ((u64)(u * nl + i) << c.log_n) + toff;
+  with_arith<W>(m, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(m.q, m.qinv);
     typename A::V* tl = reinterpret_cast<typename A::V*>(lds);

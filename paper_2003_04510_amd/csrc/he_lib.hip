@@ -18,6 +18,7 @@
 #include "host_math.hpp"
 #include "ntt.hpp"
 #include "fused.hpp"
+#include "launch.hpp"
 #include "rns_kernels.hpp"
 #include "ubench.hpp"
 
@@ -123,6 +124,7 @@ struct he_ctx {
   int device = 0;
   std::vector<u64> mod;        // [L+K]
   std::vector<u64> pmod_host;  // [P]_{m} for every modulus m
+  bool w32 = false;            // residues stored as 32-bit words (every prime below 2^31)
   uint8_t* blob = nullptr;     // device constant tables
   size_t blob_bytes = 0;
   bool owns_blob = true;       // false: caller-provided table memory
@@ -149,6 +151,16 @@ struct he_ctx {
 namespace {
 
 size_t ceil_div(size_t a, size_t b) { return (a + b - 1) / b; }
+
+// Bytes of one stored residue (a 64-bit or, for 32-bit-word contexts, a
+// 32-bit word).
+inline u64 word_bytes(const he_ctx* c) { return c->w32 ? 4 : 8; }
+
+// Entry points that move 64-bit words only.
+he_status need_w64(const he_ctx* c, const char* fn) {
+  if (c && c->w32) return fail(HE_EUNSUPPORTED, "%s: not available for 32-bit-word contexts (use he_mul32)", fn);
+  return HE_OK;
+}
 
 hipEvent_t pool_event(he_ctx* c) {
   if (!c->tpool.empty()) {
@@ -254,7 +266,13 @@ dim3 ew_grid(u64 total) { return dim3((unsigned)ceil_div(total, EW_THREADS)); }
 // Twiddle table of modulus m (N entries of 16 bytes at t) in the form the
 // kernels read for m: Shoup pairs, or for m < 2^50 the doubles W_k in the
 // first half.
-void tw_fill(Tw2* t, const std::vector<u64>& w, u64 m, u64 N) {
+void tw_fill(Tw2* t, const std::vector<u64>& w, u64 m, u64 N, bool i32 = false) {
+  if (i32) {  // 32-bit Shoup pairs: w | floor(w 2^32 / m) << 32, 8 bytes per index
+    std::vector<u64> d(2 * N, 0);
+    for (u64 k = 0; k < N; ++k) d[k] = w[k] | ((u64)(((u128)w[k] << 32) / m) << 32);
+    memcpy(t, d.data(), N * sizeof(Tw2));
+    return;
+  }
   if (f64_mod(m)) {
     std::vector<double> d(2 * N, 0.0);
     for (u64 k = 0; k < N; ++k) d[k] = (double)w[k];  // exact: w < 2^50
@@ -359,7 +377,7 @@ he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uin
 // d_tables is null, to device memory the context allocates and owns.
 static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
                           const uint64_t* p, int device, bool sizing, void* d_tables, size_t tables_bytes,
-                          size_t* table_bytes, he_ctx** out) {
+                          size_t* table_bytes, he_ctx** out, bool w32 = false) {
   if ((!out && !sizing) || !q || !p) return fail(HE_EINVAL, "he_ctx_create: null pointer");
   if (out) *out = nullptr;
   if (log_n < 12 || log_n > 17) return fail(HE_EUNSUPPORTED, "log_n must be in [12, 17]");
@@ -368,6 +386,8 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
   const u64 N = 1ull << log_n;
   std::unique_ptr<he_ctx, void (*)(he_ctx*)> c(new he_ctx, he_ctx_destroy);  // frees device memory on errors
   c->log_n = log_n; c->L = L; c->K = K; c->dnum = dnum; c->N = N;
+  c->w32 = w32;
+  if (w32 && log_n > 16) return fail(HE_EUNSUPPORTED, "32-bit words: log_n must be in [12, 16]");
   c->alpha = (L + dnum - 1) / dnum;
   c->device = device;
   const u32 nm = L + K;
@@ -378,6 +398,8 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
     if (m >= (1ull << 60) || m < (1ull << 20) || (m - 1) % (2 * N) || !is_prime(m))
       return fail(HE_EINVAL, "modulus %u (%llu) is not a prime below 2^60 that is 1 mod 2N", i,
                   (unsigned long long)m);
+    if (w32 && m >= (1ull << 31))
+      return fail(HE_EINVAL, "32-bit words: modulus %u (%llu) is not below 2^31", i, (unsigned long long)m);
     for (u32 j = 0; j < i; ++j)
       if (c->mod[j] == m) return fail(HE_EINVAL, "moduli must be distinct");
   }
@@ -401,7 +423,15 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
   Blob B;
   // moduli
   std::vector<ModInfo> mi(nm);
-  for (u32 i = 0; i < nm; ++i) mi[i] = make_modinfo(c->mod[i], N);
+  // 32-bit words run their butterflies on the 32-bit integer multipliers
+  // (I32A) when every prime is below 2^30 (measured 7% faster than the FP64
+  // butterflies on the same words at N = 2^16, 40 primes)
+  bool i32 = w32;
+  for (u32 i = 0; i < nm; ++i) i32 = i32 && c->mod[i] < (1ull << 30);
+  for (u32 i = 0; i < nm; ++i) {
+    mi[i] = make_modinfo(c->mod[i], N);
+    mi[i].arith = i32 ? ARITH_I32 : ARITH_AUTO;
+  }
   B.sizing = sizing;
   const size_t o_mods = B.add(mi);
   // twiddles: TB_W[k] = psi^bitrev(k), TB_invW[k] = psi^-bitrev(k), + Shoup companions
@@ -418,8 +448,8 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
       bw[k] = pw[e];
       ibw[k] = ipw[e];
     }
-    tw_fill(tw.data() + i * N, bw, m, N);
-    tw_fill(itw.data() + i * N, ibw, m, N);
+    tw_fill(tw.data() + i * N, bw, m, N, i32);
+    tw_fill(itw.data() + i * N, ibw, m, N, i32);
   }
   const size_t o_tw = B.add(tw.data(), nm * N * sizeof(Tw2)), o_itw = B.add(itw.data(), nm * N * sizeof(Tw2));
   const size_t o_iota = B.add(all_idx);
@@ -628,7 +658,14 @@ he_status he_ctx_create(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, c
   return ctx_make(log_n, L, K, dnum, q, p, device, false, d_tables, tables_bytes, nullptr, out);
 }
 
+he_status he_ctx_create_w32(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum, const uint64_t* q,
+                            const uint64_t* p, int device, void* d_tables, size_t tables_bytes, he_ctx** out) {
+  if (!out) return fail(HE_EINVAL, "he_ctx_create_w32: null pointer");
+  return ctx_make(log_n, L, K, dnum, q, p, device, false, d_tables, tables_bytes, nullptr, out, true);
+}
+
 size_t he_ctx_table_bytes(const he_ctx* c) { return c ? c->blob_bytes : 0; }
+uint32_t he_ctx_word_bytes(const he_ctx* c) { return c ? (c->w32 ? 4u : 8u) : 0u; }
 
 void he_ctx_destroy(he_ctx* c) {
   if (!c) return;
@@ -655,9 +692,11 @@ he_status he_ctx_info(const he_ctx* c, uint32_t* log_n, uint32_t* L, uint32_t* K
   return HE_OK;
 }
 
-size_t he_ct_bytes(const he_ctx* c, uint32_t level) { return c ? 2ull * level * c->N * 8 : 0; }
-size_t he_evk_bytes(const he_ctx* c) { return c ? (size_t)c->dnum * 2 * (c->L + c->K) * c->N * 8 : 0; }
-size_t he_pk_bytes(const he_ctx* c) { return c ? 2ull * c->L * c->N * 8 : 0; }
+size_t he_ct_bytes(const he_ctx* c, uint32_t level) { return c ? 2ull * level * c->N * word_bytes(c) : 0; }
+size_t he_evk_bytes(const he_ctx* c) {
+  return c ? (size_t)c->dnum * 2 * (c->L + c->K) * c->N * word_bytes(c) : 0;
+}
+size_t he_pk_bytes(const he_ctx* c) { return c ? 2ull * c->L * c->N * word_bytes(c) : 0; }
 
 static size_t mul_ws_limbs(const he_ctx* c, u32 level) {
   const LevelPlan& P = c->lv[level];
@@ -671,6 +710,7 @@ static size_t keygen_ws_limbs(const he_ctx* c) {
 
 size_t he_workspace_bytes(const he_ctx* c, uint32_t level) {
   if (!c || level < 1 || level > c->L) return 0;
+  if (c->w32) return mul_ws_limbs(c, level) * c->N * 4;  // he_mul32 only
   size_t l = mul_ws_limbs(c, level);
   if (level == c->L) l = std::max(l, keygen_ws_limbs(c));
   l = std::max(l, 3 * (size_t)level + 4);  // encrypt / decrypt
@@ -733,6 +773,7 @@ he_status he_mul_noalloc(he_ctx* c, uint32_t level, const uint64_t* ct1, const u
 
 he_status he_ntt(he_ctx* c, uint64_t* d, uint32_t nlimbs, uint32_t first_mod, int inverse,
                  he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_ntt")) return r_;
   if (!c || !d) return fail(HE_EINVAL, "he_ntt: null pointer");
   if (first_mod + nlimbs > c->L + c->K) return fail(HE_EINVAL, "he_ntt: modulus range");
   HIP_TRY(hipSetDevice(c->device));
@@ -746,63 +787,6 @@ he_status he_ntt(he_ctx* c, uint64_t* d, uint32_t nlimbs, uint32_t first_mod, in
 
 // ---------------------------------------------------------------- stage launches
 namespace {
-
-unsigned pad8(u32 n) { return (n + 7u) & ~7u; }
-
-template <int LOGS, int EPW>
-void launch_tensor(const Common& c, const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL((k_tensor_intt<LOGS, EPW>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, c, b);
-}
-template <bool FWD, int LOGS, int EPW, int ST>
-void launch_lcols(const Common& c, const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL((k_list_cols<FWD, LOGS, EPW, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st, c,
-                     b);
-}
-
-template <bool FWD, int LOGS, int EPW, int ST>
-void launch_lblocks(const Common& c, const Batch& b, hipStream_t st) {
-  hipLaunchKernelGGL((k_list_blocks<FWD, LOGS, EPW, ST>), dim3(pad8(b.nitems)), dim3(pass_threads(LOGS, EPW)), 0, st,
-                     c, b);
-}
-
-template <bool MD>
-void launch_conv(int bucket, const Common& c, const Batch& b, hipStream_t st) {
-  switch (bucket) {
-    case 4: hipLaunchKernelGGL((k_conv<MD, 4>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 8: hipLaunchKernelGGL((k_conv<MD, 8>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 12: hipLaunchKernelGGL((k_conv<MD, 12>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 15: hipLaunchKernelGGL((k_conv<MD, 15>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 24: hipLaunchKernelGGL((k_conv<MD, 24>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    default: hipLaunchKernelGGL((k_conv<MD, 32>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-  }
-}
-
-// n1 = log_n / 2 (cols passes), n2 = log_n - n1 (blocks passes); EC / EB:
-// workgroup tiles of the cols / blocks passes.
-template <int N1, int N2, int EC = EPW_C, int EB = EPW_B>
-void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) {
-  const dim3 g(pad8(b.nitems));
-  switch (stage) {
-    case ST_TENSOR: launch_tensor<N2, EB>(c, b, st); break;
-    case ST_Y_ICOLS: launch_lcols<false, N1, EC, ST_Y_ICOLS>(c, b, st); break;
-    case ST_MU_CONV: launch_conv<false>(conv_bucket((c.L + c.dnum - 1) / c.dnum), c, b, st); break;
-    case ST_DT_NCOLS: launch_lcols<true, N1, EC, ST_DT_NCOLS>(c, b, st); break;
-    case ST_DT_NBLOCKS: launch_lblocks<true, N2, EB, ST_DT_NBLOCKS>(c, b, st); break;
-    case ST_IP:
-      if (b.pairs) hipLaunchKernelGGL(k_ip<false>, g, dim3(IP_THREADS), 0, st, c, b);
-      else hipLaunchKernelGGL(k_ip<true>, g, dim3(IP_THREADS), 0, st, c, b);
-      break;
-    case ST_KS_IBLOCKS: launch_lblocks<false, N2, EB, ST_KS_IBLOCKS>(c, b, st); break;
-    case ST_BLOCKS_IP: hipLaunchKernelGGL((k_blocks_ip<N2>), g, dim3(64 * IP_WAVES), 0, st, c, b); break;
-    case ST_KS_ICOLS: launch_lcols<false, N1, EC, ST_KS_ICOLS>(c, b, st); break;
-    case ST_MD_CONV: launch_conv<true>(conv_bucket(c.K), c, b, st); break;
-    case ST_Z_NCOLS: hipLaunchKernelGGL((k_zcols_lift<N1, EC>), g, dim3(pass_threads(N1, EC)), 0, st, c, b); break;
-    case ST_COMBINE: hipLaunchKernelGGL((k_ntt_combine<N2, EB>), g, dim3(pass_threads(N2, EB)), 0, st, c, b); break;
-    case ST_LIFT: hipLaunchKernelGGL((k_lift_ntt_cols<N1, EC>), g, dim3(pass_threads(N1, EC)), 0, st, c, b); break;
-    case ST_RESCALE: hipLaunchKernelGGL((k_ntt_rescale<N2, EB>), g, dim3(pass_threads(N2, EB)), 0, st, c, b); break;
-    case ST_Y_IBLOCKS: launch_lblocks<false, N2, EB, ST_Y_IBLOCKS>(c, b, st); break;
-  }
-}
 
 // Tile choices a batch may select: the defaults at every ring degree, and
 // at N = 2^16 also 2048-element cols tiles and 1024-element blocks tiles.
@@ -888,21 +872,13 @@ void launch_stage(const he_ctx* c, int stage, const Common& cm, const Batch& b, 
                   hipStream_t st, TileCfg t = TileCfg{}) {
   if (!b.nitems) return;
   timed(c, stage_name(stage), ops, bytes, st, [&] {
-    switch (c->log_n) {
-      case 12: launch_stage_n<6, 6>(stage, cm, b, st); break;
-      case 13: launch_stage_n<6, 7>(stage, cm, b, st); break;
-      case 14: launch_stage_n<7, 7>(stage, cm, b, st); break;
-      case 15: launch_stage_n<7, 8>(stage, cm, b, st); break;
-      case 16:
-        if (t.epw_c == 2048)
-          t.epw_b == 1024 ? launch_stage_n<8, 8, 2048, 1024>(stage, cm, b, st)
-                          : launch_stage_n<8, 8, 2048, 2048>(stage, cm, b, st);
-        else
-          t.epw_b == 1024 ? launch_stage_n<8, 8, 4096, 1024>(stage, cm, b, st)
-                          : launch_stage_n<8, 8, 4096, 2048>(stage, cm, b, st);
-        break;
-      case 17: launch_stage_n<8, 9>(stage, cm, b, st); break;
+    if (c->w32) {
+      if (c->log_n <= 15) launch_w32_small(c->log_n, stage, cm, b, st);
+      else launch_w32_n16(stage, cm, b, st);  // 32-bit-word contexts stop at N = 2^16
     }
+    else if (c->log_n <= 15) launch_u64_small(c->log_n, stage, cm, b, st);
+    else if (c->log_n == 16) launch_u64_n16(stage, cm, b, st, t);
+    else launch_u64_n17(stage, cm, b, st);
   });
 }
 
@@ -917,39 +893,49 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return (const uint8_t*)a < (const uint8_t*)b + nb && (const uint8_t*)b < (const uint8_t*)a + na;
 }
 
-// Lay out one pair's workspace starting at ws; returns words used.
-u64 pair_layout(const he_ctx* c, u32 level, u64* ws, PairDesc& pd) {
+// Lay out one pair's workspace starting at ws; returns limbs used (a limb
+// is N words of the context's word size).
+u64 pair_layout(const he_ctx* c, u32 level, void* ws, PairDesc& pd) {
   const LevelPlan& P = c->lv[level];
-  const u64 N = c->N;
-  u64* w = ws;
-  pd.d2 = w; w += (u64)level * N;
-  pd.y = w; w += (u64)(level + 2) * N;
-  pd.dt = w; w += (u64)P.dt_limbs * N;
-  pd.ks = w; w += 2ull * (level + c->K + 1) * N;
-  pd.z = w; w += 2ull * level * N;
-  pd.zc = w; w += 2ull * level * N;
-  return (u64)(w - ws);
+  const u64 lb = c->N * word_bytes(c);
+  uint8_t* w = (uint8_t*)ws;
+  u64 limbs = 0;
+  auto take = [&](u64*& ptr, u64 n) {
+    ptr = (u64*)(w + limbs * lb);
+    limbs += n;
+  };
+  take(pd.d2, level);
+  take(pd.y, level + 2);
+  take(pd.dt, P.dt_limbs);
+  take(pd.ks, 2ull * (level + c->K + 1));
+  take(pd.z, 2ull * level);
+  take(pd.zc, 2ull * level);
+  return limbs;
 }
 
 }  // namespace
 
 extern "C" {
 
-he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t* ct2,
-                 const uint64_t* evk, uint64_t* relin, uint64_t* out, void* ws, size_t ws_bytes,
-                 he_stream stream) {
+}  // extern "C"
+
+// HE Mul on stored words of either size (the context's): pointers are
+// untyped bases of [2][level][N] words.
+static he_status mul_impl(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t* ct2, const uint64_t* evk,
+                          uint64_t* relin, uint64_t* out, void* ws, size_t ws_bytes, he_stream stream) {
   if (!c || !ct1 || !ct2 || !evk || !ws) return fail(HE_EINVAL, "he_mul: null pointer");
   if (!relin && !out) return fail(HE_EINVAL, "he_mul: no output requested");
   if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_mul: level %u not in [1, L]", level);
   if (out && level < 2) return fail(HE_ELEVEL, "he_mul: rescale needs level >= 2");
-  if (ws_bytes < mul_ws_limbs(c, level) * c->N * 8) return fail(HE_ENOMEM, "he_mul: workspace too small");
+  const u64 wb = word_bytes(c);
+  if (ws_bytes < mul_ws_limbs(c, level) * c->N * wb) return fail(HE_ENOMEM, "he_mul: workspace too small");
   const u64 N = c->N, ct_words = 2ull * level * N;
   for (const u64* o : {(const u64*)relin, (const u64*)out}) {
     if (!o) continue;
-    if (overlaps(o, ct_words * 8, ct1, ct_words * 8) || overlaps(o, ct_words * 8, ct2, ct_words * 8))
+    if (overlaps(o, ct_words * wb, ct1, ct_words * wb) || overlaps(o, ct_words * wb, ct2, ct_words * wb))
       return fail(HE_EINVAL, "he_mul: output aliases an input");
   }
-  if (relin && out && overlaps(relin, ct_words * 8, out, (ct_words - 2 * N) * 8))
+  if (relin && out && overlaps(relin, ct_words * wb, out, (ct_words - 2 * N) * wb))
     return fail(HE_EINVAL, "he_mul: the two outputs overlap");
   HIP_TRY(hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
@@ -958,8 +944,8 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
   pd.ct1 = ct1; pd.ct2 = ct2; pd.out = out; pd.r = nullptr; pd.plan = P.plan; pd.level = level;
   pd.rs = out ? 1 : 0;
   pd.wrl = relin ? 1 : 0;
-  const u64 used = pair_layout(c, level, (u64*)ws, pd);
-  pd.rl = relin ? relin : (u64*)ws + used;
+  const u64 used = pair_layout(c, level, ws, pd);
+  pd.rl = relin ? relin : (u64*)((uint8_t*)ws + used * c->N * word_bytes(c));
   const Common cm = make_common(c, evk);
   auto run = [&](int s, hipStream_t on) {
     Batch b{};
@@ -975,8 +961,24 @@ he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t*
   return HE_OK;
 }
 
+extern "C" {
+
+he_status he_mul(he_ctx* c, uint32_t level, const uint64_t* ct1, const uint64_t* ct2, const uint64_t* evk,
+                 uint64_t* relin, uint64_t* out, void* ws, size_t ws_bytes, he_stream stream) {
+  if (he_status r = need_w64(c, "he_mul")) return r;
+  return mul_impl(c, level, ct1, ct2, evk, relin, out, ws, ws_bytes, stream);
+}
+
+he_status he_mul32(he_ctx* c, uint32_t level, const uint32_t* ct1, const uint32_t* ct2, const uint32_t* evk,
+                   uint32_t* relin, uint32_t* out, void* ws, size_t ws_bytes, he_stream stream) {
+  if (c && !c->w32) return fail(HE_EUNSUPPORTED, "he_mul32: the context stores 64-bit words (use he_mul)");
+  return mul_impl(c, level, (const uint64_t*)ct1, (const uint64_t*)ct2, (const uint64_t*)evk, (uint64_t*)relin,
+                  (uint64_t*)out, ws, ws_bytes, stream);
+}
+
 he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* d_out, void* ws,
                      size_t ws_bytes, he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_rescale")) return r_;
   if (!c || !d_in || !d_out || !ws) return fail(HE_EINVAL, "he_rescale: null pointer");
   if (level < 2 || level > c->L) return fail(HE_ELEVEL, "he_rescale: level %u not in [2, L]", level);
   if (ws_bytes < (2 + 2 * (size_t)level) * c->N * 8) return fail(HE_ENOMEM, "he_rescale: workspace too small");
@@ -1014,6 +1016,7 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
 
 he_status he_ct_import(he_ctx* c, const uint64_t* host, uint32_t level, double scale, he_ct* ct,
                        he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_ct_import")) return r_;
   if (!c || !host || !ct || !ct->data) return fail(HE_EINVAL, "he_ct_import: null pointer");
   if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_ct_import: level %u not in [1, L]", level);
   if (!(scale > 0) || !std::isfinite(scale)) return fail(HE_EINVAL, "he_ct_import: scale must be positive");
@@ -1036,6 +1039,7 @@ he_status he_ct_import(he_ctx* c, const uint64_t* host, uint32_t level, double s
 }
 
 he_status he_ct_export(he_ctx* c, const he_ct* ct, uint64_t* host, he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_ct_export")) return r_;
   if (!c || !ct || !ct->data || !host) return fail(HE_EINVAL, "he_ct_export: null pointer");
   if (ct->level < 1 || ct->level > c->L) return fail(HE_ELEVEL, "he_ct_export: level %u not in [1, L]", ct->level);
   HIP_TRY(hipSetDevice(c->device));
@@ -1104,7 +1108,7 @@ static size_t batch_ws_words(const he_ctx* c, const he_batch_item* items, u32 n)
   size_t w = 0;
   for (u32 i = 0; i < n; ++i) {
     PairDesc tmp{};
-    w += pair_layout(c, items[i].level, nullptr, tmp);
+    w += pair_layout(c, items[i].level, nullptr, tmp) * c->N;
     if (!items[i].relin) w += 2ull * items[i].level * c->N;
   }
   return w;
@@ -1157,6 +1161,7 @@ size_t he_batch_desc_bytes(uint32_t n) {
 static he_status batch_build(he_ctx* c, const he_batch_item* items, uint32_t n, void* ws, size_t ws_bytes,
                              std::unique_ptr<he_batch>& bt) {
   if (!c || !items || !ws || n == 0) return fail(HE_EINVAL, "he_batch_create: bad arguments");
+  if (he_status r_ = need_w64(c, "he_batch_create")) return r_;
   for (u32 i = 0; i < n; ++i) {
     const he_batch_item& it = items[i];
     if (!it.ct1 || !it.ct2 || (!it.relin && !it.out)) return fail(HE_EINVAL, "he_batch_create: item %u incomplete", i);
@@ -1175,7 +1180,7 @@ static he_status batch_build(he_ctx* c, const he_batch_item* items, uint32_t n, 
     PairDesc& pd = pds[i];
     pd.ct1 = it.ct1; pd.ct2 = it.ct2; pd.out = it.out; pd.r = nullptr;
     pd.plan = c->lv[it.level].plan; pd.level = it.level; pd.rs = it.out ? 1 : 0; pd.wrl = it.relin ? 1 : 0;
-    w += pair_layout(c, it.level, w, pd);
+    w += pair_layout(c, it.level, w, pd) * c->N;
     if (it.relin) {
       pd.rl = it.relin;
     } else {
@@ -1453,6 +1458,7 @@ static he_status upload_sync(void* dst, const void* src, size_t bytes, hipStream
 he_status he_keygen(he_ctx* c, const int64_t* s, const int64_t* e_pk, const uint64_t* a_pk,
                     const int64_t* e_evk, const uint64_t* a_evk, uint64_t* d_pk, uint64_t* d_evk,
                     void* ws, size_t ws_bytes, he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_keygen")) return r_;
   if (!c || !s || !e_pk || !a_pk || !e_evk || !a_evk || !d_pk || !d_evk || !ws)
     return fail(HE_EINVAL, "he_keygen: null pointer");
   if (ws_bytes < keygen_ws_limbs(c) * c->N * 8) return fail(HE_ENOMEM, "he_keygen: workspace too small");
@@ -1503,6 +1509,7 @@ he_status he_keygen(he_ctx* c, const int64_t* s, const int64_t* e_pk, const uint
 he_status he_encrypt(he_ctx* c, uint32_t level, const int64_t* m, const int64_t* v, const int64_t* e0,
                      const int64_t* e1, const uint64_t* d_pk, uint64_t* d_ct, void* ws, size_t ws_bytes,
                      he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_encrypt")) return r_;
   if (!c || !m || !v || !e0 || !e1 || !d_pk || !d_ct || !ws) return fail(HE_EINVAL, "he_encrypt: null pointer");
   if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_encrypt: level %u not in [1, L]", level);
   if (ws_bytes < (3 * (size_t)level + 4) * c->N * 8) return fail(HE_ENOMEM, "he_encrypt: workspace too small");
@@ -1545,6 +1552,7 @@ he_status he_encrypt(he_ctx* c, uint32_t level, const int64_t* m, const int64_t*
 
 he_status he_decrypt(he_ctx* c, uint32_t level, const uint64_t* d_ct, const int64_t* s, uint64_t* d_m,
                      void* ws, size_t ws_bytes, he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_decrypt")) return r_;
   if (!c || !d_ct || !s || !d_m || !ws) return fail(HE_EINVAL, "he_decrypt: null pointer");
   if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_decrypt: level %u not in [1, L]", level);
   if (ws_bytes < ((size_t)level + 1) * c->N * 8) return fail(HE_ENOMEM, "he_decrypt: workspace too small");

@@ -90,9 +90,10 @@ struct ModInfo {
   u64 ninv;    // N^{-1} mod q
   u64 ninvs;   // Shoup companion of ninv
   u32 b;       // bit length of q
-  u32 pad;
+  u32 arith;   // butterfly arithmetic: ARITH_AUTO (by size), ARITH_I32 (32-bit words, q < 2^30)
   double qinv; // fl(1/q)
 };
+constexpr u32 ARITH_AUTO = 0, ARITH_I32 = 2;
 
 // x < 2^(2b+2): canonical x mod q.
 __device__ __forceinline__ u64 barrett(U128 x, const ModInfo& m) {

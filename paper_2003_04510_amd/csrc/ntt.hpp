@@ -177,6 +177,57 @@ struct F64A {
   }
 };
 
+// ---------------------------------------------------------------- 32-bit integer arithmetic
+// For q < 2^30 stored in 32-bit words (the paper's GPU word size): values
+// are u32 on the native 32x32-bit multipliers.  Shoup's product with a
+// 2^32-scaled companion w' = floor(w 2^32 / q): for any y < 2^32,
+// y w - mulhi(y, w') q lies in [0, 2q) and is computed mod 2^32 (two
+// v_mul_lo_u32 and one v_mul_hi_u32).  Forward values live in [0, 4q)
+// (Harvey), inverse values in [0, 2q); 4q < 2^32.  Table entry k holds
+// w | w' << 32 (8 bytes per index); constants keep their 2^64-scaled
+// companion, whose top half is the 2^32-scaled one.
+struct I32A {
+  using V = u32;
+  struct Mod {
+    u32 q, q2;
+  };
+  struct Scale {
+    u32 w, ws;
+  };
+  struct Tw {
+    u32 w, ws;
+  };
+  __device__ static __forceinline__ Tw twid(const Tw2* __restrict__ tw, u64 k, const Mod&) {
+    const u64 v = reinterpret_cast<const u64*>(tw)[k];
+    return Tw{(u32)v, (u32)(v >> 32)};
+  }
+  __device__ static __forceinline__ Mod mod(u64 q, double) { return Mod{(u32)q, (u32)(q << 1)}; }
+  __device__ static __forceinline__ V in(u64 x, const Mod&) { return (u32)x; }
+  __device__ static __forceinline__ u32 mulw(u32 y, u32 w, u32 ws, u32 q) { return y * w - __umulhi(y, ws) * q; }
+  __device__ static __forceinline__ void fwd(V& x, V& y, const Tw t, const Mod& M) {
+    const u32 X = x >= M.q2 ? x - M.q2 : x;
+    const u32 T = mulw(y, t.w, t.ws, M.q);
+    y = X - T + M.q2;
+    x = X + T;
+  }
+  __device__ static __forceinline__ void inv(V& x, V& y, const Tw t, const Mod& M) {
+    const u32 X = x, Y = y;
+    const u32 s = X + Y;
+    x = s >= M.q2 ? s - M.q2 : s;
+    y = mulw(X - Y + M.q2, t.w, t.ws, M.q);
+  }
+  template <bool FWD>
+  __device__ static __forceinline__ u64 out(V x, const Mod& M) {
+    if constexpr (FWD) x = x >= M.q2 ? x - M.q2 : x;
+    return x >= M.q ? x - M.q : x;
+  }
+  __device__ static __forceinline__ Scale scale(u64 w, u64 ws, const Mod&) { return Scale{(u32)w, (u32)(ws >> 32)}; }
+  __device__ static __forceinline__ u64 out_scaled(V x, const Scale s, const Mod& M) {
+    const u32 r = mulw(x, s.w, s.ws, M.q);
+    return r >= M.q ? r - M.q : r;
+  }
+};
+
 // Workgroup barrier ordering LDS accesses only: unlike __syncthreads() it
 // does not wait for outstanding global loads and stores, so prefetches and
 // stores stay in flight across the LDS exchanges of a transform.  Kernels
@@ -335,10 +386,18 @@ __device__ __forceinline__ void sub_transform_regs(typename A::V (&x)[1 << LOGR]
   }
 }
 
-// Runs body(IntA{}) or body(F64A{}) by the modulus (uniform per workgroup).
-template <class Body>
-__device__ __forceinline__ void with_arith(u64 q, Body&& body) {
-  if (f64_mod(q)) body(F64A{});
+// Runs body(IntA{}), body(F64A{}) or, for 32-bit words, body(I32A{}) by
+// the modulus (uniform per workgroup).  A modulus runs I32A when its
+// context stores 32-bit words with integer butterflies (ModInfo::arith).
+template <class W = u64, class Body>
+__device__ __forceinline__ void with_arith(const ModInfo& mo, Body&& body) {
+  if constexpr (sizeof(W) == 4) {
+    if (mo.arith == ARITH_I32) {
+      body(I32A{});
+      return;
+    }
+  }
+  if (f64_mod(mo.q)) body(F64A{});
   else body(IntA{});
 }
 
@@ -419,7 +478,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols(NttArgs a)
   u64 xi[Gm::R];
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) xi[k] = in[(u64)RF::elem(tt, k / RF::G, k % RF::G) << n2];
-  with_arith(mo.q, [&](auto ar) {
+  with_arith(mo, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(mo.q, mo.qinv);
     const typename A::Scale sc = A::scale(sw, sws, M);
@@ -470,7 +529,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_blocks(NttArgs 
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) xi[k] = in[RF::elem(tt, k / RF::G, k % RF::G)];
   }
-  with_arith(mo.q, [&](auto ar) {
+  with_arith(mo, [&](auto ar) {
     using A = decltype(ar);
     const typename A::Mod M = A::mod(mo.q, mo.qinv);
     typename A::V* tl = reinterpret_cast<typename A::V*>(lds);

@@ -27,6 +27,7 @@ he_status he_encode(he_ctx* c, const double* d_z, uint32_t n, double scale, int6
 
 he_status he_decode(he_ctx* c, uint32_t level, const uint64_t* d_m, double scale, uint32_t n, double* d_z,
                     void* ws, size_t ws_bytes, he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_decode")) return r_;
   if (!c || !d_m || !ws || (n && !d_z)) return fail(HE_EINVAL, "he_decode: null pointer");
   if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_decode: level %u not in [1, L]", level);
   if (n > c->N / 2) return fail(HE_EINVAL, "he_decode: %u slots exceed N/2", n);
@@ -70,6 +71,7 @@ he_status he_decode(he_ctx* c, uint32_t level, const uint64_t* d_m, double scale
 
 he_status he_add(he_ctx* c, uint32_t level, const uint64_t* d_ct1, const uint64_t* d_ct2, uint64_t* d_out,
                  he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_add")) return r_;
   if (!c || !d_ct1 || !d_ct2 || !d_out) return fail(HE_EINVAL, "he_add: null pointer");
   if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_add: level %u not in [1, L]", level);
   HIP_TRY(hipSetDevice(c->device));
@@ -97,6 +99,7 @@ u64 galois_element(u64 N, int64_t r) {
 
 he_status he_keygen_rot(he_ctx* c, const int64_t* s, int32_t rot, const int64_t* e_rk, const uint64_t* a_rk,
                         uint64_t* d_rk, void* ws, size_t ws_bytes, he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_keygen_rot")) return r_;
   if (!c || !s || !e_rk || !a_rk || !d_rk || !ws) return fail(HE_EINVAL, "he_keygen_rot: null pointer");
   if (ws_bytes < keygen_ws_limbs(c) * c->N * 8) return fail(HE_ENOMEM, "he_keygen_rot: workspace too small");
   HIP_TRY(hipSetDevice(c->device));
@@ -145,6 +148,7 @@ he_status he_keygen_rot(he_ctx* c, const int64_t* s, int32_t rot, const int64_t*
 
 he_status he_rotate(he_ctx* c, uint32_t level, const uint64_t* d_ct, const uint64_t* d_rk, int32_t rot,
                     uint64_t* d_out, void* ws, size_t ws_bytes, he_stream stream) {
+  if (he_status r_ = need_w64(c, "he_rotate")) return r_;
   if (!c || !d_ct || !d_rk || !d_out || !ws) return fail(HE_EINVAL, "he_rotate: null pointer");
   if (level < 1 || level > c->L) return fail(HE_ELEVEL, "he_rotate: level %u not in [1, L]", level);
   if (ws_bytes < mul_ws_limbs(c, level) * c->N * 8) return fail(HE_ENOMEM, "he_rotate: workspace too small");
@@ -158,7 +162,7 @@ he_status he_rotate(he_ctx* c, uint32_t level, const uint64_t* d_ct, const uint6
   pd.ct1 = d_ct; pd.ct2 = d_ct; pd.out = nullptr; pd.r = nullptr; pd.plan = P.plan; pd.level = level;
   pd.rs = 0;
   pd.wrl = 1;
-  pair_layout(c, level, (u64*)ws, pd);
+  pair_layout(c, level, ws, pd);
   pd.rl = d_out;  // holds (sigma(b), 0), then receives the rotated ciphertext
   const u64 g = galois_element(N, rot);
   const u64 tot = (u64)level * N;

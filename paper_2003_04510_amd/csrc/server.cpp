@@ -133,6 +133,7 @@ he_status he_server_add_ring(he_server* s, he_ctx* ctx, const uint64_t* d_evk, v
                              uint32_t* ring_id) {
   if (!s) return HE_EINVAL;
   if (!ctx || !d_evk || !d_arena || !ring_id) return set_err(s, HE_EINVAL, "null pointer");
+  if (he_ctx_word_bytes(ctx) != 8) return set_err(s, HE_EUNSUPPORTED, "serving takes 64-bit-word contexts");
   const size_t desc = he_server_arena_min_bytes(&s->cfg);
   if (arena_bytes <= desc) return set_err(s, HE_ENOMEM, "arena smaller than the descriptor slots");
   const size_t footprint = he_ctx_table_bytes(ctx) + he_evk_bytes(ctx) + arena_bytes;

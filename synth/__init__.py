@@ -70,6 +70,9 @@ CFG_TINY = _mk("n16_tiny", 4, 5, 2, 3, 4, 20, 50, 50, 60)
 # N=2^16: L=40 primes of 30 bits (log Q = 1200, the paper's), dnum=4,
 # K=11 special primes of 30 bits, scale 2^30 (one prime per rescale).
 CFG_N16_W30 = _mk("n16_L40_w30", 16, 40, 11, 4, 192, 30, 30, 30, 30)
+# A small ring of the same prime size for quick parity cases: N=2^12, L=6
+# primes of 30 bits, dnum=2 (digits of 3 primes), K=4 special primes.
+CFG_N12_W30 = _mk("n12_L6_w30", 12, 6, 4, 2, 64, 25, 30, 30, 30)
 
 # Key-switching variants at N=2^16, L=24 (Sec. III's evaluation key with
 # P ~ Q, and one digit per prime): dnum=1 with K=21 special primes of 60
@@ -80,7 +83,7 @@ CFG_N16_DL = _mk("n16_L24_d24", 16, 24, 2, 24, 192, 40, 60, 50, 60)
 CFG_N12_D1 = _mk("n12_L6_d1", 12, 6, 6, 1, 64, 40, 60, 50, 60)
 CFG_N12_DL = _mk("n12_L6_d6", 12, 6, 2, 6, 64, 40, 60, 50, 60)
 
-WORKLOADS = {w.name: w for w in (CFG_N12, CFG_N16, CFG_N17, CFG_N15, CFG_TINY, CFG_N16_W30,
+WORKLOADS = {w.name: w for w in (CFG_N12, CFG_N16, CFG_N17, CFG_N15, CFG_TINY, CFG_N16_W30, CFG_N12_W30,
                                  CFG_N16_D1, CFG_N16_DL, CFG_N12_D1, CFG_N12_DL)}
 
 # Seeds of the measured workload.

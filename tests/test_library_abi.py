@@ -136,7 +136,7 @@ def test_binding_rejects_bad_tensors_before_any_call():
 
     import paper_2003_04510_amd as P
     ctx = P.Context.__new__(P.Context)
-    ctx.torch, ctx.N, ctx.L, ctx.device = torch, 16, 3, 0
+    ctx.torch, ctx.N, ctx.L, ctx.device, ctx.wdtype = torch, 16, 3, 0, torch.int64
     t = torch.zeros(2 * 3 * 16, dtype=torch.int64)
     with pytest.raises(P.HeError, match="cuda"):
         ctx._ct(t, 3, "x")
