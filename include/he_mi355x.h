@@ -257,6 +257,10 @@ void he_batch_destroy(he_batch* batch);
  * product and the special limbs' INTT blocks pass as one fused pass (less
  * HBM traffic, longer dependency chains per workgroup) instead of three;
  * it runs one digit per wavefront of a 4-wave workgroup, so dnum <= 4.
+ * radix: the register radix of the NTT passes' butterfly rounds (the paper
+ * sweeps the NTT radix, Table IX): 0 or the default (8 for the 256-point
+ * sub-transforms at N = 2^16) or, at N = 2^16, 16 (two radix-16 rounds, one
+ * LDS exchange fewer, half the waves).
  *
  * he_batch_set_sched: validates (HE_EUNSUPPORTED for tiles not available at
  * this ring degree or the fused pass with dnum > 4, HE_EINVAL for a bad
@@ -265,8 +269,9 @@ void he_batch_destroy(he_batch* batch);
  * he_batch_get_sched: the current schedule.
  * he_batch_autotune: runs the batch (overwriting its outputs with the same
  * values) as a graph `reps` times under each candidate schedule -- every
- * available tile pair with one chunk, then the best tiles with the fused
- * inner product (dnum <= 4), then the best of those with 2 and 4 chunks --
+ * available tile pair and radix with one chunk, then the best of those with
+ * the fused inner product (dnum <= 4), then the best so far with 2 and 4
+ * chunks --
  * times each with HIP events on `stream`, and installs the
  * fastest; *best and *best_ms (may be NULL) receive it and its time per
  * replay.  Synchronizes `stream`. */
@@ -275,11 +280,31 @@ typedef struct he_batch_sched {
   uint32_t blocks_tile;
   uint32_t chunks;
   uint32_t ip_fused;
+  uint32_t radix;  /* register radix of the NTT passes: 0 = the default (reported as its value), 16 at N = 2^16 */
 } he_batch_sched;
 he_status he_batch_set_sched(he_batch* batch, const he_batch_sched* sched, he_stream stream);
 he_status he_batch_get_sched(const he_batch* batch, he_batch_sched* sched);
 he_status he_batch_autotune(he_ctx* ctx, he_batch* batch, const uint64_t* d_evk, uint32_t reps, he_stream stream,
                             he_batch_sched* best, double* best_ms);
+
+/* Batch groups: batches of different contexts (ring sizes, levels, keys) on
+ * one device run as one unit, each batch's stage kernels on a stream of its
+ * own (batch 0 on `stream`, the others on streams the group owns, forked
+ * from and joined back to `stream` by events), so the rings overlap on the
+ * device; with use_graph != 0 the whole group is captured once into one HIP
+ * graph (recaptured when an evaluation key pointer changes) and replayed as
+ * a single launch.  d_evks[i] is batch i's evaluation key.  Every batch
+ * must run in one chunk (HE_EUNSUPPORTED at creation otherwise: the group
+ * already runs the rings side by side), and a batch whose schedule changed
+ * after the group was made is refused (HE_EUNSUPPORTED): make a new group.
+ * The batches must outlive the group; destroying the group does not
+ * destroy them.  (No paper passage: an implementation choice of
+ * how independent HE Muls share the device, as the paper's GPU mapping
+ * spreads independent work over the device, Sec. V-C.) */
+typedef struct he_batch_group he_batch_group;
+he_status he_batch_group_create(he_batch* const* batches, uint32_t n, he_batch_group** out);
+he_status he_mul_batch_group(he_batch_group* group, const uint64_t* const* d_evks, int use_graph, he_stream stream);
+void he_batch_group_destroy(he_batch_group* group);
 
 /* Serving: a request loop with continuous batching (host side, native).
  * he_server_add_ring registers a context with its resident evk and a

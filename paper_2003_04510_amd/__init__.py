@@ -6,5 +6,5 @@ include/he_mi355x.h).  This package only marshals arguments: PyTorch supplies
 device memory and streams.  There is no CPU fallback: if the library is not
 built, importing the binding raises.
 """
-from .binding import (Batch, BigContext, Ciphertext, Context, HeBusy, HeError, Server, load_library,  # noqa: F401
+from .binding import (Batch, BatchGroup, BigContext, Ciphertext, Context, HeBusy, HeError, Server, load_library,  # noqa: F401
                       workload_primes)

@@ -36,7 +36,7 @@ class BatchItem(ctypes.Structure):
 
 class BatchSched(ctypes.Structure):
     _fields_ = [("cols_tile", ctypes.c_uint32), ("blocks_tile", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
-                ("ip_fused", ctypes.c_uint32)]
+                ("ip_fused", ctypes.c_uint32), ("radix", ctypes.c_uint32)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -110,6 +110,10 @@ def load_library():
     L.he_batch_get_sched.argtypes = [vp, ctypes.POINTER(BatchSched)]
     L.he_batch_autotune.argtypes = [vp, vp, vp, u32, vp, ctypes.POINTER(BatchSched),
                                     ctypes.POINTER(ctypes.c_double)]
+    L.he_batch_group_create.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(vp)]
+    L.he_mul_batch_group.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
+    L.he_batch_group_destroy.argtypes = [vp]
+    L.he_batch_group_destroy.restype = None
     L.he_server_create.argtypes = [ctypes.POINTER(ServerCfg), ctypes.POINTER(vp)]
     L.he_server_arena_min_bytes.argtypes = [ctypes.POINTER(ServerCfg)]
     L.he_server_arena_min_bytes.restype = ctypes.c_size_t
@@ -146,7 +150,7 @@ def load_library():
               "he_mul_batch", "he_server_create", "he_server_add_ring", "he_server_submit", "he_server_progress",
               "he_server_poll", "he_server_stats", "he_big_ctx_create", "he_big_info", "he_big_evk_prepare",
               "he_big_mul", "he_big_timing_enable", "he_big_timing_read", "he_encode", "he_decode", "he_add", "he_rotate",
-              "he_keygen_rot", "he_ct_import", "he_ct_export", "he_mul_ct", "he_rescale_ct", "he_mul_noalloc", "he_valu_peaks", "he_ctx_create_w32", "he_mul32"):
+              "he_keygen_rot", "he_ct_import", "he_ct_export", "he_mul_ct", "he_rescale_ct", "he_mul_noalloc", "he_valu_peaks", "he_ctx_create_w32", "he_mul32", "he_batch_group_create", "he_mul_batch_group"):
         getattr(L, f).restype = st
     _lib = L
     return L
@@ -572,15 +576,16 @@ class Batch:
                                            self.ctx._dev(evk, self.ctx.evk_bytes() // 8, "batch: evk"), int(use_graph),
                                            self.ctx._stream()), "he_mul_batch")
 
-    def set_sched(self, cols_tile: int, blocks_tile: int, chunks: int, ip_fused: int = 0):
-        sc = BatchSched(cols_tile, blocks_tile, chunks, ip_fused)
+    def set_sched(self, cols_tile: int, blocks_tile: int, chunks: int, ip_fused: int = 0, radix: int = 0):
+        sc = BatchSched(cols_tile, blocks_tile, chunks, ip_fused, radix)
         _check(load_library().he_batch_set_sched(self._h, ctypes.byref(sc), self.ctx._stream()),
                "he_batch_set_sched")
 
     def sched(self):
         sc = BatchSched()
         _check(load_library().he_batch_get_sched(self._h, ctypes.byref(sc)), "he_batch_get_sched")
-        return {"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks, "ip_fused": sc.ip_fused}
+        return {"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks, "ip_fused": sc.ip_fused,
+                "radix": sc.radix}
 
     def autotune(self, evk, reps: int = 3):
         """Time every candidate schedule (graph replays) and keep the
@@ -591,11 +596,47 @@ class Batch:
                                                 self.ctx._stream(),
                                                 ctypes.byref(sc), ctypes.byref(ms)), "he_batch_autotune")
         return ({"cols_tile": sc.cols_tile, "blocks_tile": sc.blocks_tile, "chunks": sc.chunks,
-                 "ip_fused": sc.ip_fused}, ms.value)
+                 "ip_fused": sc.ip_fused, "radix": sc.radix}, ms.value)
 
     def close(self):
         if getattr(self, "_h", None):
             load_library().he_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchGroup:
+    """Batches of different contexts (ring sizes) run as one unit, each on a
+    stream of its own, captured into one HIP graph (he_batch_group_*)."""
+
+    def __init__(self, batches):
+        self.batches = list(batches)
+        if not self.batches:
+            raise HeError("BatchGroup: no batches")
+        dev = {b.ctx.device for b in self.batches}
+        if len(dev) != 1:
+            raise HeError("BatchGroup: batches on different devices")
+        arr = (vp * len(self.batches))(*[b._h.value for b in self.batches])
+        h = vp()
+        _check(load_library().he_batch_group_create(arr, len(self.batches), ctypes.byref(h)), "he_batch_group_create")
+        self._h = h
+
+    def run(self, evks, use_graph: bool = True):
+        if len(evks) != len(self.batches):
+            raise HeError("BatchGroup.run: one evaluation key per batch")
+        arr = (vp * len(evks))(*[b.ctx._dev(k, b.ctx.evk_bytes() // 8, "group evk %d" % i).value
+                                 for i, (b, k) in enumerate(zip(self.batches, evks))])
+        ctx0 = self.batches[0].ctx
+        _check(load_library().he_mul_batch_group(self._h, arr, int(use_graph), ctx0._stream()), "he_mul_batch_group")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().he_batch_group_destroy(self._h)
             self._h = None
 
     def __del__(self):

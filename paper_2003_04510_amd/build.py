@@ -14,7 +14,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhe_mi355x.so")
-SOURCES = ["he_lib.hip", "launch_u64_n16.hip", "launch_u64_n16b.hip", "launch_w32_n16.hip",
+SOURCES = ["he_lib.hip", "launch_u64_n16.hip", "launch_u64_n16b.hip", "launch_u64_n16r.hip", "launch_w32_n16.hip",
            "launch_w32.hip", "launch_u64_n17.hip", "launch_u64_small.hip", "host_math.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

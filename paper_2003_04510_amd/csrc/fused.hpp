@@ -57,6 +57,7 @@ constexpr int EPW_C = 4096, EPW_B = 2048;
 // separate launches (shorter dependency chains per workgroup).
 struct TileCfg {
   u32 epw_c = EPW_C, epw_b = EPW_B, fused_ip = 0;
+  u32 logr = 0;  // log2 register radix of both NTT passes (0: the default per sub-transform size)
 };
 constexpr int CONV_CPT = 2, CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
 constexpr int CONV_RUN = 15;  // sources whose 30x30-bit products a 64-bit sum takes without a carry
@@ -253,7 +254,7 @@ __device__ __forceinline__ U128 conv_sum(u64 sll, u64 slh, u64 shl, u64 shh) {
 // again, its INTT blocks pass into y[level + u] (rescale by linearity).
 template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common c, Batch b) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
   constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
@@ -440,7 +441,7 @@ __device__ __forceinline__ ListView list_view(const Common& c, const PairDesc& p
 
 template <class W, bool FWD, int LOGS, int EPW, int ST>
 __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& pd, u32 local, u64* lds) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
   constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
@@ -481,7 +482,7 @@ __device__ __forceinline__ void list_cols_item(const Common& c, const PairDesc& 
 
 template <class W, bool FWD, int LOGS, int EPW, int ST>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c, Batch b) {
-  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
+  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, tile_logr(EPW, LOGS)>::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_cols(Common c,
 // coalesced.
 template <class W, bool FWD, int LOGS, int EPW, int ST>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common c, Batch b) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
   constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
@@ -958,7 +959,7 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
 // Items (i, u, block tile), tile fastest.
 template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common c, Batch b) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
   constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
@@ -1053,7 +1054,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 // Items (u, column tile, i < level-1), i fastest.
 template <class W, int LOGS, int EPW>
 __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u32 local, u64* lds) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
   using RF = RoundShape<LOGS, LOGR, 0>;
@@ -1097,7 +1098,7 @@ __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u
 
 template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Common c, Batch b) {
-  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
+  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, tile_logr(EPW, LOGS)>::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
@@ -1112,12 +1113,12 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_lift_ntt_cols(Commo
 // and only limbs i < level-1 are transformed.
 template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_zcols_lift(Common c, Batch b) {
-  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, Radix<LOGS>::LOGR>::SUB];
+  __shared__ u64 lds[PassLayout<LOGS, true, EPW>::SUBS * Geo<LOGS, tile_logr(EPW, LOGS)>::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
   const PairDesc pd = resolve(b, uniform(w), local);
-  const u32 nz = uniform(2 * (pd.rs && !pd.wrl ? pd.level - 1 : pd.level) * cols_tiles(c.log_n, EPW));
+  const u32 nz = uniform(2 * (pd.rs && !pd.wrl ? pd.level - 1 : pd.level) * cols_tiles(c.log_n, tile_elems(EPW)));
   if (local < nz) list_cols_item<W, true, LOGS, EPW, ST_Z_NCOLS>(c, pd, local, lds);
   else lift_item<W, LOGS, EPW>(c, pd, local - nz, lds);
 }
@@ -1149,7 +1150,7 @@ static __global__ __launch_bounds__(256) void k_automorphism(const u64* ct, u64*
 // Items (i < level-1, u, block tile), tile fastest.
 template <class W, int LOGS, int EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common c, Batch b) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
   constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;

@@ -792,6 +792,7 @@ namespace {
 // at N = 2^16 also 2048-element cols tiles and 1024-element blocks tiles.
 bool tiles_supported(u32 log_n, TileCfg t) {
   if (t.fused_ip > 1) return false;
+  if (t.logr != 0 && !(log_n == 16 && t.logr == 4)) return false;  // radix 16 at N = 2^16 only
   if (t.epw_c == EPW_C && t.epw_b == EPW_B) return true;
   return log_n == 16 && (t.epw_c == 2048 || t.epw_c == 4096) && (t.epw_b == 1024 || t.epw_b == 2048);
 }
@@ -1098,6 +1099,8 @@ struct he_batch {
   std::vector<u32> cut{};              // chunk boundaries in pairs [chunks + 1]
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  u32 stamp = 0;                       // bumped when the schedule changes
+  u32 group_stamp = 0;                 // stamp a batch group's graph was captured with
   // cached graph of the whole batched HE Mul
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1255,9 +1258,12 @@ he_status he_batch_set_sched(he_batch* bt, const he_batch_sched* sc, he_stream s
   t.epw_c = sc->cols_tile;
   t.epw_b = sc->blocks_tile;
   t.fused_ip = sc->ip_fused;
+  // radix 0 or the default radix of the passes: default; 16 at N = 2^16: log2 4
+  const u32 dflt = 1u << radix_log((int)(c->log_n / 2));
+  t.logr = (sc->radix == 0 || sc->radix == dflt) ? 0 : (sc->radix == 16 ? 4 : 99);
   if (!tiles_supported(c->log_n, t))
-    return fail(HE_EUNSUPPORTED, "he_batch_set_sched: tiles %u/%u not available at N = 2^%u", t.epw_c, t.epw_b,
-                c->log_n);
+    return fail(HE_EUNSUPPORTED, "he_batch_set_sched: tiles %u/%u, radix %u not available at N = 2^%u", t.epw_c,
+                t.epw_b, sc->radix, c->log_n);
   if (t.fused_ip && c->dnum > (u32)IP_WAVES)
     return fail(HE_EUNSUPPORTED, "he_batch_set_sched: the fused inner product takes at most %d digits", IP_WAVES);
   if (sc->chunks < 1 || sc->chunks > 8 || sc->chunks > bt->n)
@@ -1280,6 +1286,7 @@ he_status he_batch_set_sched(he_batch* bt, const he_batch_sched* sc, he_stream s
     HIP_TRY(hipEventCreateWithFlags(&bt->ev_join, hipEventDisableTiming));
   }
   batch_drop_graph(bt);
+  ++bt->stamp;  // graphs of batch groups holding this batch are recaptured
   return HE_OK;
 }
 
@@ -1289,6 +1296,7 @@ he_status he_batch_get_sched(const he_batch* bt, he_batch_sched* sc) {
   sc->blocks_tile = bt->tiles.epw_b;
   sc->chunks = bt->chunks;
   sc->ip_fused = bt->tiles.fused_ip;
+  sc->radix = bt->tiles.logr ? 1u << bt->tiles.logr : 1u << radix_log((int)(bt->ctx->log_n / 2));
   return HE_OK;
 }
 
@@ -1365,6 +1373,133 @@ he_status he_mul_batch(he_ctx* c, he_batch* bt, const uint64_t* evk, int use_gra
   return HE_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch groups
+// Batches of different contexts (ring sizes) run as one unit: batch 0 on
+// the caller's stream, batch i > 0 on a stream of the group, forked from
+// and joined back to the caller's stream by events, so the rings' stage
+// kernels overlap on the device; captured once into a single HIP graph.
+struct he_batch_group {
+  std::vector<he_batch*> batches;
+  std::vector<hipStream_t> side;     // [n - 1]
+  std::vector<hipEvent_t> ev_join;   // [n - 1]
+  hipEvent_t ev_fork = nullptr;
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const u64*> graph_evks;
+};
+
+static void group_drop_graph(he_batch_group* g) {
+  if (g->exec) { (void)hipGraphExecDestroy(g->exec); g->exec = nullptr; }
+  if (g->graph) { (void)hipGraphDestroy(g->graph); g->graph = nullptr; }
+  g->graph_evks.clear();
+}
+
+static hipError_t group_launch_all(he_batch_group* g, const uint64_t* const* evks, hipStream_t st) {
+  const u32 n = (u32)g->batches.size();
+  hipError_t e = hipSuccess;
+  if (n > 1) {
+    e = hipEventRecord(g->ev_fork, st);
+    for (u32 i = 1; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(g->side[i - 1], g->ev_fork, 0);
+  }
+  for (u32 i = 0; i < n && e == hipSuccess; ++i) {
+    he_batch* bt = g->batches[i];
+    e = batch_launch_all(bt->ctx, bt, evks[i], i ? g->side[i - 1] : st);
+  }
+  for (u32 i = 1; i < n && e == hipSuccess; ++i) {
+    e = hipEventRecord(g->ev_join[i - 1], g->side[i - 1]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, g->ev_join[i - 1], 0);
+  }
+  return e;
+}
+
+extern "C" {
+
+he_status he_batch_group_create(he_batch* const* batches, uint32_t n, he_batch_group** out) {
+  if (!out || !batches || n == 0 || n > 64) return fail(HE_EINVAL, "he_batch_group_create: bad arguments");
+  *out = nullptr;
+  for (u32 i = 0; i < n; ++i) {
+    if (!batches[i]) return fail(HE_EINVAL, "he_batch_group_create: batch %u is null", i);
+    if (batches[i]->ctx->device != batches[0]->ctx->device)
+      return fail(HE_EINVAL, "he_batch_group_create: batches on different devices");
+    for (u32 j = 0; j < i; ++j)
+      if (batches[j] == batches[i]) return fail(HE_EINVAL, "he_batch_group_create: batch %u listed twice", i);
+  }
+  for (u32 i = 0; i < n; ++i)
+    if (batches[i]->chunks > 1)
+      return fail(HE_EUNSUPPORTED, "he_batch_group_create: batch %u runs in %u chunks; a group takes one-chunk batches",
+                  i, batches[i]->chunks);
+  std::unique_ptr<he_batch_group, void (*)(he_batch_group*)> g(new he_batch_group, he_batch_group_destroy);
+  g->batches.assign(batches, batches + n);
+  for (he_batch* bt : g->batches) bt->group_stamp = bt->stamp;
+  g->device = batches[0]->ctx->device;
+  HIP_TRY(hipSetDevice(g->device));
+  HIP_TRY(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+  for (u32 i = 1; i < n; ++i) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    g->side.push_back(s);
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    g->ev_join.push_back(e);
+  }
+  *out = g.release();
+  return HE_OK;
+}
+
+he_status he_mul_batch_group(he_batch_group* g, const uint64_t* const* d_evks, int use_graph, he_stream stream) {
+  if (!g || !d_evks) return fail(HE_EINVAL, "he_mul_batch_group: null pointer");
+  const u32 n = (u32)g->batches.size();
+  for (u32 i = 0; i < n; ++i) {
+    if (!d_evks[i]) return fail(HE_EINVAL, "he_mul_batch_group: evk %u is null", i);
+    if (g->batches[i]->group_stamp != g->batches[i]->stamp)
+      return fail(HE_EUNSUPPORTED, "he_mul_batch_group: batch %u changed its schedule after the group was made", i);
+  }
+  HIP_TRY(hipSetDevice(g->device));
+  hipStream_t st = (hipStream_t)stream;
+  bool timing = false;
+  for (he_batch* bt : g->batches) timing = timing || bt->ctx->timing;
+  if (!use_graph || timing) {
+    const hipError_t e = group_launch_all(g, d_evks, st);
+    if (e != hipSuccess) return fail(HE_EDEVICE, "he_mul_batch_group: launch failed: %s", hipGetErrorString(e));
+    return HE_OK;
+  }
+  const std::vector<const u64*> evks(d_evks, d_evks + n);
+  if (!g->exec || g->graph_evks != evks) {
+    group_drop_graph(g);
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      const hipError_t le = group_launch_all(g, d_evks, cap);
+      e = hipStreamEndCapture(cap, &g->graph);
+      if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+      group_drop_graph(g);
+      return fail(HE_EDEVICE, "he_mul_batch_group: graph capture failed: %s", hipGetErrorString(e));
+    }
+    g->graph_evks = evks;
+  }
+  HIP_TRY(hipGraphLaunch(g->exec, st));
+  return HE_OK;
+}
+
+void he_batch_group_destroy(he_batch_group* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  for (hipStream_t s : g->side) (void)hipStreamSynchronize(s);
+  group_drop_graph(g);
+  for (hipStream_t s : g->side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : g->ev_join) (void)hipEventDestroy(e);
+  if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  delete g;
+}
+
 // Times `reps` graph replays of the batch under each candidate schedule and
 // keeps the fastest: first the tiles (one chunk), then the chunk count with
 // the best tiles.
@@ -1395,11 +1530,12 @@ he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32
   };
   std::vector<he_batch_sched> tiles;
   const TileCfg d = default_tiles(c->log_n);
-  tiles.push_back({d.epw_c, d.epw_b, 1, 0});
-  if (c->log_n == 16)
-    for (uint32_t ec : {4096u, 2048u})
-      for (uint32_t eb : {2048u, 1024u})
-        if (!(ec == d.epw_c && eb == d.epw_b)) tiles.push_back({ec, eb, 1, 0});
+  tiles.push_back({d.epw_c, d.epw_b, 1, 0, 0});
+  if (c->log_n == 16)  // every tile pair at the default radix (8) and at radix 16
+    for (uint32_t rdx : {0u, 16u})
+      for (uint32_t ec : {4096u, 2048u})
+        for (uint32_t eb : {2048u, 1024u})
+          if (!(ec == d.epw_c && eb == d.epw_b && rdx == 0)) tiles.push_back({ec, eb, 1, 0, rdx});
   he_batch_sched b = tiles[0];
   double bms = 1e30;
   he_status r = HE_OK;
@@ -1410,7 +1546,7 @@ he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32
   }
   if (r == HE_OK && c->dnum <= (u32)IP_WAVES) {  // the fused mod-up blocks + inner product pass
     he_batch_sched sc = b;
-    sc.ip_fused = 1;
+    sc.ip_fused = 1;  // (at its own radix; the other passes keep the chosen one)
     double ms = 0;
     if ((r = run(sc, ms)) == HE_OK && ms < bms) { bms = ms; b = sc; }
   }
@@ -1427,7 +1563,7 @@ he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32
   if (r != HE_OK) return r;
   r = he_batch_set_sched(bt, &b, stream);
   if (r != HE_OK) return r;
-  if (best) *best = b;
+  if (best) (void)he_batch_get_sched(bt, best);  // as get_sched reports it (default radix by value)
   if (best_ms) *best_ms = bms;
   return HE_OK;
 }

@@ -72,6 +72,7 @@ void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) 
 void launch_u64_small(u32 log_n, int stage, const Common& c, const Batch& b, hipStream_t st);  // N = 2^12..2^15
 void launch_u64_n16(int stage, const Common& c, const Batch& b, hipStream_t st, TileCfg t);
 void launch_u64_n16_c4096(int stage, const Common& c, const Batch& b, hipStream_t st, TileCfg t);
+void launch_u64_n16_r16(int stage, const Common& c, const Batch& b, hipStream_t st, TileCfg t);
 void launch_u64_n17(int stage, const Common& c, const Batch& b, hipStream_t st);
 // 32-bit words
 void launch_w32_small(u32 log_n, int stage, const Common& c, const Batch& b, hipStream_t st);  // N = 2^12..2^15

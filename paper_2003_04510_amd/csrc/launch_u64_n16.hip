@@ -5,6 +5,10 @@
 namespace he {
 
 void launch_u64_n16(int stage, const Common& c, const Batch& b, hipStream_t st, TileCfg t) {
+  if (t.logr == 4) {
+    launch_u64_n16_r16(stage, c, b, st, t);
+    return;
+  }
   if (t.epw_c != 2048) {
     launch_u64_n16_c4096(stage, c, b, st, t);
     return;

@@ -413,20 +413,28 @@ struct Radix {
   static constexpr int LOGR = radix_log(LOGS);
 };
 
+// The tile parameter T of a pass kernel: elements per workgroup in its low
+// 24 bits and, from bit 24 up, log2 of the register radix (0 there: the
+// default radix_log of the sub-transform size), so a pass can be
+// instantiated at another radix (a schedule choice of batches).
+__host__ __device__ constexpr int tile_elems(int t) { return t & 0xFFFFFF; }
+__host__ __device__ constexpr int tile_logr(int t, int logs) { return (t >> 24) ? (t >> 24) : radix_log(logs); }
+__host__ __device__ constexpr int tile_code(int elems, int logr) { return elems | (logr << 24); }
+
 // Workgroup shape of a pass: EPW elements (8*EPW bytes) per workgroup.
 // `cols` passes put the sub index fastest (adjacent lanes read adjacent
 // columns); `blocks` passes put the in-sub thread fastest.
 constexpr int NTT_EPW = NTT_EPW_DEFAULT;
 template <int LOGS, int EPW = NTT_EPW>
 struct PassGeo {
-  static constexpr int LOGR = Radix<LOGS>::LOGR;
+  static constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
-  static constexpr int SUBS = EPW / Gm::S;
+  static constexpr int SUBS = tile_elems(EPW) / Gm::S;
   static constexpr int THREADS = SUBS * Gm::T;
 };
 // threads of a pass workgroup (a plain function so it fits a macro argument)
 constexpr int pass_threads(int logs, int epw) {
-  return (epw >> logs) * ((1 << logs) >> radix_log(logs));
+  return (tile_elems(epw) >> logs) * ((1 << logs) >> tile_logr(epw, logs));
 }
 template <int LOGS, bool COLS, int EPW = NTT_EPW>
 struct PassLayout {
@@ -456,7 +464,7 @@ struct NttArgs {
 
 template <bool FWD, int LOGS, int EPW = NTT_EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols(NttArgs a) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, true, EPW>;
   constexpr int FIRST = FWD ? 0 : Gm::NR - 1;
@@ -498,7 +506,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_cols(NttArgs a)
 // access is coalesced.
 template <bool FWD, int LOGS, int EPW = NTT_EPW>
 __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_blocks(NttArgs a) {
-  constexpr int LOGR = Radix<LOGS>::LOGR;
+  constexpr int LOGR = tile_logr(EPW, LOGS);
   using Gm = Geo<LOGS, LOGR>;
   using PL = PassLayout<LOGS, false, EPW>;
   constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
