@@ -29,9 +29,10 @@ c.bx = c.ax * sk + t + e fixes decryption as t = bx - ax * sk and the key as
 evk.bx = evk.ax * sk + e + Q sk^2 (mod Q^2).
 
 Pins: tests/test_oracle_bigint_pins.py (schoolbook products over Z, X^j
-shifts, the Karatsuba identity, exact rounding of the shifts, and the
+shifts, the Karatsuba identity, exact rounding of the shifts, the
 decryption identity decrypt(c1 * c2) ~ decrypt(c1) * decrypt(c2) within the
-key-switching error bound).
+key-switching error bound, and he_mul_at -- coefficient by coefficient from
+direct sums -- against he_mul's Kronecker products at small N).
 """
 from __future__ import annotations
 
@@ -106,6 +107,60 @@ def rescale(ct, logq: int, logp: int):
     half = 1 << (logp - 1)
     m = mask(logq - logp)
     return tuple([((c + half) >> logp) & m for c in poly] for poly in ct)
+
+
+# ---------------------------------------------------------------- chosen output coefficients
+def negacyclic_coeff(a, b_terms, k: int, n: int) -> int:
+    """Coefficient k of a * b in Z[X]/(X^N + 1), N = n, with b given as its
+    nonzero terms {j: b_j}: sum_j a_{k-j} b_j for j <= k, and -a_{k-j+N} b_j
+    for j > k (X^N = -1).  O(number of terms)."""
+    c = 0
+    for j, bj in b_terms.items():
+        if j <= k:
+            c += a[k - j] * bj
+        else:
+            c -= a[k - j + n] * bj
+    return c
+
+
+def _terms(a) -> dict:
+    return {j: int(x) for j, x in enumerate(a) if x}
+
+
+def he_mul_at(ct1, ct2, evk, logq: int, logQ: int, idx, logp: int = 0):
+    """Coefficients idx of HE Mul (as he_mul, then rescale by 2^logp when
+    logp > 0), each computed on its own from the definitions of region 1
+    and region 2 by direct negacyclic sums: the products with ct2's
+    polynomials cost their nonzero terms per coefficient (cheap when ct2 is
+    sparse); the key switch needs every coefficient of ax1 ax2 and one sum
+    of N products per output coefficient.  Returns (bx3, ax3) at idx."""
+    n = len(ct1[0])
+    qm = mask(logq)
+    bx1, ax1 = ct1
+    bx2, ax2 = ct2
+    s1 = [(int(x) + int(y)) & qm for x, y in zip(ax1, bx1)]
+    t_s2 = _terms([(int(x) + int(y)) & qm for x, y in zip(ax2, bx2)])
+    t_ax2, t_bx2 = _terms(ax2), _terms(bx2)
+    ax1i = [int(x) for x in ax1]
+    bx1i = [int(x) for x in bx1]
+    axax = [negacyclic_coeff(ax1i, t_ax2, k, n) & qm for k in range(n)]
+    qq, half = mask(logq + logQ), 1 << (logQ - 1)
+    ev = [[int(x) for x in e] for e in evk]
+    bx3, ax3 = [], []
+    for k in idx:
+        axbx = negacyclic_coeff(s1, t_s2, k, n) & qm
+        bxbx = negacyclic_coeff(bx1i, t_bx2, k, n) & qm
+        ks = []
+        for e in ev:
+            c = sum(axax[i] * e[k - i] for i in range(k + 1)) - sum(axax[i] * e[k - i + n] for i in range(k + 1, n))
+            ks.append((((c & qq) + half) >> logQ) & qm)
+        bx3.append((ks[0] + bxbx) & qm)
+        ax3.append((ks[1] + axbx - axax[k] - bxbx) & qm)
+    if logp > 0:
+        hp, mo = 1 << (logp - 1), mask(logq - logp)
+        bx3 = [((c + hp) >> logp) & mo for c in bx3]
+        ax3 = [((c + hp) >> logp) & mo for c in ax3]
+    return bx3, ax3
 
 
 # ---------------------------------------------------------------- keys and encryption

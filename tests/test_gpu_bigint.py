@@ -167,3 +167,43 @@ def test_big_errors():
         lib.he_mul(300, c, c, ev, ws=lib.empty(8))
     with pytest.raises(P.HeError):
         P.BigContext(12, 1300)                # beyond the supported log Q
+
+
+@pytest.mark.parametrize("logq", [1200, 1111])
+def test_big_mul_full_size_chosen_coefficients_bit_exact(logq):
+    """The paper's parameters (N = 2^16, log Q = 1200; Table III, Table VII):
+    ct1 and the evaluation key uniform and dense, ct2 with four nonzero
+    coefficients per polynomial, so the oracle computes chosen output
+    coefficients exactly (direct negacyclic sums: O(nnz) for the region-1
+    products, one sum of N products per key-switched coefficient).  The
+    GPU's output words at those coefficients -- ends, wrap positions next to
+    ct2's support, random ones -- equal the oracle's bit for bit, with and
+    without rescale (log p = 30); log q = 1111 is not a multiple of 32."""
+    log_n, logQ = 16, 1200
+    n = 1 << log_n
+    lib = big_ctx(log_n, logQ)
+    W = lib.W
+    g = synth.rng(88 + logq)
+    c1 = synth.big_ciphertext(90 + logq, logq, n, W)
+    c2 = np.zeros((2, W, n), dtype=np.uint64)
+    supp = {}
+    for u in range(2):
+        idx = sorted(int(x) for x in g.choice(n, size=4, replace=False))
+        vals = synth.uniform_bigint(91 + logq + u, logq, 4, 0, W)
+        c2[u][:, idx] = vals
+        supp[u] = idx
+    ev = synth.big_evk(92 + logq, logQ, n)
+    chosen = sorted({0, 1, 2, n - 2, n - 1} | {(j + d) % n for u in supp for j in supp[u] for d in (-1, 0, 1)}
+                    | {int(x) for x in g.integers(0, n, size=6)})
+    log("chosen coefficients", len(chosen))
+    t1, t2, te = _ints(c1), _ints(c2), _ints(ev)
+    d1, d2 = lib.to_device(c1), lib.to_device(c2)
+    evk_ntt = lib.evk_prepare(lib.to_device(ev))
+    exact = hb.he_mul_at(t1, t2, te, logq, logQ, chosen)
+    for logp in (0, 30):
+        want = hb.rescale(exact, logq, logp) if logp else exact
+        got = lib.to_host(lib.he_mul(logq, d1, d2, evk_ntt, logp=logp))
+        for u in range(2):
+            want_w = hb.ints_to_words(want[u], W)
+            assert np.array_equal(got[u][:, chosen], want_w), (logq, logp, u)
+        log("full size chosen coefficients bit-exact", logq, logp)

@@ -150,3 +150,32 @@ def test_rescale_decrypts_to_quotient():
     got = hb.decrypt(hb.rescale(ct, logq, logp), s, logq - logp)
     for g, x in zip(got, t):
         assert abs(g - x / (1 << logp)) <= (1 + h) / 2 + 1
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_he_mul_at_equals_full_product(sparse):
+    """The chosen-coefficient HE Mul (direct negacyclic sums per
+    coefficient) equals the full Kronecker-product HE Mul at every index,
+    with and without rescale, dense and sparse second operands, including
+    maximal coefficients."""
+    rng = random.Random(5 + sparse)
+    n, logq, logQ, logp = 16, 200, 220, 30
+    qm = hb.mask(logq)
+    ct1 = ([rng.getrandbits(logq) for _ in range(n)], [rng.getrandbits(logq) for _ in range(n)])
+    if sparse:
+        ax2 = [0] * n
+        bx2 = [0] * n
+        for j in rng.sample(range(n), 3):
+            ax2[j] = rng.getrandbits(logq)
+        for j in rng.sample(range(n), 2):
+            bx2[j] = qm  # maximal
+        ct2 = (bx2, ax2)
+    else:
+        ct2 = ([rng.getrandbits(logq) for _ in range(n)], [qm] * n)
+    evk = ([rng.getrandbits(2 * logQ) for _ in range(n)], [rng.getrandbits(2 * logQ) for _ in range(n)])
+    full = hb.he_mul(ct1, ct2, evk, logq, logQ)
+    idx = list(range(n))
+    assert hb.he_mul_at(ct1, ct2, evk, logq, logQ, idx) == tuple(full)
+    resc = hb.rescale(full, logq, logp)
+    assert hb.he_mul_at(ct1, ct2, evk, logq, logQ, [0, 7, n - 1], logp) == tuple(
+        [p[k] for k in (0, 7, n - 1)] for p in resc)
