@@ -92,6 +92,8 @@ struct PlanDev {
   const ConvTarget* md_tg;    // [level]
   const u32* md_c;
   const u32* dt_mod;   // modulus of each mod-up limb [dt_limbs]
+  const u32* dtg_limb; // mod-up limbs ordered by modulus [dt_limbs] ...
+  const u32* dtg_first;// ... and where each modulus' run starts [dtg_count + 1]
   const u32* emod;     // modulus of extended-basis limb e [level + K]
   const u32* y_mod;    // INTT list d2 (+ d0, d1 of limb level-1) [level + 2]
   const u64* y_scale;  // Shoup pairs: N^-1 [(Qt_j/q_i)^-1]_{q_i}, N^-1
@@ -100,7 +102,7 @@ struct PlanDev {
   const u64* qlinv;    // Shoup pairs [q_{level-1}^-1]_{q_i}, i < level-1
   const u64* qlmod;    // q_{level-1} mod q_i
   u64 pinv_l, pinv_ls; // [P^-1]_{q_{level-1}} and its Shoup companion
-  u32 level, beta, dt_limbs, pad;
+  u32 level, beta, dt_limbs, dtg_count;
   u32 dt_first[MAX_DIGITS], lo[MAX_DIGITS], cnt[MAX_DIGITS];
 };
 
@@ -509,8 +511,24 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
   const ListView v = list_view<ST>(c, pd);
   const int n1 = c.log_n - LOGS;
   const u32 tpl = (1u << n1) / PL::SUBS;
-  const u32 pos = uniform(local % tpl), rest = local / tpl;
-  const u32 z = uniform(rest % v.np), limb = uniform(rest / v.np);  // both polys of a limb adjacent
+  u32 pos, z, limb;
+  if constexpr (ST == ST_DT_NBLOCKS) {
+    // the mod-up limbs of one modulus (one per digit that does not contain
+    // it) share their twiddles: items run tile by tile over the limbs
+    // ordered by modulus, so a modulus' limbs at one tile are adjacent and
+    // the later ones find the twiddles in L2
+    const PlanDev* P = pd.plan;
+    const u32 nl = ldc(&P->dt_limbs);
+    pos = uniform(local / nl);
+    limb = uniform(ldc(ldc(&P->dtg_limb) + local % nl));
+    z = 0;
+  } else {
+    // the two polynomials of a tile adjacent: they share its twiddles
+    z = uniform(local % v.np);
+    const u32 rest = local / v.np;
+    pos = uniform(rest % tpl);
+    limb = uniform(rest / tpl);
+  }
   const u32 mi = ldc(v.limb_mod + limb);
   const ModInfo mo = ldc(c.mods + mi);
   const int sub = PL::sub(), tt = PL::tt();

@@ -104,7 +104,8 @@ struct LevelPlan {
   const ConvJobDev* mu_jobs = nullptr;  // [beta]
   const ConvJobDev* md_jobs = nullptr;  // [1]
   u32 lo[MAX_DIGITS] = {}, cnt[MAX_DIGITS] = {}, dt_first[MAX_DIGITS] = {};
-  size_t o_modup_scale = 0, o_dt_mod = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0;
+  size_t o_modup_scale = 0, o_dt_mod = 0, o_emod = 0, o_qlinv = 0, o_qlmod = 0, o_dtg_limb = 0, o_dtg_first = 0;
+  u32 dtg_count = 0;
   // resolved device pointers
   const u64* modup_scale = nullptr;
   const u32* dt_mod = nullptr;
@@ -563,6 +564,18 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
       P.o_y_mod = B.add(ymod); P.o_y_scale = B.add(ysc); P.o_s_mod = B.add(smod); P.o_s_scale = B.add(ssc);
     }
     P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_emod = B.add(emod);
+    {
+      // mod-up limbs grouped by modulus (stable), for the blocks pass's item order
+      std::vector<u32> order(dt_mod.size()), first;
+      for (u32 k = 0; k < order.size(); ++k) order[k] = k;
+      std::stable_sort(order.begin(), order.end(), [&](u32 a, u32 b) { return dt_mod[a] < dt_mod[b]; });
+      for (u32 k = 0; k < order.size(); ++k)
+        if (k == 0 || dt_mod[order[k]] != dt_mod[order[k - 1]]) first.push_back(k);
+      first.push_back((u32)order.size());
+      P.dtg_count = (u32)first.size() - 1;
+      P.o_dtg_limb = B.add(order);
+      P.o_dtg_first = B.add(first);
+    }
     P.o_qlinv = B.add(qlinv); P.o_qlmod = B.add(qlmod);
     {
       PlanDev placeholder{};
@@ -606,6 +619,8 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
     pd.md_jobs = (const ConvJobDev*)(d + P.o_md_jobs); pd.md_tg = (const ConvTarget*)(d + P.o_md_tg);
     pd.md_c = (const u32*)(d + P.o_md_c);
     pd.dt_mod = (const u32*)(d + P.o_dt_mod); pd.emod = (const u32*)(d + P.o_emod);
+    pd.dtg_limb = (const u32*)(d + P.o_dtg_limb); pd.dtg_first = (const u32*)(d + P.o_dtg_first);
+    pd.dtg_count = P.dtg_count;
     pd.y_mod = (const u32*)(d + P.o_y_mod); pd.y_scale = (const u64*)(d + P.o_y_scale);
     pd.s_mod = (const u32*)(d + P.o_s_mod); pd.s_scale = (const u64*)(d + P.o_s_scale);
     pd.qlinv = (const u64*)(d + P.o_qlinv); pd.qlmod = (const u64*)(d + P.o_qlmod);
