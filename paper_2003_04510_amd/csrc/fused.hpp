@@ -169,8 +169,9 @@ enum Stage : int {
   ST_MU_CONV,      // mod-up conversion
   ST_DT_NCOLS,     // NTT cols of the mod-up limbs
   ST_DT_NBLOCKS,   // NTT blocks of the mod-up limbs                      (separate path)
-  ST_IP,           // inner product with evk                              (separate path)
-  ST_KS_IBLOCKS,   // INTT blocks of the special limbs (+ limb level-1)   (separate path)
+  ST_IP,           // inner product with evk, + INTT blocks of the special limbs (+ limb
+                   // level-1)                                             (separate path)
+  ST_KS_IBLOCKS,   // no launch: the pass runs in ST_IP or ST_BLOCKS_IP
   ST_BLOCKS_IP,    // the three above in one pass                         (fused path)
   ST_KS_ICOLS,     // INTT cols of the special limbs (+ limb level-1)
   ST_MD_CONV,      // mod-down conversion
@@ -215,7 +216,7 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
     case ST_DT_NCOLS: return dt_limbs * tc;
     case ST_DT_NBLOCKS: return tc_cfg.fused_ip ? 0 : dt_limbs * tb;
     case ST_IP: return tc_cfg.fused_ip ? 0 : (level + K) * chunks_i;
-    case ST_KS_IBLOCKS: return tc_cfg.fused_ip ? 0 : 2 * (K + ex) * tb;
+    case ST_KS_IBLOCKS: return 0;  // in k_ip (separate path) or k_blocks_ip (fused path)
     case ST_BLOCKS_IP: return tc_cfg.fused_ip ? (level + K + ex) * ipw_tiles(log_n) : 0;
     case ST_KS_ICOLS: return 2 * (K + ex) * tc;
     case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_c;
@@ -733,19 +734,34 @@ inline int conv_bucket(u32 ns) {
 // ---------------------------------------------------------------- inner product
 // ks_u[e] = sum_j dt_j[e] * evk_j.u[e] for every limb e of the extended basis;
 // dt_j[e] = d2[e] when q_e is in digit j, else the NTT-form mod-up limb.
-// When rescaling, the NTT-form ks_u[level-1] is also copied to limb
-// level+K (it is inverse-transformed with the special limbs).
-// Items (e, coefficient chunk).  KEY_NT: the key is read by one HE Mul
+// The special limbs leave in coefficient-bound form: an item's chunk holds
+// whole sub-transforms of the inverse NTT blocks pass (2^LOGS points), so
+// their sums go through that pass here, by way of LDS, and the special
+// limbs never make the round trip through HBM in NTT form.  When
+// rescaling, ks_u[level-1] is written in NTT form and, inverse-transformed
+// the same way, into slot level+K.  Both leave the inverse cols pass.
+// Items (coefficient chunk, e), e fastest, so every XCD takes its share of
+// the special limbs' transforms.  KEY_NT: the key is read by one HE Mul
 // (a single pair), so its loads bypass the caches.
-template <class W, bool KEY_NT>
+template <class W, bool KEY_NT, int LOGS>
 __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
+  // radix-4 rounds (radix 8 from 512 points): the transforms of an item
+  // then occupy its four waves, and the kernel stays at 64 VGPRs, 8 waves
+  // per SIMD (the default radix 8 takes 77: 6 waves per SIMD)
+  constexpr int LOGR = LOGS >= 9 ? 3 : 2;
+  using Gm = Geo<LOGS, LOGR>;
+  constexpr int EI = IP_THREADS * IP_CPT;  // coefficients per item
+  constexpr int SUBS = EI / Gm::S;         // sub-transforms per polynomial and item
+  static_assert(SUBS >= 1 && EI % Gm::S == 0, "an item holds whole blocks-pass sub-transforms");
+  static_assert(64 % Gm::T == 0, "a sub-transform's threads lie in one wavefront");
+  __shared__ u64 lds[2 * SUBS * Gm::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
   const PairDesc pd = resolve(b, uniform(w), local);
   const PlanDev* P = pd.plan;
-  const u32 nch = (1u << c.log_n) / (IP_THREADS * IP_CPT);
-  const u32 chunk = uniform(local % nch), e = uniform(local / nch);
+  const u32 nel = pd.level + c.K;
+  const u32 chunk = uniform(local / nel), e = uniform(local % nel);
   const u64 n0 = ((u64)chunk * IP_THREADS + threadIdx.x) * IP_CPT;
   const u32 mi = ldc(ldc(&P->emod) + e);
   const ModInfo m = ldc(c.mods + mi);
@@ -799,21 +815,51 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
     }
   }
   const u64 kz = (u64)(pd.level + c.K + 1) << c.log_n;
-  const auto ob = gw<W>(pd.ks) + ((u64)e << c.log_n) + n0;
   const bool last = pd.rs && e == pd.level - 1;
-  const auto xb = gw<W>(pd.ks) + ((u64)(pd.level + c.K) << c.log_n) + n0;
+  const bool coef = e >= pd.level || last;  // goes through the inverse blocks pass
+  u64 vb[IP_CPT], va[IP_CPT];
 #pragma unroll
   for (int k = 0; k < IP_CPT; ++k) {
     // beta <= 4: the sums stay below 4 q^2 < 2^(2b+2), Barrett's range
-    const u64 vb = beta <= 4 ? barrett(accb[k], m) : reduce128(accb[k], m);
-    const u64 va = beta <= 4 ? barrett(acca[k], m) : reduce128(acca[k], m);
-    ob[k] = vb;
-    ob[kz + k] = va;
-    if (last) {
-      xb[k] = vb;
-      xb[kz + k] = va;
+    vb[k] = beta <= 4 ? barrett(accb[k], m) : reduce128(accb[k], m);
+    va[k] = beta <= 4 ? barrett(acca[k], m) : reduce128(acca[k], m);
+  }
+  if (e < pd.level) {
+    const auto ob = gw<W>(pd.ks) + ((u64)e << c.log_n) + n0;
+#pragma unroll
+    for (int k = 0; k < IP_CPT; ++k) {
+      ob[k] = vb[k];
+      ob[kz + k] = va[k];
     }
   }
+  if (!coef) return;
+  // inverse blocks pass: tile z * SUBS + s holds sub-transform s of
+  // polynomial z (b, a); the transform's threads are whole sub-transforms
+  // of one wavefront each, the rest of the workgroup is done
+  with_arith<W>(m, [&](auto ar) {
+    using A = decltype(ar);
+    const typename A::Mod M = A::mod(m.q, m.qinv);
+    typename A::V* const tl = reinterpret_cast<typename A::V*>(lds);
+#pragma unroll
+    for (int k = 0; k < IP_CPT; ++k) {
+      const int idx = threadIdx.x * IP_CPT + k;
+      const int q = (idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1));
+      tl[q] = A::in(vb[k], M);
+      tl[SUBS * Gm::SUB + q] = A::in(va[k], M);
+    }
+    lds_barrier();
+    if (threadIdx.x >= 2 * SUBS * Gm::T) return;
+    const int g = threadIdx.x / Gm::T, tt = threadIdx.x % Gm::T;
+    const int z = g / SUBS, sub = g % SUBS;
+    typename A::V x[Gm::R];
+    lds_get<LOGS, LOGR, Gm::NR - 1>(tl + g * Gm::SUB, x, tt);
+    const u64 blk = (u64)chunk * SUBS + sub;  // the sub-transform's block in the limb
+    const u64 slot = last ? pd.level + c.K : e;
+    const auto out = gw<W>(pd.ks) + (z ? kz : 0) + (slot << c.log_n) + (blk << LOGS);
+    sub_transform_regs<A, false, LOGS, LOGR, false, true>(
+        x, tl + g * Gm::SUB, tt, c.itw + ((u64)mi << c.log_n), (1ull << (c.log_n - LOGS)) + blk, M,
+        [&](int e2, typename A::V v) { out[e2] = A::template out<false>(v, M); });
+  });
 }
 
 // ---------------------------------------------------------------- mod-up NTT blocks + inner product

@@ -852,8 +852,11 @@ void stage_work(const he_ctx* c, int st, u32 level, bool rs, double& ops, double
     case ST_MU_CONV: ops = macs * N; bytes = (l + P.dt_limbs) * N * 8; break;
     case ST_DT_NCOLS: ops = P.dt_limbs * hN * n1; bytes = 2.0 * P.dt_limbs * N * 8; break;
     case ST_DT_NBLOCKS: ops = P.dt_limbs * hN * n2; bytes = 2.0 * P.dt_limbs * N * 8; break;
-    case ST_IP: ops = 2.0 * P.beta * ne * N; bytes = (3.0 * P.beta + 2) * ne * N * 8 + 2 * ex * N * 8; break;
-    case ST_KS_IBLOCKS: ops = 2 * (K + ex) * hN * n2; bytes = 4 * (K + ex) * N * 8; break;
+    case ST_IP:  // + the inverse blocks pass of the special limbs (and of limb level-1 when rescaling)
+      ops = 2.0 * P.beta * ne * N + 2 * (K + ex) * hN * n2;
+      bytes = (3.0 * P.beta + 2) * ne * N * 8 + 2 * ex * N * 8;
+      break;
+    case ST_KS_IBLOCKS: ops = bytes = 0; break;
     case ST_BLOCKS_IP:  // mod-up limbs (cols-pass form) and d2 in, evk in, ks out
       ops = P.dt_limbs * hN * n2 + 2.0 * P.beta * ne * N + 2 * (K + ex) * hN * n2;
       bytes = (P.dt_limbs + l + 2.0 * P.beta * ne + 2 * (ne + ex)) * N * 8;

@@ -52,10 +52,9 @@ void launch_stage_n(int stage, const Common& c, const Batch& b, hipStream_t st) 
     case ST_DT_NCOLS: launch_lcols<W, true, N1, EC, ST_DT_NCOLS>(c, b, st); break;
     case ST_DT_NBLOCKS: launch_lblocks<W, true, N2, EB, ST_DT_NBLOCKS>(c, b, st); break;
     case ST_IP:
-      if (b.pairs) hipLaunchKernelGGL((k_ip<W, false>), g, dim3(IP_THREADS), 0, st, c, b);
-      else hipLaunchKernelGGL((k_ip<W, true>), g, dim3(IP_THREADS), 0, st, c, b);
+      if (b.pairs) hipLaunchKernelGGL((k_ip<W, false, N2>), g, dim3(IP_THREADS), 0, st, c, b);
+      else hipLaunchKernelGGL((k_ip<W, true, N2>), g, dim3(IP_THREADS), 0, st, c, b);
       break;
-    case ST_KS_IBLOCKS: launch_lblocks<W, false, N2, EB, ST_KS_IBLOCKS>(c, b, st); break;
     case ST_BLOCKS_IP: hipLaunchKernelGGL((k_blocks_ip<W, N2>), g, dim3(64 * IP_WAVES), 0, st, c, b); break;
     case ST_KS_ICOLS: launch_lcols<W, false, N1, EC, ST_KS_ICOLS>(c, b, st); break;
     case ST_MD_CONV: launch_conv<W, true>(conv_bucket(c.K), c, b, st); break;
