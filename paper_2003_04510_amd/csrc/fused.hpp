@@ -232,18 +232,9 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_lim
 // ---------------------------------------------------------------- base conversion helpers
 // sll + (slh + shl) 2^30 + shh 2^60 as a 128-bit value.
 __device__ __forceinline__ U128 conv_sum(u64 sll, u64 slh, u64 shl, u64 shh) {
-  const u64 mid = slh + shl;
-  const u64 cm = mid < slh ? 1 : 0;
-  U128 x;
-  x.lo = sll;
-  x.hi = 0;
-  const u64 alo = shh << 60;
-  x.lo += alo;
-  x.hi += (shh >> 4) + (x.lo < alo ? 1 : 0);
-  const u64 blo = mid << 30;
-  x.lo += blo;
-  x.hi += ((mid >> 34) | (cm << 30)) + (x.lo < blo ? 1 : 0);
-  return x;
+  typedef unsigned __int128 u128;  // add-with-carry chains instead of compares
+  const u128 x = (u128)sll + ((u128)shh << 60) + (((u128)slh + shl) << 30);
+  return U128{(u64)x, (u64)(x >> 64)};
 }
 
 // ---------------------------------------------------------------- tensor + INTT blocks
@@ -661,8 +652,13 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
 #pragma unroll
       for (int k = 0; k < CONV_CPT; ++k) add_to(tot[k], conv_sum(sll[k], slh[k], shl[k], shh[k]));
     }
+    if (m.q >> 32) {  // tot < 2^125
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) v[k] = reduce128(tot[k], m);
+      for (int k = 0; k < CONV_CPT; ++k) v[k] = reduce125(tot[k], m);
+    } else {
+#pragma unroll
+      for (int k = 0; k < CONV_CPT; ++k) v[k] = reduce128(tot[k], m);
+    }
   };
   // The rescale's dropped limb in coefficient form, by linearity: with the
   // mod-down constants carrying P^-1 (z' = z P^-1),
@@ -699,7 +695,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       const auto o = dst + ((u64)t << c.log_n) + n0;
 #pragma unroll
       for (int k = 0; k < CONV_CPT; ++k) {
-        u64 s = csub(r[k] - mulhi(r[k], m.one_s) * m.q, m.q);  // r mod q_t
+        u64 s = csub(mod1_lazy(r[k], m), m.q);  // r mod q_t
         if (2 * r[k] >= ql) s = submod(s, qm, m.q);           // centred
         o[k] = csub(v[k] + s, m.q);
       }
@@ -1143,7 +1139,7 @@ __device__ __forceinline__ void lift_item(const Common& c, const PairDesc& pd, u
 #pragma unroll
   for (int k = 0; k < Gm::R; ++k) {
     const u64 r = x[k];
-    u64 v = csub(r - mulhi(r, m.one_s) * m.q, m.q);  // r mod q_i
+    u64 v = csub(mod1_lazy(r, m), m.q);  // r mod q_i
     if (2 * r >= ql) v = submod(v, qlm, m.q);
     x[k] = v;
   }

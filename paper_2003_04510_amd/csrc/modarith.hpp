@@ -140,6 +140,32 @@ __device__ __forceinline__ u64 shoup63_lazy(u64 x, u64 w, u64 ws, u64 nq) {
   return ((u64)hi << 32) | (u32)t;
 }
 
+// floor(x s / 2^64) for s < 2^32 (below 2^32): the low word's product
+// contributes only its high half, so two 32-bit multiplies suffice.
+__device__ __forceinline__ u32 mulhi_u64_u32(u64 x, u32 s) {
+  const u64 t = (u64)(u32)(x >> 32) * s + __umulhi((u32)x, s);
+  return (u32)(t >> 32);
+}
+
+// x mod q in [0, 2q) for any x < 2^64 (Shoup's product by 1, companion
+// one_s = floor(2^64 / q)); for q > 2^32 the companion is below 2^32.
+__device__ __forceinline__ u64 mod1_lazy(u64 x, const ModInfo& m) {
+  if (m.q >> 32) return x - (u64)mulhi_u64_u32(x, (u32)m.one_s) * m.q;
+  return x - mulhi(x, m.one_s) * m.q;
+}
+
+// Canonical x mod q for x < 2^125 (x.hi < 2^61) and 2^32 < q < 2^61: the
+// high word through the 2^63-scaled Shoup product by 2^64 mod q (whose
+// companion floor(r64 2^63 / q) is r64s / 2), the low word through
+// mod1_lazy.  Same value as reduce128, fewer instructions.
+__device__ __forceinline__ u64 reduce125(U128 x, const ModInfo& m) {
+  const u64 u = shoup63_lazy(x.hi, m.r64, m.r64s >> 1, 0 - m.q);       // [0, 2q)
+  const u64 v = x.lo - (u64)mulhi_u64_u32(x.lo, (u32)m.one_s) * m.q;  // [0, 2q)
+  u64 r = u + v;
+  r = csub(r, m.q << 1);
+  return csub(r, m.q);
+}
+
 // x - m if x >= m else x, for x, m < 2^63; negm = 2^64 - m.
 __device__ __forceinline__ u64 sub_if_ge(u64 x, u64 negm) {
   const u64 t = x + negm;
