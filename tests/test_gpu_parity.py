@@ -116,6 +116,39 @@ def test_he_mul_extreme_inputs():
     assert np.array_equal(lib.to_host(out), want_out)
 
 
+def test_he_mul_maximal_modup_sources():
+    """Every mod-up source residue at its maximum q_i - 1, so the conversion's
+    128-bit sums reach their largest values: with ct2's a the NTT of the
+    polynomial 1, d2 = ct1's a, chosen as the NTT of the constant coefficient
+    vector v_i = (q_i - 1) [Q~_j / q_i]_{q_i}; the conversion's per-limb factor
+    [(Q~_j / q_i)^-1]_{q_i} turns every coefficient into q_i - 1."""
+    lib, orc = contexts("n16_L24")
+    level = 24
+    log("he_mul maximal mod-up sources", level)
+    rng = np.random.default_rng(31)
+    a1, a2 = [], []
+    for j in range(orc.num_digits(level)):
+        dig = [int(orc.q[i]) for i in orc.digit(j, level)]
+        qt = 1
+        for q in dig:
+            qt *= q
+        for q in dig:
+            v = (q - 1) * ((qt // q) % q) % q
+            limb = orc.ntt(len(a1), np.full(orc.N, v, dtype=np.uint64))
+            assert np.all(orc.intt(len(a1), limb) == v)
+            a1.append(limb)
+            a2.append(orc.ntt(len(a2), np.eye(1, orc.N, 0, dtype=np.uint64)[0]))
+    assert len(a1) == level
+    b1 = np.stack([rng.integers(0, q, orc.N, dtype=np.uint64) for q in orc.q[:level]])
+    b2 = np.stack([rng.integers(0, q, orc.N, dtype=np.uint64) for q in orc.q[:level]])
+    ct1, ct2 = np.stack([b1, np.stack(a1)]), np.stack([b2, np.stack(a2)])
+    evk = random_evk(orc, 3)
+    want_relin, want_out = orc.he_mul(level, ct1, ct2, evk)
+    relin, out = lib.he_mul(level, lib.to_device(ct1), lib.to_device(ct2), lib.to_device(evk))
+    assert np.array_equal(lib.to_host(relin), want_relin)
+    assert np.array_equal(lib.to_host(out), want_out)
+
+
 def test_he_mul_deterministic_repeats():
     lib, orc = contexts("n16_L24")
     level = 24
