@@ -404,9 +404,12 @@ __device__ __forceinline__ void with_arith(const ModInfo& mo, Body&& body) {
 // log2 of the register radix of a 2^logs-point sub-transform.  256 points
 // take three radix-8 rounds rather than two radix-16 rounds: twice the
 // waves per pass, which hides more memory latency in passes of about one
-// wave per SIMD (the passes over one HE Mul's limbs at N = 2^16).
+// wave per SIMD (the passes over one HE Mul's limbs at N = 2^16).  512
+// points (the blocks passes at N = 2^17) likewise take three radix-8
+// rounds: with two rounds of radix 32 a thread holds 32 values and the
+// combine pass needs more than 256 VGPRs (one wave per SIMD).
 __host__ __device__ constexpr int radix_log(int logs) {
-  return logs >= 9 ? 5 : (logs <= 6 || logs == 8 ? 3 : 4);
+  return logs >= 9 ? 3 : (logs <= 6 || logs == 8 ? 3 : 4);
 }
 template <int LOGS>
 struct Radix {
