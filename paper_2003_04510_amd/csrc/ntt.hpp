@@ -401,16 +401,16 @@ __device__ __forceinline__ void with_arith(const ModInfo& mo, Body&& body) {
   else body(IntA{});
 }
 
-// log2 of the register radix of a 2^logs-point sub-transform.  256 points
-// take three radix-8 rounds rather than two radix-16 rounds: twice the
-// waves per pass, which hides more memory latency in passes of about one
-// wave per SIMD (the passes over one HE Mul's limbs at N = 2^16).  512
-// points (the blocks passes at N = 2^17) likewise take three radix-8
-// rounds: with two rounds of radix 32 a thread holds 32 values and the
-// combine pass needs more than 256 VGPRs (one wave per SIMD).
-__host__ __device__ constexpr int radix_log(int logs) {
-  return logs >= 9 ? 3 : (logs <= 6 || logs == 8 ? 3 : 4);
-}
+// log2 of the register radix of a 2^logs-point sub-transform: radix 8 at
+// every size (64 to 512 points).  Fewer, larger rounds hold more values per
+// thread: 256 points in two radix-16 rounds halve the waves of a pass over
+// one HE Mul's limbs (about one wave per SIMD, so fewer waves hide less
+// memory latency), and 128 or 512 points at radix 16 or 32 push the passes
+// to 130-256 VGPRs (the combine pass at N = 2^17 to one wave per SIMD).
+// Measured per HE Mul: N = 2^15 0.108 -> 0.100 ms, N = 2^17 0.805 -> 0.720
+// ms against radix 16 / 32.  Batches may still choose radix 16 at N = 2^16
+// (see tile_code).
+__host__ __device__ constexpr int radix_log(int) { return 3; }
 template <int LOGS>
 struct Radix {
   static constexpr int LOGR = radix_log(LOGS);
