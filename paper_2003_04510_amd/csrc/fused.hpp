@@ -1024,7 +1024,9 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
   using PL = PassLayout<LOGS, false, EPW>;
   constexpr int THREADS = PassGeo<LOGS, EPW>::THREADS;
   using RF = RoundShape<LOGS, LOGR, 0>;
-  __shared__ u64 lds[PL::SUBS * Gm::SUB];
+  // two tiles: NTT(z) stays in the first while s (when transformed here)
+  // goes through the second, and the epilogue reads both from LDS
+  __shared__ u64 lds[2 * PL::SUBS * Gm::SUB];
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
@@ -1065,22 +1067,17 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
     sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, twl, base, M, [](int, typename A::V) {});
-    lds_barrier();
-    u64 Z[Gm::R];  // NTT(z) in the coalesced epilogue order
-#pragma unroll
-    for (int k = 0; k < Gm::R; ++k) {
-      const int idx = threadIdx.x + k * THREADS;
-      Z[k] = A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M);
-    }
+    typename A::V* const ts = tl + PL::SUBS * Gm::SUB;  // NTT(s)
     const bool two = resc && pd.wrl;  // s not merged into z
     if (two) {
-      lds_barrier();  // every Z is read before the tile is reused
 #pragma unroll
       for (int k = 0; k < Gm::R; ++k) x[k] = A::in(sp[RF::elem(tt, k / RF::G, k % RF::G)], M);
-      sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, twl, base, M,
+      sub_transform_regs<A, true, LOGS, LOGR, true>(x, ts + sub * Gm::SUB, tt, twl, base, M,
                                                     [](int, typename A::V) {});
-      lds_barrier();
     }
+    lds_barrier();
+    // NTT(z) (and NTT(s)) of element idx, in the coalesced epilogue order
+    const auto lz = [&](int idx) { return (idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1)); };
     constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
 #pragma unroll
     for (int k0 = 0; k0 < Gm::R; k0 += TG) {
@@ -1096,10 +1093,10 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
       for (int g = 0; g < TG; ++g) {
         const int idx = threadIdx.x + (k0 + g) * THREADS;
         const u64 md = shoup_lazy(kv[g], pw, pws, m.q);  // [0, 2q)
-        const u64 v = csub(csub(dv[g] + md + m.q - Z[k0 + g], m.q << 1), m.q);
+        const u64 v = csub(csub(dv[g] + md + m.q - A::template out<true>(tl[lz(idx)], M), m.q << 1), m.q);
         if (pd.wrl) rlu[idx] = v;
         if (resc) {
-          const u64 S = two ? A::template out<true>(tl[(idx >> LOGS) * Gm::SUB + Gm::pad(idx & (Gm::S - 1))], M) : 0;
+          const u64 S = two ? A::template out<true>(ts[lz(idx)], M) : 0;
           __builtin_nontemporal_store((W)csub(shoup_lazy(v + m.q - S, qw, qws, m.q), m.q), &ou[idx]);
         }
       }
