@@ -69,12 +69,14 @@ constexpr int IP_CPT = 2, IP_THREADS = 256;                        // inner prod
 __device__ __forceinline__ u32 xcd_item(u32 bid, u32 grid) { return (bid & 7u) * (grid >> 3) + (bid >> 3); }
 
 // ---------------------------------------------------------------- tables
-// One base-conversion target: z = (sum_{s < ns} y_s * c_s) mod t with
-// sources y_s = limb src_off + s, constants c_s = {c0, c1} (30-bit halves)
-// at consts[c_off + 2 s], t = modulus mi.
-struct ConvTarget {
-  u32 src_off, ns, c_off, mi;
-};
+// One base-conversion target, z = (sum_{s < ns} y_s c_s) mod t, as a record
+// of conv_rec_words(NSMAX) words (NSMAX: the kernel's source bound): five
+// 64-bit words (t, 2^64 mod t, its Shoup companion, floor(2^64 / t), and for
+// mod down q_{level-1} mod t, which the rescale's lift uses), then the
+// constants c_s = {c0, c1} (30-bit halves) of sources s < NSMAX, zero past
+// the job's ns sources.  A job's targets are consecutive records, so the
+// address of the next target's constants depends on nothing loaded.
+__host__ __device__ constexpr u32 conv_rec_words(int nsmax) { return 10 + 2 * nsmax; }
 // One conversion job (a digit for mod up, the special limbs for mod down):
 // targets tg[tg_off .. tg_off + nt) write limbs dst_off .. dst_off + nt.
 struct ConvJobDev {
@@ -86,11 +88,9 @@ constexpr int MAX_DIGITS = 64;  // key-switching digits (dnum) of a context
 // Per-level plan (device-resident, built once per context).
 struct PlanDev {
   const ConvJobDev* mu_jobs;  // [beta]
-  const ConvTarget* mu_tg;    // [dt_limbs]
-  const u32* mu_c;
+  const u32* mu_c;            // conversion records of the mod-up targets [dt_limbs]
   const ConvJobDev* md_jobs;  // [1]
-  const ConvTarget* md_tg;    // [level]
-  const u32* md_c;
+  const u32* md_c;            // ... of the mod-down targets [level]
   const u32* dt_mod;   // modulus of each mod-up limb [dt_limbs]
   const u32* dtg_limb; // mod-up limbs ordered by modulus [dt_limbs] ...
   const u32* dtg_first;// ... and where each modulus' run starts [dtg_count + 1]
@@ -595,8 +595,8 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 grp = uniform(local % CONV_GROUPS), rest = local / CONV_GROUPS;
   const u32 chunk = uniform(rest % nch), jz = uniform(rest / nch);
   const ConvJobDev J = ldc((MD ? ldc(&P->md_jobs) : ldc(&P->mu_jobs)) + (MD ? 0 : jz));
-  const ConvTarget* tg = MD ? ldc(&P->md_tg) : ldc(&P->mu_tg);
-  const u32* consts = MD ? ldc(&P->md_c) : ldc(&P->mu_c);
+  constexpr u32 RW = conv_rec_words(NSMAX);
+  const u32* recs = (MD ? ldc(&P->md_c) : ldc(&P->mu_c)) + (u64)J.tg_off * RW;
   const u64 N = 1ull << c.log_n;
   const u64 ne1 = pd.level + c.K + 1;
   const auto src = MD ? gw<W>(pd.ks) + (u64)jz * ne1 * N : gw<W>(pd.y);
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const bool merged = MD && pd.rs && !pd.wrl;
   const u32 nt = merged ? J.nt - 1 : J.nt;
   const u32 per = (nt + CONV_GROUPS - 1) / CONV_GROUPS;
-  const u32 t0 = grp * per, t1 = min(nt, t0 + per);
+  const u32 t0 = uniform(grp * per), t1 = uniform(min(nt, t0 + per));
   if (t0 >= t1) return;
   const u64 n0 = ((u64)chunk * CONV_THREADS + threadIdx.x) * CONV_CPT;
   const auto s0 = src + ((u64)J.src_off << c.log_n) + n0;
@@ -624,10 +624,33 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   // sum_s y_s c_s mod t for target index t of the job, canonical.  The
   // 64-bit partial sums take up to 15 sources without a carry; longer jobs
   // fold each run of 15 into a 128-bit total before the one reduction.
-  const auto convert = [&](u32 t, u64 (&v)[CONV_CPT]) {
-    const ConvTarget T = ldc(tg + J.tg_off + t);
-    const ModInfo m = ldc(c.mods + T.mi);
-    const u32* C = consts + T.c_off;
+  // The scalars of target t: its record (see conv_rec_words).  The loops
+  // below load target t+1's record before working on target t, so the
+  // scalar loads are in flight during the multiply-accumulates (the record's
+  // address depends on nothing loaded; constants past the job's sources are
+  // zero, so no source needs a branch).
+  struct Rec {
+    ModInfo m;  // q, r64, r64s, one_s
+    u64 extra;  // mod down: q_{level-1} mod t
+    u32 c0[NSMAX], c1[NSMAX];
+  };
+  const auto load = [&](u32 t) {
+    const u32* r = recs + (u64)t * RW;
+    Rec x{};
+    x.m.q = ldc((const u64*)r);
+    x.m.r64 = ldc((const u64*)(r + 2));
+    x.m.r64s = ldc((const u64*)(r + 4));
+    x.m.one_s = ldc((const u64*)(r + 6));
+    x.extra = ldc((const u64*)(r + 8));
+#pragma unroll
+    for (int s = 0; s < NSMAX; ++s) {
+      x.c0[s] = ldc(r + 10 + 2 * s);
+      x.c1[s] = ldc(r + 11 + 2 * s);
+    }
+    return x;
+  };
+  const auto convert = [&](const Rec& R, u64 (&v)[CONV_CPT]) {
+    const ModInfo& m = R.m;
     U128 tot[CONV_CPT];
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) tot[k] = U128{0, 0};
@@ -638,9 +661,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       for (int k = 0; k < CONV_CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
 #pragma unroll
       for (int s = s0; s < s0 + CONV_RUN && s < NSMAX; ++s) {
-        const u32 sc = min((u32)s, T.ns - 1);
-        const bool use = (u32)s < T.ns;
-        const u32 c0 = use ? ldc(C + 2 * sc) : 0u, c1 = use ? ldc(C + 2 * sc + 1) : 0u;
+        const u32 c0 = R.c0[s], c1 = R.c1[s];
 #pragma unroll
         for (int k = 0; k < CONV_CPT; ++k) {
           sll[k] += (u64)y0[s][k] * c0;
@@ -682,29 +703,32 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
     u64 r[CONV_CPT];
     {
       u64 zl[CONV_CPT];
-      convert(pd.level - 1, zl);
+      convert(load(pd.level - 1), zl);
       dropped(zl, r);
     }
     const u64 ql = ldc(&c.mods[pd.level - 1].q);
-    const u64* qlm = ldc(&P->qlmod);
+    Rec cur = load(t0);
     for (u32 t = t0; t < t1; ++t) {
+      const Rec nxt = load(t + 1 < t1 ? t + 1 : t);
       u64 v[CONV_CPT];
-      convert(t, v);
-      const ModInfo m = ldc(c.mods + t);
-      const u64 qm = ldc(qlm + t);
+      convert(cur, v);
+      const ModInfo& m = cur.m;
       const auto o = dst + ((u64)t << c.log_n) + n0;
 #pragma unroll
       for (int k = 0; k < CONV_CPT; ++k) {
-        u64 s = csub(mod1_lazy(r[k], m), m.q);  // r mod q_t
-        if (2 * r[k] >= ql) s = submod(s, qm, m.q);           // centred
+        u64 s = csub(mod1_lazy(r[k], m), m.q);           // r mod q_t
+        if (2 * r[k] >= ql) s = submod(s, cur.extra, m.q);  // centred
         o[k] = csub(v[k] + s, m.q);
       }
+      cur = nxt;
     }
     return;
   }
+  Rec cur = load(t0);
   for (u32 t = t0; t < t1; ++t) {
+    const Rec nxt = load(t + 1 < t1 ? t + 1 : t);
     u64 v[CONV_CPT];
-    convert(t, v);
+    convert(cur, v);
     const auto o = dst + ((u64)(J.dst_off + t) << c.log_n) + n0;
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) o[k] = v[k];
@@ -719,6 +743,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
         for (int k = 0; k < CONV_CPT; ++k) yy[k] = r[k];
       }
     }
+    cur = nxt;
   }
 }
 

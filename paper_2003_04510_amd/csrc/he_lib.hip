@@ -91,11 +91,9 @@ struct ConvJob {
 
 struct LevelPlan {
   u32 beta = 0, dt_limbs = 0;
-  size_t o_mu_tg = 0, o_mu_c = 0, o_md_tg = 0, o_md_c = 0, o_y_mod = 0, o_y_scale = 0, o_s_mod = 0, o_s_scale = 0;
-  const ConvTarget* mu_tg = nullptr;  // mod-up targets [dt_limbs]
-  const u32* mu_c = nullptr;          // their constants (30-bit halves)
-  const ConvTarget* md_tg = nullptr;  // mod-down targets [level]
-  const u32* md_c = nullptr;
+  size_t o_mu_c = 0, o_md_c = 0, o_y_mod = 0, o_y_scale = 0, o_s_mod = 0, o_s_scale = 0;
+  const u32* mu_c = nullptr;  // mod-up conversion records [dt_limbs] (see conv_rec_words)
+  const u32* md_c = nullptr;  // mod-down conversion records [level]
   const u32* y_mod = nullptr;         // INTT list of d2 (+ d0, d1 of the last limb): [level + 2]
   const u64* y_scale = nullptr;
   const u32* s_mod = nullptr;         // INTT list of the special limbs (+ limb level-1): [K + 1]
@@ -524,31 +522,34 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
       qlinv[2 * i] = invmod(ql, m);
       qlinv[2 * i + 1] = shoup(qlinv[2 * i], m);
     }
-    // fused-kernel tables: conversion targets with 30-bit split constants
+    // fused-kernel tables: one record per conversion target (its modulus's
+    // reduction constants, then 30-bit split constants padded with zeros to
+    // the kernel's source bound)
     {
-      std::vector<ConvTarget> mtg;
+      const auto record = [&](std::vector<u32>& out, u32 nsmax, u64 m, u64 extra, u32 ns, auto cst) {
+        const ModInfo mi = make_modinfo(m, N);
+        const u64 head[5] = {mi.q, mi.r64, mi.r64s, mi.one_s, extra};
+        for (u64 h : head) {
+          out.push_back((u32)h);
+          out.push_back((u32)(h >> 32));
+        }
+        for (u32 s2 = 0; s2 < nsmax; ++s2) {
+          const u64 cv = s2 < ns ? cst(s2) : 0;
+          out.push_back((u32)(cv & M30));
+          out.push_back((u32)(cv >> 30));
+        }
+      };
+      const u32 mu_ns = (u32)conv_bucket(c->alpha), md_ns = (u32)conv_bucket(K);
       std::vector<u32> mc;
       for (u32 j = 0; j < P.beta; ++j) {
         const ConvJob& J = jobs[j];
-        for (u32 t = 0; t < J.nt; ++t) {
-          mtg.push_back({J.src_off, J.ns, (u32)mc.size(), tmods[J.m_off + t]});
-          for (u32 s2 = 0; s2 < J.ns; ++s2) {
-            const u64 cv = consts[J.c_off + (size_t)s2 * J.nt + t];
-            mc.push_back((u32)(cv & M30));
-            mc.push_back((u32)(cv >> 30));
-          }
-        }
+        for (u32 t = 0; t < J.nt; ++t)
+          record(mc, mu_ns, c->mod[tmods[J.m_off + t]], 0, J.ns,
+                 [&](u32 s2) { return consts[J.c_off + (size_t)s2 * J.nt + t]; });
       }
-      std::vector<ConvTarget> dtg;
       std::vector<u32> dc;
-      for (u32 i = 0; i < lvl; ++i) {
-        dtg.push_back({lvl, K, (u32)dc.size(), i});
-        for (u32 k = 0; k < K; ++k) {
-          const u64 cv = mdc[(size_t)k * lvl + i];
-          dc.push_back((u32)(cv & M30));
-          dc.push_back((u32)(cv >> 30));
-        }
-      }
+      for (u32 i = 0; i < lvl; ++i)
+        record(dc, md_ns, q[i], i + 1 < lvl ? qlmod[i] : 0, K, [&](u32 k) { return mdc[(size_t)k * lvl + i]; });
       std::vector<u32> ymod(lvl + 2), smod(K + 1);
       std::vector<u64> ysc(2 * (lvl + 2)), ssc(2 * (K + 1));
       for (u32 i = 0; i < lvl; ++i) { ymod[i] = i; ysc[2 * i] = scale[2 * i]; ysc[2 * i + 1] = scale[2 * i + 1]; }
@@ -560,7 +561,7 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
       for (u32 j = 0; j < P.beta; ++j) mj[j] = {jobs[j].src_off, jobs[j].ns, jobs[j].dst_off, jobs[j].nt, jobs[j].dst_off, 0};
       dj[0] = {lvl, K, 0, lvl, 0, 0};
       P.o_mu_jobs = B.add(mj); P.o_md_jobs = B.add(dj);
-      P.o_mu_tg = B.add(mtg); P.o_mu_c = B.add(mc); P.o_md_tg = B.add(dtg); P.o_md_c = B.add(dc);
+      P.o_mu_c = B.add(mc); P.o_md_c = B.add(dc);
       P.o_y_mod = B.add(ymod); P.o_y_scale = B.add(ysc); P.o_s_mod = B.add(smod); P.o_s_scale = B.add(ssc);
     }
     P.o_modup_scale = B.add(scale); P.o_dt_mod = B.add(dt_mod); P.o_emod = B.add(emod);
@@ -614,10 +615,8 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
     LevelPlan& P = c->lv[lvl];
     uint8_t* d = c->blob;
     PlanDev pd{};
-    pd.mu_jobs = (const ConvJobDev*)(d + P.o_mu_jobs); pd.mu_tg = (const ConvTarget*)(d + P.o_mu_tg);
-    pd.mu_c = (const u32*)(d + P.o_mu_c);
-    pd.md_jobs = (const ConvJobDev*)(d + P.o_md_jobs); pd.md_tg = (const ConvTarget*)(d + P.o_md_tg);
-    pd.md_c = (const u32*)(d + P.o_md_c);
+    pd.mu_jobs = (const ConvJobDev*)(d + P.o_mu_jobs); pd.mu_c = (const u32*)(d + P.o_mu_c);
+    pd.md_jobs = (const ConvJobDev*)(d + P.o_md_jobs); pd.md_c = (const u32*)(d + P.o_md_c);
     pd.dt_mod = (const u32*)(d + P.o_dt_mod); pd.emod = (const u32*)(d + P.o_emod);
     pd.dtg_limb = (const u32*)(d + P.o_dtg_limb); pd.dtg_first = (const u32*)(d + P.o_dtg_first);
     pd.dtg_count = P.dtg_count;
@@ -647,8 +646,7 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
     P.emod = (const u32*)(b + P.o_emod);
     P.qlinv = (const u64*)(b + P.o_qlinv);
     P.qlmod = (const u64*)(b + P.o_qlmod);
-    P.mu_tg = (const ConvTarget*)(b + P.o_mu_tg); P.mu_c = (const u32*)(b + P.o_mu_c);
-    P.md_tg = (const ConvTarget*)(b + P.o_md_tg); P.md_c = (const u32*)(b + P.o_md_c);
+    P.mu_c = (const u32*)(b + P.o_mu_c); P.md_c = (const u32*)(b + P.o_md_c);
     P.y_mod = (const u32*)(b + P.o_y_mod); P.y_scale = (const u64*)(b + P.o_y_scale);
     P.s_mod = (const u32*)(b + P.o_s_mod); P.s_scale = (const u64*)(b + P.o_s_scale);
     P.mu_jobs = (const ConvJobDev*)(b + P.o_mu_jobs); P.md_jobs = (const ConvJobDev*)(b + P.o_md_jobs);
