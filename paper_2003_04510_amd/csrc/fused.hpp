@@ -61,6 +61,7 @@ struct TileCfg {
 };
 constexpr int CONV_CPT = 2, CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
 constexpr int CONV_RUN = 15;  // sources whose 30x30-bit products a 64-bit sum takes without a carry
+constexpr int CONV_MAXT = 32;  // targets of one conversion item (jobs of at most 4 x 32 targets)
 constexpr int IP_CPT = 2, IP_THREADS = 256;                        // inner product
 
 // Item index for workgroup `bid` of a grid of `grid` (grid % 8 == 0):
@@ -133,6 +134,8 @@ struct Common {
   const u64* pinv;  // Shoup pairs [P^-1]_{q_i}
   const u32* iota;  // 0, 1, 2, ...
   u32 L, K, log_n, dnum;
+  u32 bigq;         // every prime above 2^32 (the conversions' reductions then take one form)
+  u32 pad;
 };
 
 // Which pairs a launch covers.
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
 // down): all NSMAX source loads are issued unconditionally (index clamped to
 // the job's ns, constants of unused sources zero), so each thread waits for
 // its loads once instead of once per source.
-template <class W, bool MD, int NSMAX>
+template <class W, bool MD, int NSMAX, bool BIGQ>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
@@ -621,36 +624,50 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       y1[s][k] = (u32)(y >> 30);
     }
   }
-  // sum_s y_s c_s mod t for target index t of the job, canonical.  The
-  // 64-bit partial sums take up to 15 sources without a carry; longer jobs
-  // fold each run of 15 into a 128-bit total before the one reduction.
-  // The scalars of target t: its record (see conv_rec_words).  The loops
-  // below load target t+1's record before working on target t, so the
-  // scalar loads are in flight during the multiply-accumulates (the record's
-  // address depends on nothing loaded; constants past the job's sources are
-  // zero, so no source needs a branch).
-  struct Rec {
-    ModInfo m;  // q, r64, r64s, one_s
-    u64 extra;  // mod down: q_{level-1} mod t
-    u32 c0[NSMAX], c1[NSMAX];
+  // The item's target records (see conv_rec_words); slot i holds target
+  // t0 + i, slot t1 - t0 the dropped limb's target (merged rescale).  Mod
+  // down stages them in LDS right behind its source loads, so per target the
+  // constants come from LDS, whose loads complete in order and can run
+  // ahead of the arithmetic, rather than from scalar loads, which the
+  // compiler re-issues next to each use and waits on target by target
+  // (measured: 23.2 -> 21.1 us at n16_L24).  Mod up, and mod down from 12
+  // sources on, read them with scalar loads: there the constants' VGPRs
+  // would cost a wave per SIMD.
+  constexpr bool LREC = MD && NSMAX <= 8;
+  __shared__ u64 lrec64[LREC ? (CONV_MAXT + 1) * RW / 2 : 2];
+  u32* const lrec = reinterpret_cast<u32*>(lrec64);
+  if constexpr (LREC) {
+    const auto g = gbl(recs);
+    const u32 nw = (t1 - t0) * RW;
+    for (u32 i = threadIdx.x; i < nw; i += CONV_THREADS) lrec[i] = g[(u64)t0 * RW + i];
+    if (merged)
+      for (u32 i = threadIdx.x; i < RW; i += CONV_THREADS) lrec[nw + i] = g[(u64)(pd.level - 1) * RW + i];
+    lds_barrier();
+  }
+  // the record of slot `slot` in the table (the last slot, when merged, is
+  // target level-1)
+  const auto rec_of = [&](u32 slot) -> u64 { return merged && slot == t1 - t0 ? pd.level - 1 : t0 + slot; };
+  const auto rec32 = [&](u32 slot, u32 i) -> u32 {
+    if constexpr (LREC) return lrec[slot * RW + i];
+    else return ldc(recs + rec_of(slot) * RW + i);
   };
-  const auto load = [&](u32 t) {
-    const u32* r = recs + (u64)t * RW;
-    Rec x{};
-    x.m.q = ldc((const u64*)r);
-    x.m.r64 = ldc((const u64*)(r + 2));
-    x.m.r64s = ldc((const u64*)(r + 4));
-    x.m.one_s = ldc((const u64*)(r + 6));
-    x.extra = ldc((const u64*)(r + 8));
-#pragma unroll
-    for (int s = 0; s < NSMAX; ++s) {
-      x.c0[s] = ldc(r + 10 + 2 * s);
-      x.c1[s] = ldc(r + 11 + 2 * s);
-    }
-    return x;
+  const auto rec64 = [&](u32 slot, u32 i) -> u64 {
+    if constexpr (LREC) return lrec64[slot * (RW / 2) + i];
+    else return ldc(reinterpret_cast<const u64*>(recs + rec_of(slot) * RW) + i);
   };
-  const auto convert = [&](const Rec& R, u64 (&v)[CONV_CPT]) {
-    const ModInfo& m = R.m;
+  // sum_s y_s c_s mod t for the target in record slot `slot`, canonical.
+  // The 64-bit partial sums take up to 15 sources without a carry; longer
+  // jobs fold each run of 15 into a 128-bit total before the one reduction.
+  const auto modulus = [&](u32 slot) {
+    ModInfo m{};
+    m.q = rec64(slot, 0);
+    m.r64 = rec64(slot, 1);
+    m.r64s = rec64(slot, 2);
+    m.one_s = rec64(slot, 3);
+    return m;
+  };
+  const auto convert = [&](u32 slot, u64 (&v)[CONV_CPT]) {
+    const ModInfo m = modulus(slot);
     U128 tot[CONV_CPT];
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) tot[k] = U128{0, 0};
@@ -661,7 +678,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
       for (int k = 0; k < CONV_CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
 #pragma unroll
       for (int s = s0; s < s0 + CONV_RUN && s < NSMAX; ++s) {
-        const u32 c0 = R.c0[s], c1 = R.c1[s];
+        const u32 c0 = rec32(slot, 10 + 2 * s), c1 = rec32(slot, 11 + 2 * s);
 #pragma unroll
         for (int k = 0; k < CONV_CPT; ++k) {
           sll[k] += (u64)y0[s][k] * c0;
@@ -673,13 +690,10 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
 #pragma unroll
       for (int k = 0; k < CONV_CPT; ++k) add_to(tot[k], conv_sum(sll[k], slh[k], shl[k], shh[k]));
     }
-    if (m.q >> 32) {  // tot < 2^125
+    // one form per launch (BIGQ: every modulus above 2^32), so the body of
+    // a target has no branch and the next record's loads stay ahead of it
 #pragma unroll
-      for (int k = 0; k < CONV_CPT; ++k) v[k] = reduce125(tot[k], m);
-    } else {
-#pragma unroll
-      for (int k = 0; k < CONV_CPT; ++k) v[k] = reduce128(tot[k], m);
-    }
+    for (int k = 0; k < CONV_CPT; ++k) v[k] = BIGQ ? reduce125(tot[k], m) : reduce128(tot[k], m);  // tot < 2^125
   };
   // The rescale's dropped limb in coefficient form, by linearity: with the
   // mod-down constants carrying P^-1 (z' = z P^-1),
@@ -703,32 +717,29 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
     u64 r[CONV_CPT];
     {
       u64 zl[CONV_CPT];
-      convert(load(pd.level - 1), zl);
+      convert(t1 - t0, zl);
       dropped(zl, r);
     }
     const u64 ql = ldc(&c.mods[pd.level - 1].q);
-    Rec cur = load(t0);
     for (u32 t = t0; t < t1; ++t) {
-      const Rec nxt = load(t + 1 < t1 ? t + 1 : t);
       u64 v[CONV_CPT];
-      convert(cur, v);
-      const ModInfo& m = cur.m;
+      convert(t - t0, v);
+      const ModInfo m = modulus(t - t0);
+      const u64 qm = rec64(t - t0, 4);
       const auto o = dst + ((u64)t << c.log_n) + n0;
 #pragma unroll
       for (int k = 0; k < CONV_CPT; ++k) {
-        u64 s = csub(mod1_lazy(r[k], m), m.q);           // r mod q_t
-        if (2 * r[k] >= ql) s = submod(s, cur.extra, m.q);  // centred
+        const u64 rq = BIGQ ? (u64)mulhi_u64_u32(r[k], (u32)m.one_s) : mulhi(r[k], m.one_s);
+        u64 s = csub(r[k] - rq * m.q, m.q);               // r mod q_t
+        if (2 * r[k] >= ql) s = submod(s, qm, m.q);  // centred
         o[k] = csub(v[k] + s, m.q);
       }
-      cur = nxt;
     }
     return;
   }
-  Rec cur = load(t0);
   for (u32 t = t0; t < t1; ++t) {
-    const Rec nxt = load(t + 1 < t1 ? t + 1 : t);
     u64 v[CONV_CPT];
-    convert(cur, v);
+    convert(t - t0, v);
     const auto o = dst + ((u64)(J.dst_off + t) << c.log_n) + n0;
 #pragma unroll
     for (int k = 0; k < CONV_CPT; ++k) o[k] = v[k];
@@ -743,7 +754,6 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
         for (int k = 0; k < CONV_CPT; ++k) yy[k] = r[k];
       }
     }
-    cur = nxt;
   }
 }
 

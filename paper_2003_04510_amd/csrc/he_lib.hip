@@ -404,6 +404,8 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
   }
   if (c->alpha > 32 || K > 32)
     return fail(HE_EUNSUPPORTED, "digit size ceil(L/dnum) and K must be <= 32");
+  if (L + K > CONV_GROUPS * CONV_MAXT)  // a conversion item stages at most CONV_MAXT target records
+    return fail(HE_EUNSUPPORTED, "L + K must be <= %d", CONV_GROUPS * CONV_MAXT);
   // special primes must cover every digit: P > prod(digit)
   {
     long double lp = 0, ld = 0;
@@ -903,6 +905,8 @@ Common make_common(const he_ctx* c, const u64* evk) {
   Common cm{};
   cm.mods = c->mods; cm.tw = c->tw; cm.itw = c->itw; cm.evk = evk; cm.pinv = c->pinv; cm.iota = c->iota;
   cm.L = c->L; cm.K = c->K; cm.log_n = c->log_n; cm.dnum = c->dnum;
+  cm.bigq = 1;
+  for (u64 m : c->mod) cm.bigq &= m >> 32 ? 1u : 0u;
   return cm;
 }
 

@@ -28,15 +28,22 @@ void launch_lblocks(const Common& c, const Batch& b, hipStream_t st) {
                      st, c, b);
 }
 
+template <class W, bool MD, int NS>
+void launch_conv_ns(const Common& c, const Batch& b, hipStream_t st) {
+  // 32-bit words hold primes below 2^30: only the general reduction
+  constexpr bool WIDE = sizeof(W) == 8;
+  if (WIDE && c.bigq) hipLaunchKernelGGL((k_conv<W, MD, NS, WIDE>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b);
+  else hipLaunchKernelGGL((k_conv<W, MD, NS, false>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b);
+}
 template <class W, bool MD>
 void launch_conv(int bucket, const Common& c, const Batch& b, hipStream_t st) {
   switch (bucket) {
-    case 4: hipLaunchKernelGGL((k_conv<W, MD, 4>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 8: hipLaunchKernelGGL((k_conv<W, MD, 8>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 12: hipLaunchKernelGGL((k_conv<W, MD, 12>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 15: hipLaunchKernelGGL((k_conv<W, MD, 15>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    case 24: hipLaunchKernelGGL((k_conv<W, MD, 24>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
-    default: hipLaunchKernelGGL((k_conv<W, MD, 32>), dim3(pad8(b.nitems)), dim3(CONV_THREADS), 0, st, c, b); break;
+    case 4: launch_conv_ns<W, MD, 4>(c, b, st); break;
+    case 8: launch_conv_ns<W, MD, 8>(c, b, st); break;
+    case 12: launch_conv_ns<W, MD, 12>(c, b, st); break;
+    case 15: launch_conv_ns<W, MD, 15>(c, b, st); break;
+    case 24: launch_conv_ns<W, MD, 24>(c, b, st); break;
+    default: launch_conv_ns<W, MD, 32>(c, b, st); break;
   }
 }
 
