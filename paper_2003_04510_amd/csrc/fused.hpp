@@ -59,7 +59,11 @@ struct TileCfg {
   u32 epw_c = EPW_C, epw_b = EPW_B, fused_ip = 0;
   u32 logr = 0;  // log2 register radix of both NTT passes (0: the default per sub-transform size)
 };
-constexpr int CONV_CPT = 2, CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
+constexpr int CONV_THREADS = 256, CONV_GROUPS = 4;  // base conversion
+// Coefficients per conversion thread for jobs of up to ns sources: all the
+// source residues of a thread's coefficients stay in registers, so jobs of
+// more than 8 sources take one coefficient per thread.
+__host__ __device__ constexpr u32 conv_cpt(u32 ns) { return ns > 8 ? 1 : 2; }
 constexpr int CONV_RUN = 15;  // sources whose 30x30-bit products a 64-bit sum takes without a carry
 constexpr int CONV_MAXT = 32;  // targets of one conversion item (jobs of at most 4 x 32 targets)
 constexpr int IP_CPT = 2, IP_THREADS = 256;                        // inner product
@@ -206,23 +210,24 @@ __host__ __device__ constexpr u32 ipw_elems(u32 log_n) {
 __host__ __device__ constexpr u32 ipw_tiles(u32 log_n) { return (1u << log_n) / ipw_elems(log_n); }
 
 // Work items of one pair in a stage.
-inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 beta, u32 dt_limbs, bool rs, bool wrl,
+inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 alpha, u32 beta, u32 dt_limbs, bool rs, bool wrl,
                        TileCfg tc_cfg = TileCfg{}) {
   const u32 tc = cols_tiles(log_n, tc_cfg.epw_c), tb = blocks_tiles(log_n, tc_cfg.epw_b);
   const u32 chunks_i = (1u << log_n) / (IP_THREADS * IP_CPT);
-  const u32 chunks_c = (1u << log_n) / (CONV_THREADS * CONV_CPT);
+  const u32 chunks_up = (1u << log_n) / (CONV_THREADS * conv_cpt(alpha));
+  const u32 chunks_down = (1u << log_n) / (CONV_THREADS * conv_cpt(K));
   const u32 ex = rs ? 1 : 0;
   switch (st) {
     case ST_TENSOR: return (2 * level + 2 * ex) * tb;
     case ST_Y_ICOLS: return (level + 2 * ex) * tc;
-    case ST_MU_CONV: return beta * CONV_GROUPS * chunks_c;
+    case ST_MU_CONV: return beta * CONV_GROUPS * chunks_up;
     case ST_DT_NCOLS: return dt_limbs * tc;
     case ST_DT_NBLOCKS: return tc_cfg.fused_ip ? 0 : dt_limbs * tb;
     case ST_IP: return tc_cfg.fused_ip ? 0 : (level + K) * chunks_i;
     case ST_KS_IBLOCKS: return 0;  // in k_ip (separate path) or k_blocks_ip (fused path)
     case ST_BLOCKS_IP: return tc_cfg.fused_ip ? (level + K + ex) * ipw_tiles(log_n) : 0;
     case ST_KS_ICOLS: return 2 * (K + ex) * tc;
-    case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_c;
+    case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_down;
     case ST_Z_NCOLS: return rs ? (wrl ? 2 * level * tc + 2 * (level - 1) * tc : 2 * (level - 1) * tc) : 2 * level * tc;
     case ST_LIFT: return rs ? 2 * (level - 1) * tc : 0;
     case ST_COMBINE: return 2 * level * tb;
@@ -572,7 +577,7 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
 
 // ---------------------------------------------------------------- base conversion
 // Fast base conversion (the matrix form of the paper's iCRT, Algorithm 6,
-// with its delayed modulo): a thread owns CONV_CPT consecutive
+// with its delayed modulo): a thread owns conv_cpt(NSMAX) consecutive
 // coefficients, loads each source residue once (split into 30-bit halves),
 // then loops over a group of targets, accumulating four 64-bit sums of
 // 30x30-bit products (no carries for up to 15 sources, runs of 15 folded
@@ -587,12 +592,13 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
 // its loads once instead of once per source.
 template <class W, bool MD, int NSMAX, bool BIGQ>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
+  constexpr int CPT = conv_cpt(NSMAX);
   const u32 w = xcd_item(blockIdx.x, gridDim.x);
   if (w >= b.nitems) return;
   u32 local;
   const PairDesc pd = resolve(b, uniform(w), local);
   const PlanDev* P = pd.plan;
-  const u32 nch = (1u << c.log_n) / (CONV_THREADS * CONV_CPT);
+  const u32 nch = (1u << c.log_n) / (CONV_THREADS * CPT);
   // the target groups of a chunk are adjacent items (same XCD, same time),
   // so their repeated source loads hit L2
   const u32 grp = uniform(local % CONV_GROUPS), rest = local / CONV_GROUPS;
@@ -611,14 +617,14 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
   const u32 per = (nt + CONV_GROUPS - 1) / CONV_GROUPS;
   const u32 t0 = uniform(grp * per), t1 = uniform(min(nt, t0 + per));
   if (t0 >= t1) return;
-  const u64 n0 = ((u64)chunk * CONV_THREADS + threadIdx.x) * CONV_CPT;
+  const u64 n0 = ((u64)chunk * CONV_THREADS + threadIdx.x) * CPT;
   const auto s0 = src + ((u64)J.src_off << c.log_n) + n0;
-  u32 y0[NSMAX][CONV_CPT], y1[NSMAX][CONV_CPT];
+  u32 y0[NSMAX][CPT], y1[NSMAX][CPT];
 #pragma unroll
   for (int s = 0; s < NSMAX; ++s) {
     const u32 sc = min((u32)s, J.ns - 1);
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       const u64 y = s0[((u64)sc << c.log_n) + k];
       y0[s][k] = (u32)(y & M30);
       y1[s][k] = (u32)(y >> 30);
@@ -666,21 +672,21 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
     m.one_s = rec64(slot, 3);
     return m;
   };
-  const auto convert = [&](u32 slot, u64 (&v)[CONV_CPT]) {
+  const auto convert = [&](u32 slot, u64 (&v)[CPT]) {
     const ModInfo m = modulus(slot);
-    U128 tot[CONV_CPT];
+    U128 tot[CPT];
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) tot[k] = U128{0, 0};
+    for (int k = 0; k < CPT; ++k) tot[k] = U128{0, 0};
 #pragma unroll
     for (int s0 = 0; s0 < NSMAX; s0 += CONV_RUN) {
-      u64 sll[CONV_CPT], slh[CONV_CPT], shl[CONV_CPT], shh[CONV_CPT];
+      u64 sll[CPT], slh[CPT], shl[CPT], shh[CPT];
 #pragma unroll
-      for (int k = 0; k < CONV_CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
+      for (int k = 0; k < CPT; ++k) sll[k] = slh[k] = shl[k] = shh[k] = 0;
 #pragma unroll
       for (int s = s0; s < s0 + CONV_RUN && s < NSMAX; ++s) {
         const u32 c0 = rec32(slot, 10 + 2 * s), c1 = rec32(slot, 11 + 2 * s);
 #pragma unroll
-        for (int k = 0; k < CONV_CPT; ++k) {
+        for (int k = 0; k < CPT; ++k) {
           sll[k] += (u64)y0[s][k] * c0;
           slh[k] += (u64)y0[s][k] * c1;
           shl[k] += (u64)y1[s][k] * c0;
@@ -688,24 +694,24 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
         }
       }
 #pragma unroll
-      for (int k = 0; k < CONV_CPT; ++k) add_to(tot[k], conv_sum(sll[k], slh[k], shl[k], shh[k]));
+      for (int k = 0; k < CPT; ++k) add_to(tot[k], conv_sum(sll[k], slh[k], shl[k], shh[k]));
     }
     // one form per launch (BIGQ: every modulus above 2^32), so the body of
     // a target has no branch and the next record's loads stay ahead of it
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) v[k] = BIGQ ? reduce125(tot[k], m) : reduce128(tot[k], m);  // tot < 2^125
+    for (int k = 0; k < CPT; ++k) v[k] = BIGQ ? reduce125(tot[k], m) : reduce128(tot[k], m);  // tot < 2^125
   };
   // The rescale's dropped limb in coefficient form, by linearity: with the
   // mod-down constants carrying P^-1 (z' = z P^-1),
   //   r_u = INTT(d_u[l-1]) + INTT(ks_u[l-1]) [P^-1]_{q_{l-1}} - z'_u[l-1]
   // where INTT(d_u[l-1]) = y[level + u] and INTT(ks_u[l-1]) = ks_u[level + K].
-  const auto dropped = [&](const u64 (&zl)[CONV_CPT], u64 (&r)[CONV_CPT]) {
+  const auto dropped = [&](const u64 (&zl)[CPT], u64 (&r)[CPT]) {
     const u64 ql = ldc(&c.mods[pd.level - 1].q);
     const u64 pw = ldc(&P->pinv_l), pws = ldc(&P->pinv_ls);
     const auto yy = gw<W>(pd.y) + ((u64)(pd.level + jz) << c.log_n) + n0;
     const auto kk = src + ((u64)(pd.level + c.K) << c.log_n) + n0;
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       const u64 a = csub(yy[k] + csub(shoup_lazy(kk[k], pw, pws, ql), ql), ql);
       r[k] = submod(a, zl[k], ql);
     }
@@ -714,21 +720,21 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
     // Every group forms r (one more target), then each output is
     // z'_t + [r]_t with r lifted centred; the NTT of that sum is
     // NTT(z) P^-1 + NTT(s), so one transform serves mod down and rescale.
-    u64 r[CONV_CPT];
+    u64 r[CPT];
     {
-      u64 zl[CONV_CPT];
+      u64 zl[CPT];
       convert(t1 - t0, zl);
       dropped(zl, r);
     }
     const u64 ql = ldc(&c.mods[pd.level - 1].q);
     for (u32 t = t0; t < t1; ++t) {
-      u64 v[CONV_CPT];
+      u64 v[CPT];
       convert(t - t0, v);
       const ModInfo m = modulus(t - t0);
       const u64 qm = rec64(t - t0, 4);
       const auto o = dst + ((u64)t << c.log_n) + n0;
 #pragma unroll
-      for (int k = 0; k < CONV_CPT; ++k) {
+      for (int k = 0; k < CPT; ++k) {
         const u64 rq = BIGQ ? (u64)mulhi_u64_u32(r[k], (u32)m.one_s) : mulhi(r[k], m.one_s);
         u64 s = csub(r[k] - rq * m.q, m.q);               // r mod q_t
         if (2 * r[k] >= ql) s = submod(s, qm, m.q);  // centred
@@ -738,20 +744,20 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(Common c, Batch b) {
     return;
   }
   for (u32 t = t0; t < t1; ++t) {
-    u64 v[CONV_CPT];
+    u64 v[CPT];
     convert(t - t0, v);
     const auto o = dst + ((u64)(J.dst_off + t) << c.log_n) + n0;
 #pragma unroll
-    for (int k = 0; k < CONV_CPT; ++k) o[k] = v[k];
+    for (int k = 0; k < CPT; ++k) o[k] = v[k];
     if constexpr (MD) {
       // rescaling with the relinearized value as an output: r_u replaces
       // y[level + u] for the lift
       if (pd.rs && t == pd.level - 1) {
-        u64 r[CONV_CPT];
+        u64 r[CPT];
         dropped(v, r);
         const auto yy = gw<W>(pd.y) + ((u64)(pd.level + jz) << c.log_n) + n0;
 #pragma unroll
-        for (int k = 0; k < CONV_CPT; ++k) yy[k] = r[k];
+        for (int k = 0; k < CPT; ++k) yy[k] = r[k];
       }
     }
   }

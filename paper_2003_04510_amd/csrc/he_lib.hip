@@ -972,7 +972,7 @@ static he_status mul_impl(he_ctx* c, uint32_t level, const uint64_t* ct1, const 
     Batch b{};
     b.one = pd;
     b.npairs = 1;
-    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, pd.rs != 0, pd.wrl != 0, default_tiles(c->log_n));
+    b.nitems = stage_items(s, c->log_n, level, c->K, c->alpha, P.beta, P.dt_limbs, pd.rs != 0, pd.wrl != 0, default_tiles(c->log_n));
     double ops = 0, bytes = 0;
     if (c->timing) stage_work(c, s, level, pd.rs != 0, ops, bytes, pd.wrl != 0);
     launch_stage(c, s, cm, b, ops, bytes, on, default_tiles(c->log_n));
@@ -1024,7 +1024,7 @@ he_status he_rescale(he_ctx* c, uint32_t level, const uint64_t* d_in, uint64_t* 
     Batch b{};
     b.one = pd;
     b.npairs = 1;
-    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, true, false, default_tiles(c->log_n));
+    b.nitems = stage_items(s, c->log_n, level, c->K, c->alpha, P.beta, P.dt_limbs, true, false, default_tiles(c->log_n));
     double ops = 0, bytes = 0;
     if (c->timing) stage_work(c, s, level, true, ops, bytes);
     launch_stage(c, s, cm, b, ops, bytes, st, default_tiles(c->log_n));
@@ -1147,7 +1147,7 @@ static he_status batch_offsets(const he_ctx* c, he_batch* bt) {
     for (u32 i = 0; i < n; ++i) {
       bt->hoffs[(size_t)s * (n + 1) + i] = (u32)acc;
       const LevelPlan& P = c->lv[bt->levels[i]];
-      acc += stage_items(s, c->log_n, bt->levels[i], c->K, P.beta, P.dt_limbs, bt->rs[i] != 0, bt->wrl[i] != 0, bt->tiles);
+      acc += stage_items(s, c->log_n, bt->levels[i], c->K, c->alpha, P.beta, P.dt_limbs, bt->rs[i] != 0, bt->wrl[i] != 0, bt->tiles);
     }
     if (acc > 0xffffff00ull) return fail(HE_EUNSUPPORTED, "he_batch: batch too large");
     bt->hoffs[(size_t)s * (n + 1) + n] = (u32)acc;

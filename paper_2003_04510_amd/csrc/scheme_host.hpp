@@ -176,7 +176,7 @@ he_status he_rotate(he_ctx* c, uint32_t level, const uint64_t* d_ct, const uint6
     Batch b{};
     b.one = pd;
     b.npairs = 1;
-    b.nitems = stage_items(s, c->log_n, level, c->K, P.beta, P.dt_limbs, false, true, tc);
+    b.nitems = stage_items(s, c->log_n, level, c->K, c->alpha, P.beta, P.dt_limbs, false, true, tc);
     double ops = 0, bytes = 0;
     if (c->timing) stage_work(c, s, level, false, ops, bytes, true);
     launch_stage(c, s, cm, b, ops, bytes, st, tc);
