@@ -89,11 +89,14 @@ def test_he_mul_n17(level):
 
 
 @pytest.mark.parametrize("wname,level", [("n16_L24_d1", 24), ("n16_L24_d1", 9), ("n16_L24_d24", 24),
-                                         ("n16_L24_d24", 5), ("n12_L6_d1", 6), ("n12_L6_d6", 6)])
+                                         ("n16_L24_d24", 5), ("n12_L6_d1", 6), ("n12_L6_d6", 6),
+                                         ("n12_L28_d1", 28), ("n12_L28_d1", 13)])
 def test_he_mul_dnum_variants(wname, level):
     """Key switching with dnum = 1 (one digit of up to 24 primes, 21 special
-    primes: the conversion's runs of 15 sources folded in 128 bits) and
-    dnum = L (one prime per digit, 24 digits in the inner product)."""
+    primes: the conversion's runs of 15 sources folded in 128 bits; 28 and
+    24 sources at N = 2^12, the conversion's widest source bound, with the
+    digit cut to 13 primes at level 13) and dnum = L (one prime per digit,
+    24 digits in the inner product)."""
     _he_mul_case(wname, level)
 
 
