@@ -86,9 +86,12 @@ CFG_N12_DL = _mk("n12_L6_d6", 12, 6, 2, 6, 64, 40, 60, 50, 60)
 # primes (60 + 27 x 50 bits) and K = 24 special primes of 60 bits (1440 bits
 # > 1410): 28 sources in the mod-up conversion, 24 in the mod-down one.
 CFG_N12_D1W = _mk("n12_L28_d1", 12, 28, 24, 1, 64, 40, 60, 50, 60)
+# Ring degrees 2^13 and 2^14 (128-point blocks sub-transforms): small L.
+CFG_N13 = _mk("n13_L4", 13, 4, 2, 2, 64, 40, 60, 50, 60)
+CFG_N14 = _mk("n14_L6", 14, 6, 3, 2, 64, 40, 60, 50, 60)
 
 WORKLOADS = {w.name: w for w in (CFG_N12, CFG_N16, CFG_N17, CFG_N15, CFG_TINY, CFG_N16_W30, CFG_N12_W30,
-                                 CFG_N16_D1, CFG_N16_DL, CFG_N12_D1, CFG_N12_DL, CFG_N12_D1W)}
+                                 CFG_N16_D1, CFG_N16_DL, CFG_N12_D1, CFG_N12_DL, CFG_N12_D1W, CFG_N13, CFG_N14)}
 
 # Seeds of the measured workload.
 SEED_KEYS, SEED_MSG_A, SEED_MSG_B, SEED_ENC_A, SEED_ENC_B = 1, 2, 3, 4, 5

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 SMALL = synth.Workload("n12_L7_ragged", 12, 7, 3, 3, (60, 50, 50, 50, 50, 50, 50), 60, 64, 40)
 
 
-@pytest.mark.parametrize("wname", ["n12_L3", "n15_L12", "n16_L24", "n17_L45"])
+@pytest.mark.parametrize("wname", ["n12_L3", "n13_L4", "n14_L6", "n15_L12", "n16_L24", "n17_L45"])
 def test_ntt_intt_bit_exact(wname):
     lib, orc = contexts(wname)
     log("ntt", wname)
@@ -97,6 +97,14 @@ def test_he_mul_dnum_variants(wname, level):
     24 sources at N = 2^12, the conversion's widest source bound, with the
     digit cut to 13 primes at level 13) and dnum = L (one prime per digit,
     24 digits in the inner product)."""
+    _he_mul_case(wname, level)
+
+
+@pytest.mark.parametrize("wname,level", [("n13_L4", 4), ("n13_L4", 3), ("n14_L6", 6), ("n14_L6", 2)])
+def test_he_mul_n13_n14(wname, level):
+    """Ring degrees 2^13 and 2^14: 128-point blocks sub-transforms (and
+    64- / 128-point cols sub-transforms) in every pass, including the inner
+    product's inverse blocks epilogue."""
     _he_mul_case(wname, level)
 
 
