@@ -253,10 +253,12 @@ void he_batch_destroy(he_batch* batch);
  * level; their stage sequences alternate between the batch's stream and a
  * side stream the batch owns, so stages of different groups overlap; a
  * captured graph keeps that structure.  Results are identical under every
- * schedule.  ip_fused (0 or 1): run the mod-up NTT blocks pass, the evk inner
- * product and the special limbs' INTT blocks pass as one fused pass (less
- * HBM traffic, longer dependency chains per workgroup) instead of three;
- * it runs one digit per wavefront of a 4-wave workgroup, so dnum <= 4.
+ * schedule.  ip_fused (0..4): for the pairs of at least ip_fused key-switching
+ * digits (0: none), run the mod-up NTT blocks pass, the evk inner product and
+ * the special limbs' INTT blocks pass as one fused pass (less HBM traffic,
+ * longer dependency chains per workgroup) instead of the separate launches;
+ * it runs one digit per wavefront of a 4-wave workgroup, so dnum <= 4, and
+ * pairs of fewer digits leave waves idle in its NTT phase.
  * radix: the register radix of the NTT passes' butterfly rounds (the paper
  * sweeps the NTT radix, Table IX): 0 or the default (8 for the 256-point
  * sub-transforms at N = 2^16) or, at N = 2^16, 16 (two radix-16 rounds, one
@@ -270,8 +272,8 @@ void he_batch_destroy(he_batch* batch);
  * he_batch_autotune: runs the batch (overwriting its outputs with the same
  * values) as a graph `reps` times under each candidate schedule -- every
  * available tile pair and radix with one chunk, then the best of those with
- * the fused inner product (dnum <= 4), then the best so far with 2 and 4
- * chunks --
+ * the fused inner product for the pairs of at least 1, 2, 3 digits
+ * (dnum <= 4), then the best so far with 2 and 4 chunks --
  * times each with HIP events on `stream`, and installs the
  * fastest; *best and *best_ms (may be NULL) receive it and its time per
  * replay.  Synchronizes `stream`. */

@@ -53,8 +53,10 @@ __device__ __forceinline__ gptr<const W> gw(const u64* p) {
 // passes 2048; batches at N = 2^16 may select other tiles (TileCfg).
 constexpr int EPW_C = 4096, EPW_B = 2048;
 // fused_ip selects k_blocks_ip (mod-up NTT blocks + inner product +
-// special INTT blocks in one pass, less HBM traffic) over the three
-// separate launches (shorter dependency chains per workgroup).
+// special INTT blocks in one pass, less HBM traffic) over the separate
+// launches (shorter dependency chains per workgroup) for the pairs of at
+// least fused_ip digits (0: none): the fused pass runs one digit per
+// wavefront, so pairs of few digits leave waves idle in its NTT phase.
 struct TileCfg {
   u32 epw_c = EPW_C, epw_b = EPW_B, fused_ip = 0;
   u32 logr = 0;  // log2 register radix of both NTT passes (0: the default per sub-transform size)
@@ -217,15 +219,16 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 alpha, u32 beta,
   const u32 chunks_up = (1u << log_n) / (CONV_THREADS * conv_cpt(alpha));
   const u32 chunks_down = (1u << log_n) / (CONV_THREADS * conv_cpt(K));
   const u32 ex = rs ? 1 : 0;
+  const bool fused = tc_cfg.fused_ip && beta >= tc_cfg.fused_ip;
   switch (st) {
     case ST_TENSOR: return (2 * level + 2 * ex) * tb;
     case ST_Y_ICOLS: return (level + 2 * ex) * tc;
     case ST_MU_CONV: return beta * CONV_GROUPS * chunks_up;
     case ST_DT_NCOLS: return dt_limbs * tc;
-    case ST_DT_NBLOCKS: return tc_cfg.fused_ip ? 0 : dt_limbs * tb;
-    case ST_IP: return tc_cfg.fused_ip ? 0 : (level + K) * chunks_i;
+    case ST_DT_NBLOCKS: return fused ? 0 : dt_limbs * tb;
+    case ST_IP: return fused ? 0 : (level + K) * chunks_i;
     case ST_KS_IBLOCKS: return 0;  // in k_ip (separate path) or k_blocks_ip (fused path)
-    case ST_BLOCKS_IP: return tc_cfg.fused_ip ? (level + K + ex) * ipw_tiles(log_n) : 0;
+    case ST_BLOCKS_IP: return fused ? (level + K + ex) * ipw_tiles(log_n) : 0;
     case ST_KS_ICOLS: return 2 * (K + ex) * tc;
     case ST_MD_CONV: return 2 * CONV_GROUPS * chunks_down;
     case ST_Z_NCOLS: return rs ? (wrl ? 2 * level * tc + 2 * (level - 1) * tc : 2 * (level - 1) * tc) : 2 * level * tc;

@@ -806,7 +806,7 @@ namespace {
 // Tile choices a batch may select: the defaults at every ring degree, and
 // at N = 2^16 also 2048-element cols tiles and 1024-element blocks tiles.
 bool tiles_supported(u32 log_n, TileCfg t) {
-  if (t.fused_ip > 1) return false;
+  if (t.fused_ip > (u32)IP_WAVES) return false;  // a digit threshold: pairs of >= fused_ip digits fuse
   if (t.logr != 0 && !(log_n == 16 && t.logr == 4)) return false;  // radix 16 at N = 2^16 only
   if (t.epw_c == EPW_C && t.epw_b == EPW_B) return true;
   return log_n == 16 && (t.epw_c == 2048 || t.epw_c == 4096) && (t.epw_b == 1024 || t.epw_b == 2048);
@@ -1564,9 +1564,13 @@ he_status he_batch_autotune(he_ctx* c, he_batch* bt, const uint64_t* evk, uint32
     if ((r = run(sc, ms)) != HE_OK) break;
     if (ms < bms) { bms = ms; b = sc; }
   }
-  if (r == HE_OK && c->dnum <= (u32)IP_WAVES) {  // the fused mod-up blocks + inner product pass
-    he_batch_sched sc = b;
-    sc.ip_fused = 1;  // (at its own radix; the other passes keep the chosen one)
+  // the fused mod-up blocks + inner product pass for the pairs of at least
+  // 1, 2 or 3 digits (at its own radix; the other passes keep the chosen one)
+  const he_batch_sched plain = b;
+  for (uint32_t f = 1; f <= std::min(3u, c->dnum); ++f) {
+    if (r != HE_OK || c->dnum > (u32)IP_WAVES) break;
+    he_batch_sched sc = plain;
+    sc.ip_fused = f;
     double ms = 0;
     if ((r = run(sc, ms)) == HE_OK && ms < bms) { bms = ms; b = sc; }
   }

@@ -90,7 +90,7 @@ def test_batch_n12_all_levels_every_schedule():
     bt = lib.batch(items)
     sc = bt.sched()
     import torch
-    for fused in (0, 1):
+    for fused in (0, 1, 2, 3):  # none, every pair, the pairs of >= 2 or 3 digits
         for chunks in (1, 2, 4):
             bt.set_sched(sc["cols_tile"], sc["blocks_tile"], chunks, fused)
             for k, use_graph in enumerate((False, True, True)):
@@ -133,11 +133,14 @@ N16_LEVELS = (24, 4, 17, 9, 24, 5, 12, 20)
 @pytest.mark.parametrize("sched", [(4096, 2048, 1, 0, 8), (2048, 2048, 2, 0, 8), (4096, 1024, 4, 1, 8),
                                    (2048, 1024, 3, 1, 8), (4096, 2048, 8, 0, 8), (4096, 1024, 1, 1, 8),
                                    (2048, 1024, 2, 1, 8), (4096, 1024, 2, 0, 8), (2048, 1024, 1, 0, 16),
-                                   (4096, 2048, 2, 0, 16), (2048, 2048, 1, 1, 16), (4096, 1024, 3, 0, 16)])
+                                   (4096, 2048, 2, 0, 16), (2048, 2048, 1, 1, 16), (4096, 1024, 3, 0, 16),
+                                   (2048, 1024, 1, 2, 8), (4096, 1024, 2, 3, 16)])
 def test_batch_schedules_match_oracle(sched):
     """Every tile choice, NTT radix, chunk split and the fused inner-product
-    pass give the oracle's results for every pair, eagerly and on repeated
-    graph replays."""
+    pass (for every pair, or only for the pairs of at least 2 or 3 digits,
+    the others taking the separate launches in the same batch) give the
+    oracle's results for every pair, eagerly and on repeated graph
+    replays."""
     lib, orc, evk, items, want = _setup("n16_L24", N16_LEVELS, 500, 7, 3)
     log("batch sched", sched, N16_LEVELS)
     bt = lib.batch(items)
@@ -159,7 +162,7 @@ def test_batch_autotune_keeps_results():
     assert ms > 0
     assert sc == bt.sched()
     assert sc["cols_tile"] in (2048, 4096) and sc["blocks_tile"] in (1024, 2048) and sc["chunks"] in (1, 2, 4)
-    assert sc["ip_fused"] in (0, 1) and sc["radix"] in (8, 16)
+    assert sc["ip_fused"] in (0, 1, 2, 3) and sc["radix"] in (8, 16)
     for k, use_graph in enumerate((True, False, True)):
         _run_check(lib, bt, items, evk, want, use_graph, ("tuned", k))
     bt.close()
@@ -176,7 +179,7 @@ def test_batch_sched_errors():
     with pytest.raises(P.HeError):
         bt.set_sched(4096, 2048, 3)   # more chunks than pairs
     with pytest.raises(P.HeError):
-        bt.set_sched(4096, 2048, 1, 2)  # ip_fused is 0 or 1
+        bt.set_sched(4096, 2048, 1, 5)  # ip_fused: a digit threshold 0..4
     with pytest.raises(P.HeError, match="radix"):
         bt.set_sched(4096, 2048, 1, 0, 16)  # radix 16 only at N = 2^16
     with pytest.raises(P.HeError, match="radix"):
