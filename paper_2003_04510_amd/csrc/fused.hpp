@@ -801,7 +801,12 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
   const PairDesc pd = resolve(b, uniform(w), local);
   const PlanDev* P = pd.plan;
   const u32 nel = pd.level + c.K;
-  const u32 chunk = uniform(local / nel), e = uniform(local % nel);
+  // items in 8 chunk blocks (one per XCD when the item count is a multiple
+  // of 8), limb-major inside a block: each XCD takes its share of the
+  // special limbs' transforms, and a limb's chunks stay adjacent
+  const u32 nch = (1u << c.log_n) / (IP_THREADS * IP_CPT), cpb = nch / 8, blk = nel * cpb;
+  const u32 rem = local % blk;
+  const u32 e = uniform(rem / cpb), chunk = uniform((local / blk) * cpb + rem % cpb);
   const u64 n0 = ((u64)chunk * IP_THREADS + threadIdx.x) * IP_CPT;
   const u32 mi = ldc(ldc(&P->emod) + e);
   const ModInfo m = ldc(c.mods + mi);
