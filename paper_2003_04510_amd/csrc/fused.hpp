@@ -141,7 +141,8 @@ struct Common {
   const u32* iota;  // 0, 1, 2, ...
   u32 L, K, log_n, dnum;
   u32 bigq;         // every prime above 2^32 (the conversions' reductions then take one form)
-  u32 pad;
+  u32 gstride;      // words per modulus of gtw / igtw
+  const double *gtw, *igtw;  // factored blocks-pass twiddles of the FP64 moduli (GenTw)
 };
 
 // Which pairs a launch covers.
@@ -238,6 +239,20 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 alpha, u32 beta,
     case ST_Y_IBLOCKS: return level * tb;
   }
   return 0;
+}
+
+// ---------------------------------------------------------------- blocks-pass twiddles
+// Twiddle source of the sub-transform of row block blk (of 2^(log_n - LOGS))
+// in a blocks pass of modulus mi: the factored form for FP64 moduli (GenTw),
+// the table otherwise.
+template <class A, bool FWD, int LOGS>
+__device__ __forceinline__ auto blocks_tw(const Common& c, u32 mi, u64 blk) {
+  if constexpr (std::is_same<A, F64A>::value) {
+    const double* g = (FWD ? c.gtw : c.igtw) + (u64)mi * c.gstride;
+    return GenTw{g, g + (1u << LOGS) + blk * LOGS};
+  } else {
+    return TabTw{(FWD ? c.tw : c.itw) + ((u64)mi << c.log_n), (1ull << (c.log_n - LOGS)) + blk};
+  }
 }
 
 // ---------------------------------------------------------------- base conversion helpers
@@ -400,9 +415,9 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_tensor_intt(Common 
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
     if constexpr (sizeof(typename A::V) != 8) lds_barrier();
-    sub_transform_regs<A, false, LOGS, LOGR, false>(
-        x, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, c.itw + ((u64)i << c.log_n),
-        (1ull << n1) + blk0 + sub, M, [&](int e, typename A::V v) { out[e] = A::template out<false>(v, M); });
+    sub_transform_src<A, false, LOGS, LOGR, false>(
+        x, reinterpret_cast<typename A::V*>(lds) + sub * Gm::SUB, tt, blocks_tw<A, false, LOGS>(c, i, blk0 + sub), M,
+        [&](int e, typename A::V v) { out[e] = A::template out<false>(v, M); });
   });
 }
 
@@ -564,9 +579,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
     // 4-byte values: the inverse input tile (8-byte words) is read by every
     // thread before the transform reuses it
     if constexpr (!FWD && sizeof(typename A::V) != 8) lds_barrier();
-    sub_transform_regs<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
-                                                (1ull << n1) + blk0 + sub, M,
-                                                [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); });
+    sub_transform_src<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, blocks_tw<A, FWD, LOGS>(c, mi, blk0 + sub), M,
+                                               [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); });
     if constexpr (FWD) {
       lds_barrier();
 #pragma unroll
@@ -901,8 +915,8 @@ __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
     const u64 blk = (u64)chunk * SUBS + sub;  // the sub-transform's block in the limb
     const u64 slot = last ? pd.level + c.K : e;
     const auto out = gw<W>(pd.ks) + (z ? kz : 0) + (slot << c.log_n) + (blk << LOGS);
-    sub_transform_regs<A, false, LOGS, LOGR, false, true>(
-        x, tl + g * Gm::SUB, tt, c.itw + ((u64)mi << c.log_n), (1ull << (c.log_n - LOGS)) + blk, M,
+    sub_transform_src<A, false, LOGS, LOGR, false, true>(
+        x, tl + g * Gm::SUB, tt, blocks_tw<A, false, LOGS>(c, mi, blk), M,
         [&](int e2, typename A::V v) { out[e2] = A::template out<false>(v, M); });
   });
 }
@@ -978,9 +992,9 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
         typename A::V x[Gm::R];
 #pragma unroll
         for (int k = 0; k < Gm::R; ++k) x[k] = A::in(src[RF::elem(tt, k / RF::G, k % RF::G)], M);
-        sub_transform_regs<A, true, LOGS, LOGR, true, true>(x, mine + sub * Gm::SUB, tt,
-                                                            c.tw + ((u64)mi << c.log_n), base, M,
-                                                            [](int, typename A::V) {});
+        sub_transform_src<A, true, LOGS, LOGR, true, true>(x, mine + sub * Gm::SUB, tt,
+                                                           blocks_tw<A, true, LOGS>(c, mi, base - (1ull << n1)), M,
+                                                           [](int, typename A::V) {});
       }
     }
     // phase 2 operands: the evk values of this thread's elements for every
@@ -1049,8 +1063,8 @@ __global__ __launch_bounds__(64 * IP_WAVES) void k_blocks_ip(Common c, Batch b) 
       lds_get<LOGS, LOGR, IFIRST>(mine + sub * Gm::SUB, x, tt);
       const u64 slot = copy ? pd.level + c.K : e;
       const auto out = gw<W>(pd.ks) + (wave ? kz : 0) + (slot << c.log_n) + toff + ((u64)sub << LOGS);
-      sub_transform_regs<A, false, LOGS, LOGR, false, true>(
-          x, mine + sub * Gm::SUB, tt, c.itw + ((u64)mi << c.log_n), base, M,
+      sub_transform_src<A, false, LOGS, LOGR, false, true>(
+          x, mine + sub * Gm::SUB, tt, blocks_tw<A, false, LOGS>(c, mi, base - (1ull << n1)), M,
           [&](int e2, typename A::V v) { out[e2] = A::template out<false>(v, M); });
     }
   });
@@ -1106,7 +1120,6 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
     qw = ldc(ql + 2 * i);
     qws = ldc(ql + 2 * i + 1);
   }
-  const Tw2* twl = c.tw + ((u64)i << c.log_n);
   const u64 base = (1ull << n1) + blk0 + sub;
   with_arith<W>(m, [&](auto ar) {
     using A = decltype(ar);
@@ -1115,14 +1128,14 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_combine(Common 
     typename A::V x[Gm::R];
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
-    sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, twl, base, M, [](int, typename A::V) {});
+    const auto tws = blocks_tw<A, true, LOGS>(c, i, base - (1ull << n1));
+    sub_transform_src<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, tws, M, [](int, typename A::V) {});
     typename A::V* const ts = tl + PL::SUBS * Gm::SUB;  // NTT(s)
     const bool two = resc && pd.wrl;  // s not merged into z
     if (two) {
 #pragma unroll
       for (int k = 0; k < Gm::R; ++k) x[k] = A::in(sp[RF::elem(tt, k / RF::G, k % RF::G)], M);
-      sub_transform_regs<A, true, LOGS, LOGR, true>(x, ts + sub * Gm::SUB, tt, twl, base, M,
-                                                    [](int, typename A::V) {});
+      sub_transform_src<A, true, LOGS, LOGR, true>(x, ts + sub * Gm::SUB, tt, tws, M, [](int, typename A::V) {});
     }
     lds_barrier();
     // NTT(z) (and NTT(s)) of element idx, in the coalesced epilogue order
@@ -1290,8 +1303,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_ntt_rescale(Common 
     typename A::V x[Gm::R];
 #pragma unroll
     for (int k = 0; k < Gm::R; ++k) x[k] = A::in(xi[k], M);
-    sub_transform_regs<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, c.tw + ((u64)i << c.log_n),
-                                                  (1ull << n1) + blk0 + sub, M, [](int, typename A::V) {});
+    sub_transform_src<A, true, LOGS, LOGR, true>(x, tl + sub * Gm::SUB, tt, blocks_tw<A, true, LOGS>(c, i, blk0 + sub),
+                                                 M, [](int, typename A::V) {});
     lds_barrier();
     constexpr int TG = Gm::R < 8 ? Gm::R : 8;  // loads in flight before the stores
 #pragma unroll

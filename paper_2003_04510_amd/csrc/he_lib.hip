@@ -130,6 +130,8 @@ struct he_ctx {
   // device pointers into blob
   const ModInfo* mods = nullptr;
   const Tw2 *tw = nullptr, *itw = nullptr;
+  const double *gtw = nullptr, *igtw = nullptr;  // factored blocks-pass twiddles (FP64 moduli)
+  u32 gstride = 0;
   const u32* iota = nullptr;
   const u64* spec_scale = nullptr;  // [K] pairs: N^-1 [(P/p_k)^-1]_{p_k}
   const u64* pinv = nullptr;        // [L] pairs: [P^-1]_{q_i}
@@ -437,6 +439,9 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
   const size_t o_mods = B.add(mi);
   // twiddles: TB_W[k] = psi^bitrev(k), TB_invW[k] = psi^-bitrev(k), + Shoup companions
   std::vector<Tw2> tw(sizing ? 0 : nm * N), itw(sizing ? 0 : nm * N);
+  const u32 n1 = log_n / 2, n2 = log_n - n1;
+  const size_t gst = ((size_t)1 << n2) + ((size_t)n2 << n1);  // words per modulus: gA, then gB
+  std::vector<double> gt(sizing ? 0 : nm * gst, 0.0), igt(sizing ? 0 : nm * gst, 0.0);
   for (u32 i = 0; i < nm && !sizing; ++i) {
     const u64 m = c->mod[i];
     const u64 psi = min_root_2n(m, log_n), psii = invmod(psi, m);
@@ -451,8 +456,27 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
     }
     tw_fill(tw.data() + i * N, bw, m, N, i32);
     tw_fill(itw.data() + i * N, ibw, m, N, i32);
+    // Blocks passes (n1 = log_n / 2 cols stages done, sub-transforms of
+    // 2^n2 points) at stage s < n2, group t < 2^s of row block blk read
+    // TB_W[2^(n1+s) + blk 2^s + t] = psi^(brv_s(t) 2^(log_n-s)) *
+    // psi^((2 brv_n1(blk) + 1) 2^(n2-1-s)): the first factor (gA, 2^n2 words)
+    // is shared by all blocks, the second (gB, n2 words per block) by the
+    // groups of a stage.  FP64 moduli form the product exactly instead of
+    // reading the table entry.
+    if (f64_mod(m)) {
+      for (int dir = 0; dir < 2; ++dir) {
+        const std::vector<u64>& p = dir ? ipw : pw;
+        double* g = (dir ? igt.data() : gt.data()) + (size_t)i * gst;
+        for (u32 s2 = 0; s2 < n2; ++s2)
+          for (u32 t = 0; t < (1u << s2); ++t) g[(1u << s2) + t] = (double)p[(u64)bitrev(t, s2) << (log_n - s2)];
+        for (u32 blk = 0; blk < (1u << n1); ++blk)
+          for (u32 s2 = 0; s2 < n2; ++s2)
+            g[(1u << n2) + blk * n2 + s2] = (double)p[(2ull * bitrev(blk, n1) + 1) << (n2 - 1 - s2)];
+      }
+    }
   }
   const size_t o_tw = B.add(tw.data(), nm * N * sizeof(Tw2)), o_itw = B.add(itw.data(), nm * N * sizeof(Tw2));
+  const size_t o_gt = B.add(gt.data(), nm * gst * sizeof(double)), o_igt = B.add(igt.data(), nm * gst * sizeof(double));
   const size_t o_iota = B.add(all_idx);
   // ModDown constants (level independent)
   std::vector<u64> spec_scale(2 * K), pinv(2 * L), pm(nm);
@@ -638,6 +662,9 @@ static he_status ctx_make(uint32_t log_n, uint32_t L, uint32_t K, uint32_t dnum,
   c->mods = (const ModInfo*)(b + o_mods);
   c->tw = (const Tw2*)(b + o_tw);
   c->itw = (const Tw2*)(b + o_itw);
+  c->gtw = (const double*)(b + o_gt);
+  c->igtw = (const double*)(b + o_igt);
+  c->gstride = (u32)gst;
   c->iota = (const u32*)(b + o_iota);
   c->spec_scale = (const u64*)(b + o_spec); c->pinv = (const u64*)(b + o_pinv);
   c->pmod = (const u64*)(b + o_pmod);
@@ -904,6 +931,7 @@ void launch_stage(const he_ctx* c, int stage, const Common& cm, const Batch& b, 
 Common make_common(const he_ctx* c, const u64* evk) {
   Common cm{};
   cm.mods = c->mods; cm.tw = c->tw; cm.itw = c->itw; cm.evk = evk; cm.pinv = c->pinv; cm.iota = c->iota;
+  cm.gtw = c->gtw; cm.igtw = c->igtw; cm.gstride = c->gstride;
   cm.L = c->L; cm.K = c->K; cm.log_n = c->log_n; cm.dnum = c->dnum;
   cm.bigq = 1;
   for (u64 m : c->mod) cm.bigq &= m >> 32 ? 1u : 0u;

@@ -23,6 +23,8 @@
 // multipliers, F64A on FP64 FMAs for q < 2^50); lazy ranges live in
 // registers and LDS only, every value written to HBM is canonical.
 #pragma once
+#include <type_traits>
+
 #include "modarith.hpp"
 
 #ifndef NTT_EPW_DEFAULT
@@ -279,36 +281,67 @@ struct RoundShape {
   __device__ static __forceinline__ int blk(int tt, int u) { return (tt + u * Gm::T) / cnt_c; }
 };
 
+// Twiddle sources of the register rounds of one sub-transform; stage s
+// (0 .. LOGS-1 inside the sub-transform), group t < 2^s.
+//   TabTw: the table entry at (base << s) + t (TB_W or TB_invW of the
+//          modulus; base = 2^n1 + blk in a blocks pass, 1 in a cols pass).
+//   GenTw: FP64 moduli in blocks passes.  That entry factors as
+//          a[2^s + t] * b[s] mod q (a: psi^(brv_s(t) 2^(log_n - s)), shared
+//          by every block of the modulus; b: psi^((2 brv_n1(blk) + 1)
+//          2^(LOGS - 1 - s)), the block's row), formed exactly by F64A::mulw
+//          (centred, |w| < q, as the butterflies' bounds allow), so a block
+//          reads LOGS words of b rather than 2^LOGS - 1 table entries.
+struct TabTw {
+  const Tw2* __restrict__ tw;
+  u64 base;
+};
+struct GenTw {
+  const double* __restrict__ a;
+  const double* __restrict__ b;
+};
+template <class A>
+__device__ __forceinline__ typename A::Tw twiddle(const TabTw& s, int sl, u64 t, const typename A::Mod& M) {
+  return A::twid(s.tw, (s.base << sl) + t, M);
+}
+template <class A>
+__device__ __forceinline__ typename A::Tw twiddle(const GenTw& s, int sl, u64 t, const typename A::Mod& M) {
+  static_assert(std::is_same<A, F64A>::value, "generated twiddles are for FP64 moduli");
+  const double b = s.b[sl];
+  if (__builtin_constant_p(t) && t == 0) return F64A::Tw{b, __dmul_rn(b, M.qinv)};  // a[2^s] = 1
+  const double w = F64A::mulw(s.a[(1ull << sl) + t], b, __dmul_rn(b, M.qinv), M);
+  return F64A::Tw{w, __dmul_rn(w, M.qinv)};
+}
+
 // Butterflies of round RD on the registers x[0..R) of thread tt.
-template <class A, bool FWD, int LOGS, int LOGR, int RD>
-__device__ __forceinline__ void round_math(typename A::V (&x)[1 << LOGR], int tt, const Tw2* __restrict__ tw,
-                                           u64 base, const typename A::Mod& M) {
+template <class A, bool FWD, int LOGS, int LOGR, int RD, class TS>
+__device__ __forceinline__ void round_math(typename A::V (&x)[1 << LOGR], int tt, const TS& ts,
+                                           const typename A::Mod& M) {
   using RS = RoundShape<LOGS, LOGR, RD>;
   constexpr int G = RS::G, rr = RS::rr, st = RS::st;
 #pragma unroll
   for (int u = 0; u < RS::NG; ++u) {
-    const u64 blk = (u64)RS::blk(tt, u);
+    // the first round's groups all start at 0 (its threads' group index
+    // tt + u T stays below cnt_c)
+    const u64 blk = st == 0 ? 0 : (u64)RS::blk(tt, u);
     typename A::V* v = x + u * G;
     if constexpr (FWD) {
 #pragma unroll
       for (int k = 0; k < rr; ++k) {
         const int half = G >> (k + 1);
-        const u64 mloc = 1ull << (st + k);
 #pragma unroll
         for (int i = 0; i < G; ++i) {
           if (i & half) continue;
-          A::fwd(v[i], v[i + half], A::twid(tw, mloc * base + (blk << k) + (u64)(i >> (rr - k)), M), M);
+          A::fwd(v[i], v[i + half], twiddle<A>(ts, st + k, (blk << k) + (u64)(i >> (rr - k)), M), M);
         }
       }
     } else {
 #pragma unroll
       for (int k = rr - 1; k >= 0; --k) {
         const int half = G >> (k + 1);
-        const u64 mloc = 1ull << (st + k);
 #pragma unroll
         for (int i = 0; i < G; ++i) {
           if (i & half) continue;
-          A::inv(v[i], v[i + half], A::twid(tw, mloc * base + (blk << k) + (u64)(i >> (rr - k)), M), M);
+          A::inv(v[i], v[i + half], twiddle<A>(ts, st + k, (blk << k) + (u64)(i >> (rr - k)), M), M);
         }
       }
     }
@@ -334,9 +367,9 @@ __device__ __forceinline__ void lds_get(const V* tile, V (&x)[1 << LOGR], int tt
 
 // Middle rounds 1 .. NR-2 (forward order) through LDS.  WAVE: the
 // transform's threads are one wavefront (wave-level LDS ordering suffices).
-template <class A, bool FWD, int LOGS, int LOGR, int K, bool WAVE = false>
-__device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
-                                           const Tw2* __restrict__ tw, u64 base, const typename A::Mod& M) {
+template <class A, bool FWD, int LOGS, int LOGR, int K, bool WAVE, class TS>
+__device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt, const TS& ts,
+                                           const typename A::Mod& M) {
   constexpr int NR = Geo<LOGS, LOGR>::NR;
   if constexpr (K < NR - 1) {
     constexpr int RD = FWD ? K : NR - 1 - K;
@@ -344,10 +377,10 @@ __device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typena
     lds_put<LOGS, LOGR, PREV>(tile, x, tt);
     lds_sync<WAVE>();
     lds_get<LOGS, LOGR, RD>(tile, x, tt);
-    round_math<A, FWD, LOGS, LOGR, RD>(x, tt, tw, base, M);
+    round_math<A, FWD, LOGS, LOGR, RD>(x, tt, ts, M);
     // no barrier needed before the next lds_put: within one round every LDS
     // position belongs to exactly one thread
-    mid_rounds<A, FWD, LOGS, LOGR, K + 1, WAVE>(x, tile, tt, tw, base, M);
+    mid_rounds<A, FWD, LOGS, LOGR, K + 1, WAVE>(x, tile, tt, ts, M);
   }
 }
 
@@ -358,22 +391,21 @@ __device__ __forceinline__ void mid_rounds(typename A::V (&x)[1 << LOGR], typena
 // sub-transform's LDS area (Geo::SUB words).  A caller that runs several
 // sub-transforms on the same tile back to back must place a barrier between
 // them.
-template <class A, bool FWD, int LOGS, int LOGR, bool OUT_LDS, bool WAVE = false, class Store>
-__device__ __forceinline__ void sub_transform_regs(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
-                                                   const Tw2* __restrict__ tw, u64 base, const typename A::Mod& M,
-                                                   Store&& store) {
+template <class A, bool FWD, int LOGS, int LOGR, bool OUT_LDS, bool WAVE = false, class TS, class Store>
+__device__ __forceinline__ void sub_transform_src(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
+                                                  const TS& ts, const typename A::Mod& M, Store&& store) {
   using Gm = Geo<LOGS, LOGR>;
   constexpr int NR = Gm::NR;
   constexpr int FIRST = FWD ? 0 : NR - 1;
   constexpr int LAST = FWD ? NR - 1 : 0;
-  round_math<A, FWD, LOGS, LOGR, FIRST>(x, tt, tw, base, M);
+  round_math<A, FWD, LOGS, LOGR, FIRST>(x, tt, ts, M);
   if constexpr (NR > 1) {
-    mid_rounds<A, FWD, LOGS, LOGR, 1, WAVE>(x, tile, tt, tw, base, M);
+    mid_rounds<A, FWD, LOGS, LOGR, 1, WAVE>(x, tile, tt, ts, M);
     constexpr int PREV = FWD ? LAST - 1 : LAST + 1;
     lds_put<LOGS, LOGR, PREV>(tile, x, tt);
     lds_sync<WAVE>();
     lds_get<LOGS, LOGR, LAST>(tile, x, tt);
-    round_math<A, FWD, LOGS, LOGR, LAST>(x, tt, tw, base, M);
+    round_math<A, FWD, LOGS, LOGR, LAST>(x, tt, ts, M);
   }
   if constexpr (OUT_LDS) {
     lds_put<LOGS, LOGR, LAST>(tile, x, tt);
@@ -384,6 +416,14 @@ __device__ __forceinline__ void sub_transform_regs(typename A::V (&x)[1 << LOGR]
 #pragma unroll
       for (int i = 0; i < RS::G; ++i) store(RS::elem(tt, u, i), x[u * RS::G + i]);
   }
+}
+
+// The same with the twiddles of the table tw at base (see TabTw).
+template <class A, bool FWD, int LOGS, int LOGR, bool OUT_LDS, bool WAVE = false, class Store>
+__device__ __forceinline__ void sub_transform_regs(typename A::V (&x)[1 << LOGR], typename A::V* tile, int tt,
+                                                   const Tw2* __restrict__ tw, u64 base, const typename A::Mod& M,
+                                                   Store&& store) {
+  sub_transform_src<A, FWD, LOGS, LOGR, OUT_LDS, WAVE>(x, tile, tt, TabTw{tw, base}, M, store);
 }
 
 // Runs body(IntA{}), body(F64A{}) or, for 32-bit words, body(I32A{}) by
