@@ -64,8 +64,9 @@ he_status he_gen_primes(uint32_t log_n, uint32_t bits, uint32_t count, const uin
 
 /* Create a context: moduli q (host, [L]) and p (host, [K]), dnum key-switch
  * digits.  Builds twiddle tables (powers of the smallest primitive 2N-th root
- * in bit-reversed order, with Shoup companions, Algorithms 2-3) and all
- * base-conversion constants on device `device`.  The tables go to
+ * in bit-reversed order, with Shoup companions, Algorithms 2-3; for primes
+ * below 2^50 also the two factors that the NTT's later stages multiply
+ * together instead) and all base-conversion constants on device `device`.  The tables go to
  * d_tables, device memory of at least he_ctx_device_bytes(...) bytes that
  * the caller owns and keeps valid until he_ctx_destroy (HE_ENOMEM if
  * tables_bytes is smaller); with d_tables = NULL the context allocates them
