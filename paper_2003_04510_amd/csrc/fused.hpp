@@ -794,9 +794,11 @@ inline int conv_bucket(u32 ns) {
 // limbs never make the round trip through HBM in NTT form.  When
 // rescaling, ks_u[level-1] is written in NTT form and, inverse-transformed
 // the same way, into slot level+K.  Both leave the inverse cols pass.
-// Items (coefficient chunk, e), e fastest, so every XCD takes its share of
-// the special limbs' transforms.  KEY_NT: the key is read by one HE Mul
-// (a single pair), so its loads bypass the caches.
+// Items in eight blocks of coefficient chunks (one per XCD for a single
+// pair), limb-major inside a block: every XCD takes its share of the
+// special limbs' transforms, and the workgroups in flight on it read a few
+// limbs' adjacent chunks.  KEY_NT: the key is read by one HE Mul (a single
+// pair), so its loads bypass the caches.
 template <class W, bool KEY_NT, int LOGS>
 __global__ __launch_bounds__(IP_THREADS) void k_ip(Common c, Batch b) {
   // radix-4 rounds (radix 8 from 512 points): the transforms of an item
