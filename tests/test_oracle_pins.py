@@ -232,8 +232,8 @@ def test_modup_fast_conversion_identity(level):
     """Fast conversion without overflow correction: with X the exact CRT
     value of the digit's coefficients and y_i = x_i [(Qt/q_i)^-1]_{q_i},
     every target limb holds X + u Qt with u = floor(sum_i y_i / q_i), the
-    overflow count of the matrix form of "CRT right after iCRT" (Table XI,
-    Algorithm 6); u is computed here from Python integers, and an exact
+    overflow count of the matrix form of an iCRT followed at once by a CRT
+    (Table XI, Algorithm 6); u is computed here from Python integers, and an exact
     conversion (u = 0 everywhere) fails the check."""
     ctx = _tiny_ctx(log_n=4, L=5, K=2, dnum=3)
     d2 = synth.uniform_limbs(9, ctx.q[:level], ctx.N)
