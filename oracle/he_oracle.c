@@ -17,7 +17,7 @@
  *   - HE Mul flow: Fig. 2 (region 1 tensor, region 2 key switching with evk,
  *     shift), rescale by division (Sec. III-A).
  *   - Full-RNS form (mod up / mod down): Table XI and the Discussion section
- *     ("applicability to other libraries"); the paper only names these
+ *     (its part on other libraries); the paper only names these
  *     functions, so the formulas below are the standard fast base conversion
  *     of full-RNS CKKS: non-centred sources, no overflow correction, mod down
  *     without a rounding offset, rescale rounding to nearest by the centred
