@@ -579,8 +579,16 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
     // 4-byte values: the inverse input tile (8-byte words) is read by every
     // thread before the transform reuses it
     if constexpr (!FWD && sizeof(typename A::V) != 8) lds_barrier();
-    sub_transform_src<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, blocks_tw<A, FWD, LOGS>(c, mi, blk0 + sub), M,
-                                               [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); });
+    const auto st_out = [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); };
+    if constexpr (ST == ST_DT_NBLOCKS && LOGS < 9)
+      // the mod-up limbs of one modulus at a tile run side by side and share
+      // its table reads in L2, which up to 256 points costs less than
+      // forming the twiddles
+      sub_transform_regs<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
+                                                  (1ull << n1) + blk0 + sub, M, st_out);
+    else
+      sub_transform_src<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, blocks_tw<A, FWD, LOGS>(c, mi, blk0 + sub), M,
+                                                 st_out);
     if constexpr (FWD) {
       lds_barrier();
 #pragma unroll
