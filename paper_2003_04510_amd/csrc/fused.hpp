@@ -243,11 +243,14 @@ inline u32 stage_items(int st, u32 log_n, u32 level, u32 K, u32 alpha, u32 beta,
 
 // ---------------------------------------------------------------- blocks-pass twiddles
 // Twiddle source of the sub-transform of row block blk (of 2^(log_n - LOGS))
-// in a blocks pass of modulus mi: the factored form for FP64 moduli (GenTw),
-// the table otherwise.
+// in a blocks pass of modulus mi: the factored form for FP64 moduli (GenTw)
+// from 512-point sub-transforms up, the table otherwise.  Up to 256 points
+// the table's reads cost less than forming the twiddles: a block's share of
+// the table is smaller, and limbs of one modulus that run side by side (the
+// digits of mod up, the two polynomials of the combine) share it in L2.
 template <class A, bool FWD, int LOGS>
 __device__ __forceinline__ auto blocks_tw(const Common& c, u32 mi, u64 blk) {
-  if constexpr (std::is_same<A, F64A>::value) {
+  if constexpr (std::is_same<A, F64A>::value && LOGS >= 9) {
     const double* g = (FWD ? c.gtw : c.igtw) + (u64)mi * c.gstride;
     return GenTw{g, g + (1u << LOGS) + blk * LOGS};
   } else {
@@ -579,16 +582,8 @@ __global__ __launch_bounds__(pass_threads(LOGS, EPW)) void k_list_blocks(Common 
     // 4-byte values: the inverse input tile (8-byte words) is read by every
     // thread before the transform reuses it
     if constexpr (!FWD && sizeof(typename A::V) != 8) lds_barrier();
-    const auto st_out = [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); };
-    if constexpr (ST == ST_DT_NBLOCKS && LOGS < 9)
-      // the mod-up limbs of one modulus at a tile run side by side and share
-      // its table reads in L2, which up to 256 points costs less than
-      // forming the twiddles
-      sub_transform_regs<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, (FWD ? c.tw : c.itw) + ((u64)mi << c.log_n),
-                                                  (1ull << n1) + blk0 + sub, M, st_out);
-    else
-      sub_transform_src<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, blocks_tw<A, FWD, LOGS>(c, mi, blk0 + sub), M,
-                                                 st_out);
+    sub_transform_src<A, FWD, LOGS, LOGR, FWD>(x, tl + sub * Gm::SUB, tt, blocks_tw<A, FWD, LOGS>(c, mi, blk0 + sub), M,
+                                               [&](int e, typename A::V val) { out[e] = A::template out<FWD>(val, M); });
     if constexpr (FWD) {
       lds_barrier();
 #pragma unroll
